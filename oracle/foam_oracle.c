@@ -1,0 +1,654 @@
+/*
+ * foam_oracle.c -- plain FP64 CPU oracle for the single-component Shan-Chen
+ * lattice-Boltzmann foam step with the inter-bubble film barrier and the
+ * pressure-second-derivative rupture criterion of Barzegari, Bayani,
+ * Mirbagheri and Shetabivash, "Multiphase Aluminum A356 Foam Formation
+ * Process Simulation Using Lattice Boltzmann Method" (arXiv:1708.01613).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference the GPU library is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or generator with the HIP library.
+ *
+ * Everything is FP64, written as plain loops in the order the method states
+ * it.  Per step n, with f^n the post-streaming populations:
+ *   1. moments        rho = sum_i f_i, j = sum_i e_i f_i        (Sec. 2.1.1, Eq. vel_dens)
+ *   2. pseudopotential psi = rho0 (1 - exp(-rho/rho0))          (Sec. 2.1.2, Eq. pseudopotential)
+ *   3. film maps (every k_own steps): labels, owner/dist, barrier links,
+ *      alias carry                                              (Sec. 2.1.5, Fig. shanchenflowchart)
+ *   4. force          F = -G psi(x) sum_i w_i psi~(x+e_i) e_i    (Sec. 2.1.2, Eq. shanchen3)
+ *   5. velocity shift u_eq = (j + tau F) / rho                  (Sec. 2.1.5, final-velocity equations, read with /rho)
+ *   6. BGK collision  f* = f - (f - f^eq(rho, u_eq)) / tau       (Sec. 2.1.1, collision equation; f^eq equation)
+ *   7. streaming      f_i(x + e_i) = f*_i(x), periodic           (Sec. 2.1.1, streaming equation)
+ *   8. rupture test   d2 p0 / dn2 >= 0 on barrier links          (Sec. 2.1.5, eta_m equation; Sec. 4)
+ *
+ * Readings of passages the paper leaves silent or garbled are named where
+ * they are used (R-numbers match the table of readings kept with the design
+ * notes).  No part of this file is tuned for speed beyond an OpenMP pragma on
+ * the independent per-cell loops; reductions are serial in index order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAXQ 19
+
+/* ------------------------------------------------------------------ */
+/* Lattices.                                                           */
+/* D2Q9: Sec. 2.1.1 (velocity and weight equations): rest, 4 axes with  */
+/* weight 1/9, 4 diagonals with weight 1/36.                            */
+/* D3Q19 is not printed in the paper; it is the textbook lattice: rest  */
+/* 1/3, 6 axes 1/18, 12 face diagonals 1/36 (c_s^2 = 1/3 as in D2Q9).   */
+/* ------------------------------------------------------------------ */
+static const int OR_E2[9][3] = {
+    {0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+static const double OR_W2[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+static const int OR_E3[19][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+static const double OR_W3[19] = {
+    1.0 / 3,
+    1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+/* Parameters.  Field meaning follows the boundary of the GPU library, but   */
+/* the struct is declared here on its own (the oracle includes no product    */
+/* header).                                                                  */
+typedef struct {
+  int32_t lattice; /* 0 = D2Q9, 1 = D3Q19 */
+  int32_t nx, ny, nz;
+  double tau, G, rho0;
+  double rho_liquid, rho_gas, noise_amp;
+  uint64_t seed;
+  int32_t film_on;
+  int32_t k_own;
+  int32_t zone_width;
+  double rho_th;
+  int32_t psi_bar_mode;   /* 0: psi(rho_liquid); 1: psi(x) */
+  int32_t rupture_warmup; /* first step at which the rupture test runs */
+  int32_t on_rupture;     /* 0: remove pair barrier; 1: stop after the step */
+  int32_t velocity_mode;  /* 0: j/rho; 1: (j + F/2)/rho */
+} or_params;
+
+typedef struct {
+  or_params p;
+  int Q, D;
+  const int (*e)[3];
+  const double* w;
+  int opp[OR_MAXQ];
+  long N;
+  double* f;     /* populations f[i*N + c], post-streaming state f^n */
+  double* fpost; /* post-collision scratch */
+  double* rho;
+  double* psi;
+  double* force; /* 3*N, last computed force */
+  /* film maps (as of the last refresh) */
+  int32_t* label;     /* canonical labels, 0 = liquid */
+  int32_t* label_old; /* labels of the previous refresh */
+  int32_t* owner;     /* smallest label among the nearest bubbles, 0 = none */
+  int32_t* owner2;    /* largest label among the nearest bubbles (== owner unless tied) */
+  int32_t* dist;      /* hop distance to owner's gas, -1 = none */
+  uint32_t* mask;     /* barrier-link bit mask (bit i = link i) */
+  int32_t nb, nb_old;
+  int32_t* alias;     /* union-find parents over labels 0..nb */
+  int32_t* alias_old;
+  int32_t maps_valid;
+  /* rupture events: (step, k, k2) triples */
+  int64_t* ev;
+  long nev, evcap;
+  int64_t n_ruptures;
+  int64_t step;
+  int32_t stopped;
+} or_sim;
+
+/* ------------------------------------------------------------------ */
+/* small helpers                                                       */
+/* ------------------------------------------------------------------ */
+static long wrap(long a, long n) {
+  long r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+static long nbr(const or_sim* s, long c, int i, int sign) {
+  long nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
+  long x = c % nx, y = (c / nx) % ny, z = c / (nx * ny);
+  x = wrap(x + sign * s->e[i][0], nx);
+  y = wrap(y + sign * s->e[i][1], ny);
+  z = wrap(z + sign * s->e[i][2], nz);
+  return x + nx * (y + ny * z);
+}
+
+static double psi_of(const or_params* p, double rho) {
+  /* Sec. 2.1.2, Eq. pseudopotential, generalised to rho0 (1 - e^{-rho/rho0}). */
+  return p->rho0 * (1.0 - exp(-rho / p->rho0));
+}
+
+double or_p0(double rho, double G, double rho0) {
+  /* Bulk equation of state p = rho c_s^2 + (G/6) psi^2 (Sec. 2.1.2, Eq. Pequ;
+   * the same expression is the interaction potential xi of Sec. 2.1.5). */
+  double psi = rho0 * (1.0 - exp(-rho / rho0));
+  return rho / 3.0 + G / 6.0 * psi * psi;
+}
+
+/* Vigna's SplitMix64 output function applied to one 64-bit state. */
+uint64_t or_splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* Uniform in [0,1) for cell index idx: top 53 bits of the hash. */
+double or_uniform(uint64_t seed, uint64_t idx) {
+  uint64_t h = or_splitmix64(seed ^ (idx * 0x9E3779B97F4A7C15ULL));
+  return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* union-find with the smaller index as root */
+static int32_t uf_find(int32_t* par, int32_t a) {
+  while (par[a] != a) a = par[a];
+  return a;
+}
+static int uf_union(int32_t* par, int32_t a, int32_t b) {
+  int32_t ra = uf_find(par, a), rb = uf_find(par, b);
+  if (ra == rb) return 0;
+  if (ra < rb) par[rb] = ra; else par[ra] = rb;
+  return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* creation                                                            */
+/* ------------------------------------------------------------------ */
+void or_destroy(or_sim* s);
+
+or_sim* or_create(const or_params* p) {
+  if (p->lattice != 0 && p->lattice != 1) return NULL;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
+  if (p->lattice == 0 && p->nz != 1) return NULL;
+  if (!(p->tau > 0.5)) return NULL;
+  or_sim* s = (or_sim*)calloc(1, sizeof(or_sim));
+  s->p = *p;
+  if (s->p.k_own < 1) s->p.k_own = 1;
+  if (p->lattice == 0) {
+    s->Q = 9; s->D = 2; s->e = OR_E2; s->w = OR_W2;
+  } else {
+    s->Q = 19; s->D = 3; s->e = OR_E3; s->w = OR_W3;
+  }
+  for (int i = 0; i < s->Q; i++)
+    for (int j = 0; j < s->Q; j++)
+      if (s->e[j][0] == -s->e[i][0] && s->e[j][1] == -s->e[i][1] && s->e[j][2] == -s->e[i][2])
+        s->opp[i] = j;
+  s->N = (long)p->nx * p->ny * p->nz;
+  long N = s->N;
+  s->f = (double*)calloc((size_t)s->Q * N, sizeof(double));
+  s->fpost = (double*)calloc((size_t)s->Q * N, sizeof(double));
+  s->rho = (double*)calloc(N, sizeof(double));
+  s->psi = (double*)calloc(N, sizeof(double));
+  s->force = (double*)calloc(3 * (size_t)N, sizeof(double));
+  s->label = (int32_t*)calloc(N, sizeof(int32_t));
+  s->label_old = (int32_t*)calloc(N, sizeof(int32_t));
+  s->owner = (int32_t*)calloc(N, sizeof(int32_t));
+  s->owner2 = (int32_t*)calloc(N, sizeof(int32_t));
+  s->dist = (int32_t*)calloc(N, sizeof(int32_t));
+  s->mask = (uint32_t*)calloc(N, sizeof(uint32_t));
+  s->alias = (int32_t*)calloc(N + 2, sizeof(int32_t));
+  s->alias_old = (int32_t*)calloc(N + 2, sizeof(int32_t));
+  s->evcap = 1024;
+  s->ev = (int64_t*)calloc(3 * (size_t)s->evcap, sizeof(int64_t));
+  if (!s->f || !s->fpost || !s->rho || !s->psi || !s->force || !s->label || !s->label_old ||
+      !s->owner || !s->owner2 || !s->dist || !s->mask || !s->alias || !s->alias_old || !s->ev) {
+    or_destroy(s);
+    return NULL;
+  }
+  for (long c = 0; c < N; c++) s->dist[c] = -1;
+  return s;
+}
+
+void or_destroy(or_sim* s) {
+  if (!s) return;
+  free(s->f); free(s->fpost); free(s->rho); free(s->psi); free(s->force);
+  free(s->label); free(s->label_old); free(s->owner); free(s->owner2); free(s->dist); free(s->mask);
+  free(s->alias); free(s->alias_old); free(s->ev);
+  free(s);
+}
+
+int or_Q(const or_sim* s) { return s->Q; }
+long or_N(const or_sim* s) { return s->N; }
+int64_t or_step_count(const or_sim* s) { return s->step; }
+int32_t or_stopped(const or_sim* s) { return s->stopped; }
+
+/* lattice tables, for tests */
+void or_lattice(int lattice, int32_t* e_out, double* w_out) {
+  int Q = lattice == 0 ? 9 : 19;
+  for (int i = 0; i < Q; i++) {
+    for (int k = 0; k < 3; k++) e_out[3 * i + k] = lattice == 0 ? OR_E2[i][k] : OR_E3[i][k];
+    w_out[i] = lattice == 0 ? OR_W2[i] : OR_W3[i];
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* initial state: random nucleation at "domain gas points" (Sec. 2.1.3) */
+/* rho = rho_gas inside any nucleus (periodic minimum image, cell      */
+/* centres at integer coordinates), rho_liquid elsewhere, plus seeded  */
+/* uniform noise; populations at rest equilibrium f_i = w_i rho.       */
+/* ------------------------------------------------------------------ */
+static double min_image(double d, long n) { return d - (double)n * floor(d / (double)n + 0.5); }
+
+int or_set_nuclei(or_sim* s, const double* nuc, int32_t n) {
+  const or_params* p = &s->p;
+  long N = s->N;
+  for (long c = 0; c < N; c++) {
+    long x = c % p->nx, y = (c / p->nx) % p->ny, z = c / ((long)p->nx * p->ny);
+    int inside = 0;
+    for (int k = 0; k < n && !inside; k++) {
+      double dx = min_image((double)x - nuc[4 * k + 0], p->nx);
+      double dy = min_image((double)y - nuc[4 * k + 1], p->ny);
+      double dz = min_image((double)z - nuc[4 * k + 2], p->nz);
+      double r = nuc[4 * k + 3];
+      if (dx * dx + dy * dy + dz * dz <= r * r) inside = 1;
+    }
+    double rho = inside ? p->rho_gas : p->rho_liquid;
+    rho += p->noise_amp * (2.0 * or_uniform(p->seed, (uint64_t)c) - 1.0);
+    for (int i = 0; i < s->Q; i++) s->f[(long)i * N + c] = s->w[i] * rho;
+  }
+  s->step = 0;
+  s->stopped = 0;
+  s->nev = 0;
+  s->n_ruptures = 0;
+  s->maps_valid = 0;
+  s->nb = 0;
+  s->nb_old = 0;
+  memset(s->label, 0, N * sizeof(int32_t));
+  memset(s->label_old, 0, N * sizeof(int32_t));
+  return 0;
+}
+
+void or_set_populations(or_sim* s, const double* f) {
+  memcpy(s->f, f, (size_t)s->Q * s->N * sizeof(double));
+}
+void or_get_populations(const or_sim* s, double* f) {
+  memcpy(f, s->f, (size_t)s->Q * s->N * sizeof(double));
+}
+
+/* ------------------------------------------------------------------ */
+/* step 1-2: moments and pseudopotential of the current state          */
+/* ------------------------------------------------------------------ */
+static void compute_moments(or_sim* s, double* jx, double* jy, double* jz) {
+  long N = s->N;
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < N; c++) {
+    double r = 0, a = 0, b = 0, d = 0;
+    for (int i = 0; i < s->Q; i++) {
+      double fi = s->f[(long)i * N + c];
+      r += fi;
+      a += s->e[i][0] * fi;
+      b += s->e[i][1] * fi;
+      d += s->e[i][2] * fi;
+    }
+    s->rho[c] = r;
+    s->psi[c] = psi_of(&s->p, r);
+    if (jx) { jx[c] = a; jy[c] = b; jz[c] = d; }
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* step 3: film maps                                                   */
+/* ------------------------------------------------------------------ */
+
+/* Canonical connected-component labels of the gas cells (rho < rho_th),  */
+/* links = the lattice's velocity set, periodic.  Components are found by */
+/* flood fill started from the lowest unlabelled gas index, so component  */
+/* k (1-based) is exactly the k-th component ordered by its minimum linear */
+/* index.  Returns the number of components.                              */
+static int32_t label_field(const or_sim* s, const double* rho, double rho_th, int32_t* lab) {
+  long N = s->N;
+  long* queue = (long*)malloc(N * sizeof(long));
+  for (long c = 0; c < N; c++) lab[c] = rho[c] < rho_th ? -1 : 0;
+  int32_t nb = 0;
+  for (long c0 = 0; c0 < N; c0++) {
+    if (lab[c0] != -1) continue;
+    nb++;
+    long head = 0, tail = 0;
+    queue[tail++] = c0;
+    lab[c0] = nb;
+    while (head < tail) {
+      long c = queue[head++];
+      for (int i = 1; i < s->Q; i++) {
+        long d = nbr(s, c, i, +1);
+        if (lab[d] == -1) {
+          lab[d] = nb;
+          queue[tail++] = d;
+        }
+      }
+    }
+  }
+  free(queue);
+  return nb;
+}
+
+/* Owner and hop distance (R6, R7): the hop distance (in lattice links) from */
+/* each cell to the nearest gas cell, and the smallest and largest label     */
+/* among the gas cells at that distance.  A cell equidistant from two        */
+/* bubbles keeps both, so the wall between two bubbles is placed             */
+/* symmetrically.  Distances are truncated at zone_width-1 hops.  Built      */
+/* layer by layer: a cell first reached at layer d takes the min / max owner */
+/* of its neighbours of layer d-1.                                           */
+static void owner_dist(const or_sim* s, const int32_t* lab, int zone_width, int32_t* owner,
+                       int32_t* owner2, int32_t* dist) {
+  long N = s->N;
+  for (long c = 0; c < N; c++) {
+    owner[c] = lab[c];
+    owner2[c] = lab[c];
+    dist[c] = lab[c] > 0 ? 0 : -1;
+  }
+  for (int d = 1; d <= zone_width - 1; d++) {
+    for (long c = 0; c < N; c++) {
+      if (dist[c] != -1) continue;
+      int32_t lo = 0, hi = 0;
+      for (int i = 1; i < s->Q; i++) {
+        long y = nbr(s, c, i, +1);
+        if (dist[y] != d - 1) continue;
+        if (lo == 0 || owner[y] < lo) lo = owner[y];
+        if (owner2[y] > hi) hi = owner2[y];
+      }
+      if (lo > 0) {
+        owner[c] = lo;
+        owner2[c] = hi;
+        dist[c] = -2 - d; /* provisional marker for this layer */
+      }
+    }
+    for (long c = 0; c < N; c++)
+      if (dist[c] == -2 - d) dist[c] = d;
+  }
+}
+
+/* The pair of alias roots of a cell's nearest bubbles, as (low, high). */
+static void root_pair(const or_sim* s, long c, int32_t* lo, int32_t* hi) {
+  int32_t a = uf_find(s->alias, s->owner[c]), b = uf_find(s->alias, s->owner2[c]);
+  *lo = a < b ? a : b;
+  *hi = a < b ? b : a;
+}
+
+/* A link joins two walls of a film when both ends are owned and their     */
+/* nearest-bubble root pairs differ (R5-R7).                               */
+static int roots_differ(const or_sim* s, long c, long y) {
+  int32_t a0, a1, b0, b1;
+  root_pair(s, c, &a0, &a1);
+  root_pair(s, y, &b0, &b1);
+  return a0 != b0 || a1 != b1;
+}
+
+static void refresh_maps(or_sim* s) {
+  long N = s->N;
+  /* keep the previous labels and aliases for the alias carry */
+  int32_t* t = s->label_old; s->label_old = s->label; s->label = t;
+  t = s->alias_old; s->alias_old = s->alias; s->alias = t;
+  s->nb_old = s->maps_valid ? s->nb : 0;
+
+  s->nb = label_field(s, s->rho, s->p.rho_th, s->label);
+  owner_dist(s, s->label, s->p.zone_width, s->owner, s->owner2, s->dist);
+
+  /* alias carry: new bubbles whose gas cells overlap old components of one */
+  /* old alias class become aliases of each other.                          */
+  for (int32_t b = 0; b <= s->nb; b++) s->alias[b] = b;
+  if (s->nb_old > 0) {
+    int32_t* rep = (int32_t*)malloc((s->nb_old + 1) * sizeof(int32_t));
+    for (int32_t a = 0; a <= s->nb_old; a++) rep[a] = 0;
+    for (long c = 0; c < N; c++) {
+      int32_t b = s->label[c], a = s->label_old[c];
+      if (b > 0 && a > 0) {
+        int32_t r = uf_find(s->alias_old, a);
+        if (rep[r] == 0) rep[r] = b;
+        else uf_union(s->alias, b, rep[r]);
+      }
+    }
+    free(rep);
+  }
+
+  /* barrier links: both ends owned, their nearest-bubble root pairs differ,  */
+  /* and the film between their gas regions is at most zone_width links      */
+  /* thick (R5-R7).                                                          */
+  for (long c = 0; c < N; c++) {
+    uint32_t m = 0;
+    if (s->owner[c] > 0) {
+      for (int i = 1; i < s->Q; i++) {
+        long y = nbr(s, c, i, +1);
+        if (s->owner[y] > 0 && roots_differ(s, c, y) &&
+            s->dist[c] + s->dist[y] + 1 <= s->p.zone_width)
+          m |= 1u << i;
+      }
+    }
+    s->mask[c] = m;
+  }
+  s->maps_valid = 1;
+}
+
+/* a barrier link stays active while the root pairs of its ends differ */
+static int link_active(const or_sim* s, long c, int i) {
+  if (!s->maps_valid || !(s->mask[c] & (1u << i))) return 0;
+  return roots_differ(s, c, nbr(s, c, i, +1));
+}
+
+/* ------------------------------------------------------------------ */
+/* step 4: Shan-Chen force with the film-barrier substitution            */
+/* F(x) = -G psi(x) sum_i w_i psi~(x+e_i) e_i (Sec. 2.1.2, Eq. shanchen3), */
+/* summed over opposite pairs so a uniform psi gives exactly zero.        */
+/* psi~ = psi_bar on an active barrier link (R5), psi otherwise.          */
+/* ------------------------------------------------------------------ */
+static void compute_force(or_sim* s, int with_film) {
+  long N = s->N;
+  const or_params* p = &s->p;
+  double psi_liq = psi_of(p, p->rho_liquid);
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < N; c++) {
+    double acc[3] = {0, 0, 0};
+    for (int i = 1; i < s->Q; i++) {
+      int o = s->opp[i];
+      if (o < i) continue; /* each opposite pair once */
+      long yp = nbr(s, c, i, +1), ym = nbr(s, c, i, -1);
+      double sp = s->psi[yp], sm = s->psi[ym];
+      if (with_film) {
+        double bar = p->psi_bar_mode == 0 ? psi_liq : s->psi[c];
+        if (link_active(s, c, i)) sp = bar;
+        if (link_active(s, c, o)) sm = bar;
+      }
+      for (int k = 0; k < 3; k++) acc[k] += s->w[i] * s->e[i][k] * (sp - sm);
+    }
+    for (int k = 0; k < 3; k++) s->force[3 * c + k] = -p->G * s->psi[c] * acc[k];
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* one time step                                                       */
+/* ------------------------------------------------------------------ */
+static void one_step(or_sim* s) {
+  long N = s->N;
+  const or_params* p = &s->p;
+  int Q = s->Q;
+  double* jx = (double*)malloc(3 * N * sizeof(double));
+  double* jy = jx + N;
+  double* jz = jy + N;
+
+  compute_moments(s, jx, jy, jz);                       /* 1, 2 */
+  if (p->film_on && s->step % p->k_own == 0) refresh_maps(s); /* 3 */
+  compute_force(s, p->film_on);                         /* 4 */
+
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < N; c++) {
+    double rho = s->rho[c];
+    double u[3];
+    u[0] = (jx[c] + p->tau * s->force[3 * c + 0]) / rho; /* 5 */
+    u[1] = (jy[c] + p->tau * s->force[3 * c + 1]) / rho;
+    u[2] = (jz[c] + p->tau * s->force[3 * c + 2]) / rho;
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < Q; i++) {                       /* 6 */
+      double eu = s->e[i][0] * u[0] + s->e[i][1] * u[1] + s->e[i][2] * u[2];
+      double feq = s->w[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+      double fi = s->f[(long)i * N + c];
+      s->fpost[(long)i * N + c] = fi - (fi - feq) / p->tau;
+    }
+  }
+
+  /* 8: rupture test on active barrier links, with the aliases of the start */
+  /* of this step; unions take effect from the next step (R8-R11).          */
+  int any_rupture = 0;
+  if (p->film_on && s->maps_valid && s->step >= p->rupture_warmup) {
+    long first_ev = s->nev;
+    for (long c = 0; c < N; c++) {
+      if (!s->mask[c]) continue;
+      for (int i = 1; i < Q; i++) {
+        if (!link_active(s, c, i)) continue;
+        long yp = nbr(s, c, i, +1), ym = nbr(s, c, i, -1);
+        double d2 = or_p0(s->rho[yp], p->G, p->rho0) - 2.0 * or_p0(s->rho[c], p->G, p->rho0) +
+                    or_p0(s->rho[ym], p->G, p->rho0);
+        if (d2 >= 0.0) {
+          /* the film's pair: smallest and largest nearest-bubble label */
+          int32_t k = s->owner[c] < s->owner[yp] ? s->owner[c] : s->owner[yp];
+          int32_t k2 = s->owner2[c] > s->owner2[yp] ? s->owner2[c] : s->owner2[yp];
+          if (s->nev == s->evcap) {
+            s->evcap *= 2;
+            s->ev = (int64_t*)realloc(s->ev, 3 * (size_t)s->evcap * sizeof(int64_t));
+          }
+          s->ev[3 * s->nev + 0] = s->step;
+          s->ev[3 * s->nev + 1] = k;
+          s->ev[3 * s->nev + 2] = k2;
+          s->nev++;
+        }
+      }
+    }
+    for (long e = first_ev; e < s->nev; e++) {
+      any_rupture = 1;
+      s->n_ruptures += uf_union(s->alias, (int32_t)s->ev[3 * e + 1], (int32_t)s->ev[3 * e + 2]);
+    }
+  }
+
+  /* 7: pull form of f_i(x + e_i) <- f*_i(x) */
+#pragma omp parallel for schedule(static)
+  for (long c = 0; c < N; c++)
+    for (int i = 0; i < Q; i++) s->f[(long)i * N + c] = s->fpost[(long)i * N + nbr(s, c, i, -1)];
+
+  free(jx);
+  s->step++;
+  if (any_rupture && p->on_rupture == 1) s->stopped = 1;
+}
+
+/* Runs up to nsteps steps; returns 1 if the run stopped on a rupture      */
+/* (on_rupture == 1, the flowchart's termination), 0 otherwise.           */
+int or_step(or_sim* s, int64_t nsteps) {
+  for (int64_t k = 0; k < nsteps; k++) {
+    if (s->stopped) return 1;
+    one_step(s);
+  }
+  return s->stopped;
+}
+
+/* ------------------------------------------------------------------ */
+/* queries                                                             */
+/* ------------------------------------------------------------------ */
+void or_density(or_sim* s, double* out) {
+  compute_moments(s, NULL, NULL, NULL);
+  memcpy(out, s->rho, s->N * sizeof(double));
+}
+
+/* velocity, structure of arrays by component (D components).  Mode 0:     */
+/* u = j/rho (Sec. 2.1.1, Eq. vel_dens); mode 1: (j + F/2)/rho with the    */
+/* force of the current state under the current film maps.                 */
+void or_velocity(or_sim* s, double* out) {
+  long N = s->N;
+  double* j = (double*)malloc(3 * N * sizeof(double));
+  compute_moments(s, j, j + N, j + 2 * N);
+  if (s->p.velocity_mode == 1) compute_force(s, s->p.film_on);
+  for (int k = 0; k < s->D; k++)
+    for (long c = 0; c < N; c++) {
+      double jk = j[k * N + c];
+      if (s->p.velocity_mode == 1) jk += 0.5 * s->force[3 * c + k];
+      out[k * N + c] = jk / s->rho[c];
+    }
+  free(j);
+}
+
+/* force field of the current state (3*N, component-major), for tests */
+void or_force(or_sim* s, int with_film, double* out) {
+  compute_moments(s, NULL, NULL, NULL);
+  compute_force(s, with_film);
+  for (int k = 0; k < 3; k++)
+    for (long c = 0; c < s->N; c++) out[k * s->N + c] = s->force[3 * c + k];
+}
+
+/* labels of the current state, computed on demand */
+int32_t or_labels(or_sim* s, int32_t* out) {
+  compute_moments(s, NULL, NULL, NULL);
+  return label_field(s, s->rho, s->p.rho_th, out);
+}
+
+/* labels / owner / dist of an arbitrary density field (pins and parity) */
+int32_t or_label_field(or_sim* s, const double* rho, int32_t* lab) {
+  return label_field(s, rho, s->p.rho_th, lab);
+}
+void or_owner_dist(or_sim* s, const int32_t* lab, int32_t* owner, int32_t* owner2, int32_t* dist) {
+  owner_dist(s, lab, s->p.zone_width, owner, owner2, dist);
+}
+
+/* film maps as of the last refresh */
+int32_t or_maps(const or_sim* s, int32_t* label, int32_t* owner, int32_t* owner2, int32_t* dist,
+                uint32_t* mask, int32_t* alias_root) {
+  long N = s->N;
+  if (label) memcpy(label, s->label, N * sizeof(int32_t));
+  if (owner) memcpy(owner, s->owner, N * sizeof(int32_t));
+  if (owner2) memcpy(owner2, s->owner2, N * sizeof(int32_t));
+  if (dist) memcpy(dist, s->dist, N * sizeof(int32_t));
+  if (mask) memcpy(mask, s->mask, N * sizeof(uint32_t));
+  if (alias_root)
+    for (int32_t b = 0; b <= s->nb; b++) alias_root[b] = uf_find(s->alias, b);
+  return s->nb;
+}
+
+/* FP64 totals of the current state: mass and momentum, serial sums */
+void or_stats(or_sim* s, double* mass, double* mom) {
+  long N = s->N;
+  double m = 0, px = 0, py = 0, pz = 0;
+  for (long c = 0; c < N; c++)
+    for (int i = 0; i < s->Q; i++) {
+      double fi = s->f[(long)i * N + c];
+      m += fi;
+      px += s->e[i][0] * fi;
+      py += s->e[i][1] * fi;
+      pz += s->e[i][2] * fi;
+    }
+  *mass = m;
+  mom[0] = px; mom[1] = py; mom[2] = pz;
+}
+
+int64_t or_n_ruptures(const or_sim* s) { return s->n_ruptures; }
+
+/* raw rupture events (step, k, k2) with k < k2, in the order found */
+long or_events(const or_sim* s, int64_t* out, long cap) {
+  long n = s->nev < cap ? s->nev : cap;
+  memcpy(out, s->ev, 3 * n * sizeof(int64_t));
+  return s->nev;
+}
+
+/* Bubble-size histogram of a label field: equivalent diameter of each     */
+/* bubble (2-D: area-equivalent circle, 3-D: volume-equivalent sphere),    */
+/* binned by floor(d / bin_width), last bin open-ended.                    */
+void or_histogram(const or_sim* s, const int32_t* lab, int32_t nb, int32_t nbins, double bin_width,
+                  int64_t* counts, int64_t* sizes) {
+  for (int32_t b = 0; b <= nb; b++) sizes[b] = 0;
+  for (long c = 0; c < s->N; c++) sizes[lab[c]]++;
+  for (int32_t k = 0; k < nbins; k++) counts[k] = 0;
+  for (int32_t b = 1; b <= nb; b++) {
+    double v = (double)sizes[b];
+    double d = s->D == 2 ? 2.0 * sqrt(v / M_PI) : cbrt(6.0 * v / M_PI);
+    long k = (long)floor(d / bin_width);
+    if (k >= nbins) k = nbins - 1;
+    counts[k]++;
+  }
+}

@@ -1,0 +1,395 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (tests/golden/paper_values.json), closed forms, conservation
+invariants, mechanical balance, or an independent brute-force restatement
+(tests/bruteforce.py).  No GPU is needed.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import OracleSim, lattice, p0, splitmix64, uniform
+
+from . import bruteforce as bf
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def _rest_populations(rho, kind):
+    e, w = lattice(kind)
+    rho = np.asarray(rho, np.float64)
+    return (w.reshape((-1,) + (1,) * rho.ndim) * rho[None]).copy()
+
+
+# --------------------------------------------------------------------------
+# lattice constants (textbook moments; D2Q9 weights printed in Sec. 2.1.1)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", [0, 1])
+def test_lattice_isotropy(kind):
+    e, w = lattice(kind)
+    e = e.astype(np.float64)
+    assert len(w) == (9 if kind == 0 else 19)
+    assert abs(w.sum() - 1) < 1e-15
+    assert np.abs((w[:, None] * e).sum(0)).max() < 1e-15
+    second = np.einsum("q,qa,qb->ab", w, e, e)
+    D = 2 if kind == 0 else 3
+    expect2 = np.zeros((3, 3))
+    expect2[:D, :D] = np.eye(D) / 3
+    assert np.abs(second - expect2).max() < 1e-15
+    third = np.einsum("q,qa,qb,qc->abc", w, e, e, e)
+    assert np.abs(third).max() < 1e-15
+    fourth = np.einsum("q,qa,qb,qc,qd->abcd", w, e, e, e, e)
+    d = np.zeros((3, 3))
+    d[:D, :D] = np.eye(D)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d) + np.einsum("ad,bc->abcd", d, d)) / 9
+    assert np.abs(fourth - iso).max() < 1e-15
+    # every direction has its opposite
+    for v in e:
+        assert any((u == -v).all() for u in e)
+
+
+def test_d2q9_weights_match_paper():
+    e, w = lattice(0)
+    g = GOLD["d2q9_weights"]
+    speed2 = (e ** 2).sum(1)
+    assert np.allclose(w[speed2 == 0], g["rest"], rtol=0, atol=1e-16)
+    assert np.allclose(w[speed2 == 1], g["axis"], rtol=0, atol=1e-16)
+    assert np.allclose(w[speed2 == 2], g["diagonal"], rtol=0, atol=1e-16)
+
+
+# --------------------------------------------------------------------------
+# counter-based generator for the seeded initial noise
+# --------------------------------------------------------------------------
+def test_splitmix64_published_outputs():
+    state = 0
+    for hexval in GOLD["splitmix64_state0_outputs"]["values_hex"]:
+        assert splitmix64(state) == int(hexval, 16)
+        state = (state + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+
+
+def test_uniform_range_and_mean():
+    u = np.array([uniform(7, i) for i in range(20000)])
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert abs(u.mean() - 0.5) < 0.01
+    assert len(set(u.tolist())) == len(u)
+
+
+# --------------------------------------------------------------------------
+# equation of state and pseudopotential (Sec. 2.1.2)
+# --------------------------------------------------------------------------
+def test_critical_point_matches_paper():
+    g = GOLD["critical_point"]
+    Gc, rc = g["G_c"], g["rho_c"]
+    assert abs(rc - math.log(2)) < 1e-15
+    h = 1e-4
+    d1 = (p0(rc + h, Gc) - p0(rc - h, Gc)) / (2 * h)
+    d2 = (p0(rc + h, Gc) - 2 * p0(rc, Gc) + p0(rc - h, Gc)) / h ** 2
+    assert abs(d1) < 1e-8
+    assert abs(d2) < 1e-5
+    # away from (G_c, rho_c) the conditions fail, so the zero above is not trivial
+    d1b = (p0(rc + h, -4.4) - p0(rc - h, -4.4)) / (2 * h)
+    assert d1b < -0.01
+    # G > G_c: p0 monotone (no phase separation); G < G_c: a spinodal region
+    rr = np.linspace(0.01, 4, 400)
+    assert np.all(np.diff([p0(r, -3.8) for r in rr]) > 0)
+    assert np.any(np.diff([p0(r, -4.5) for r in rr]) < 0)
+
+
+def test_pseudopotential_limits_match_paper():
+    # the limits printed after Eq. pseudopotential, read through p0 = rho/3 + G/6 psi^2
+    G = -6.0
+    lim = GOLD["pseudopotential_limits"]
+    for rho in (1e-4, 1e-3):
+        psi = math.sqrt(max(0.0, (p0(rho, G) - rho / 3) / (G / 6)))
+        assert abs(psi / rho - lim["small_rho_slope"]) < 2 * rho
+    psi_big = math.sqrt((p0(40.0, G) - 40.0 / 3) / (G / 6))
+    assert abs(psi_big - lim["large_rho_limit"]) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# quiescent state, conservation (T1-T3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,dims", [(0, (10, 7, 1)), (1, (5, 4, 3))])
+def test_quiescent_uniform_state_unchanged(kind, dims):
+    nx, ny, nz = dims
+    s = OracleSim(lattice=kind, nx=nx, ny=ny, nz=nz, G=-5.0, noise_amp=0.0, rho_liquid=1.3)
+    s.set_nuclei([])
+    f0 = s.populations().copy()
+    s.step(1000)
+    f = s.populations()
+    assert np.abs(f - f0).max() / f0.max() <= 1e-14
+    assert np.all(s.velocity() == 0.0)
+
+
+def test_mass_conservation_config1():
+    # 128^2, G=-5, one centred bubble R=20 (rho 0.15 in 2.0), noise 0.01, film on
+    s = OracleSim(lattice=0, nx=128, ny=128, G=-5.0, film_on=1, seed=1)
+    s.set_nuclei([[64, 64, 0, 20]])
+    m0, _ = s.stats()
+    s.step(2000)
+    m1, _ = s.stats()
+    # BGK with sum_i f_eq,i = rho conserves mass exactly in exact arithmetic; in FP64
+    # the weights 1/9 and 1/36 round, which leaves a bias below one ulp per step
+    assert abs(m1 - m0) / m0 <= 2000 * 2.0 ** -52
+
+
+def test_momentum_conservation_film_off():
+    s = OracleSim(lattice=0, nx=48, ny=40, G=-5.5, rho_liquid=2.3, rho_gas=0.11, seed=5)
+    s.set_nuclei([[10, 12, 0, 6], [30, 25, 0, 8]])
+    m, _ = s.stats()
+    s.step(400)
+    _, mom = s.stats()
+    assert np.abs(mom).max() <= 1e-12 * m
+
+
+# --------------------------------------------------------------------------
+# collision: equilibrium moments and BGK relaxation on a one-cell lattice
+# (every neighbour is the cell itself, so F = 0 and streaming is the identity)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", [0, 1])
+def test_equilibrium_moments(kind):
+    e, w = lattice(kind)
+    rng = np.random.default_rng(11 + kind)
+    f = w * (1.4 + 0.3 * rng.random(len(w)))
+    s = OracleSim(lattice=kind, nx=1, ny=1, nz=1, tau=1.0, G=-5.0)
+    s.set_populations(f)
+    s.step(1)
+    feq = s.populations().reshape(-1)
+    rho = f.sum()
+    j = (e * f[:, None]).sum(0)
+    assert abs(feq.sum() - rho) < 1e-14
+    assert np.abs((e * feq[:, None]).sum(0) - j).max() < 1e-14
+    Pi = np.einsum("q,qa,qb->ab", feq, e.astype(float), e.astype(float))
+    D = 2 if kind == 0 else 3
+    expect = np.zeros((3, 3))
+    expect[:D, :D] = rho / 3 * np.eye(D)
+    expect += np.outer(j, j) / rho
+    assert np.abs(Pi - expect).max() < 1e-14
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_bgk_relaxation_factor(kind):
+    e, w = lattice(kind)
+    rng = np.random.default_rng(3)
+    f0 = w * (1.0 + 0.5 * rng.random(len(w)))
+    one = OracleSim(lattice=kind, nx=1, ny=1, nz=1, tau=1.0)
+    one.set_populations(f0)
+    one.step(1)
+    feq = one.populations().reshape(-1)
+    tau = 1.7
+    s = OracleSim(lattice=kind, nx=1, ny=1, nz=1, tau=tau)
+    s.set_populations(f0)
+    s.step(2)
+    f2 = s.populations().reshape(-1)
+    assert np.abs((f2 - feq) - (1 - 1 / tau) ** 2 * (f0 - feq)).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# Shan-Chen force: closed form on sinusoidal psi, Taylor coefficients
+# --------------------------------------------------------------------------
+def _psi_to_rho(psi):
+    return -np.log(1 - psi)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_force_closed_form_sinusoid(kind):
+    nx, ny, nz = (48, 40, 1) if kind == 0 else (24, 20, 16)
+    kx, ky, kz = 2 * np.pi / nx, 2 * np.pi / ny, 2 * np.pi / nz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    A, B, C = 0.2, 0.15, (0.1 if kind == 1 else 0.0)
+    psi = 0.5 + A * np.sin(kx * x) + B * np.sin(ky * y) + C * np.sin(kz * z)
+    G = -5.0
+    s = OracleSim(lattice=kind, nx=nx, ny=ny, nz=nz, G=G)
+    rho = _psi_to_rho(psi)
+    s.set_populations(_rest_populations(rho if kind == 1 else rho[0], kind))
+    F = s.force(with_film=0)
+    # sum_i w_i e_i psi(x+e_i) for a separable sinusoid: (1/3) A sin(k) cos(k x) per axis
+    ex = -G * psi * (1 / 3) * A * np.sin(kx) * np.cos(kx * x)
+    ey = -G * psi * (1 / 3) * B * np.sin(ky) * np.cos(ky * y)
+    if kind == 0:
+        ex, ey = ex[0], ey[0]
+    assert np.abs(F[0] - ex).max() < 1e-13
+    assert np.abs(F[1] - ey).max() < 1e-13
+    if kind == 1:
+        ez = -G * psi * (1 / 3) * C * np.sin(kz) * np.cos(kz * z)
+        assert np.abs(F[2] - ez).max() < 1e-13
+
+
+def test_force_taylor_coefficients_match_paper():
+    # F = -G psi (a psi' + b psi''') + O(k^5) with (a, b) printed in Eq. tylor
+    tc = GOLD["taylor_coefficients"]
+    G = -5.0
+    errs = []
+    for n in (64, 128, 256):
+        k = 2 * np.pi / n
+        x = np.arange(n)
+        psi = 0.5 + 0.2 * np.sin(k * x)
+        s = OracleSim(lattice=0, nx=n, ny=1, G=G)
+        s.set_populations(_rest_populations(_psi_to_rho(psi)[None], 0))
+        F = s.force(with_film=0)[0, 0]
+        d1 = 0.2 * k * np.cos(k * x)
+        d3 = -0.2 * k ** 3 * np.cos(k * x)
+        taylor = -G * psi * (tc["grad"] * d1 + tc["grad_laplacian"] * d3)
+        errs.append(np.abs(F - taylor).max())
+    # remainder shrinks like k^5: halving k cuts it by ~32
+    assert errs[0] / errs[1] > 25 and errs[1] / errs[2] > 25
+
+
+# --------------------------------------------------------------------------
+# brute force on tiny lattices (T6)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,dims,G,tau", [(0, (8, 8, 1), -5.0, 1.0), (0, (7, 5, 1), -4.6, 0.8),
+                                             (1, (4, 4, 4), -5.5, 1.0), (1, (5, 3, 4), -5.0, 1.3)])
+def test_bruteforce_literal_steps(kind, dims, G, tau):
+    nx, ny, nz = dims
+    e, w = lattice(kind)
+    rng = np.random.default_rng(17)
+    rho = 0.3 + 1.7 * rng.random((nz, ny, nx))
+    f = w[:, None, None, None] * rho[None] * (1 + 0.2 * (rng.random((len(w), nz, ny, nx)) - 0.5))
+    s = OracleSim(lattice=kind, nx=nx, ny=ny, nz=nz, G=G, tau=tau)
+    s.set_populations(f if kind == 1 else f[:, 0])
+    ref = bf.to_velset_order(f, e, kind)
+    for _ in range(5):
+        ref = bf.literal_step(ref, kind, G, tau)
+    s.step(5)
+    got = s.populations()
+    got = bf.to_velset_order(got if kind == 1 else got[:, None], e, kind)
+    assert np.abs(got - ref).max() / ref.max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# flat interface: mechanical coexistence p0(rho_l) = p0(rho_g) (T4)
+# --------------------------------------------------------------------------
+def _flat_profile(kind, G, rl, rg, steps=40000, nx=65):
+    # an odd periodic length: the checkerboard momentum mode (j alternating cell by
+    # cell and step by step, which LBM never damps) cannot exist, so the slab
+    # reaches a true steady state.
+    s = OracleSim(lattice=kind, nx=nx, ny=1, nz=1, G=G, noise_amp=0.0)
+    x = np.arange(nx)
+    rho = np.where(np.abs(x - nx // 2) < nx // 4, rl, rg).astype(np.float64)
+    s.set_populations(_rest_populations(rho[None, None] if kind == 1 else rho[None], kind))
+    s.step(steps)
+    return s, s.density().reshape(-1)
+
+
+BRACKET = {-5.0: ((0.119, 1.888), (0.187, 1.959))}  # eps = 0 and eps = 2 coexistence pairs
+
+
+def test_flat_interface_coexistence_and_cross_lattice():
+    G = -5.0
+    s2, r2 = _flat_profile(0, G, 1.9, 0.15)
+    s3, r3 = _flat_profile(1, G, 1.9, 0.15)
+    rl, rg = r2.max(), r2.min()
+    assert abs(p0(rl, G) - p0(rg, G)) <= 1e-9
+    # D2Q9 and D3Q19 project to the same 1-D lattice for an x-aligned slab; the
+    # two sum 9 vs 19 terms in different orders, so 40000 steps leave roundoff
+    assert np.abs(r2 - r3).max() <= 1e-10
+    # sanity range between the eps=0 and eps=2 mechanical-stability solutions
+    (g0, l0), (g2, l2) = BRACKET[G]
+    assert 0.95 * g0 <= rg <= 1.05 * g2
+    assert 0.95 * l0 <= rl <= 1.05 * l2
+    # steady state: no further change
+    f0 = s2.populations().copy()
+    s2.step(1)
+    assert np.abs(s2.populations() - f0).max() < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Laplace's law for static bubbles (T5)
+# --------------------------------------------------------------------------
+@pytest.mark.slow
+def test_laplace_law():
+    G, rl0, rg0 = -5.5, 2.3, 0.11
+    # surface tension of the flat interface: the paper's pressure-tensor term
+    # -(G/18) int (d psi/dn)^2 dn summed on lattice links, plus the kinetic
+    # anisotropy rho u_eq^2 = F^2 / (4 rho) that the velocity-shift forcing adds
+    s, r = _flat_profile(0, G, rl0, rg0)
+    psi = 1 - np.exp(-r)
+    F = s.force(with_film=0)[0].reshape(-1)
+    sigma = (-(G / 18) * np.sum((np.roll(psi, -1) - psi) ** 2) + np.sum(F ** 2 / (4 * r))) / 2
+    L = 101
+    c = (L - 1) / 2
+    rows = []
+    for R in (15.0, 18.0, 22.0, 26.0):
+        b = OracleSim(lattice=0, nx=L, ny=L, G=G, noise_amp=0.0, rho_liquid=rl0, rho_gas=rg0)
+        b.set_nuclei([[c, c, 0, R]])
+        b.step(6000)
+        d = b.density()
+        ic = int(c)
+        rin, rout = d[ic, ic], d[0, 0]
+        req = math.sqrt(np.sum((d - rout) / (rin - rout)) / math.pi)
+        rows.append((req, p0(rin, G) - p0(rout, G)))
+    rows = np.array(rows)
+    A = np.vstack([1 / rows[:, 0], np.ones(len(rows))]).T
+    (slope, icpt), *_ = np.linalg.lstsq(A, rows[:, 1], rcond=None)
+    pred = A @ np.array([slope, icpt])
+    r2 = 1 - np.sum((rows[:, 1] - pred) ** 2) / np.sum((rows[:, 1] - rows[:, 1].mean()) ** 2)
+    assert r2 >= 0.999
+    assert abs(icpt) <= 0.05 * rows[0, 1]
+    assert abs(slope / sigma - 1) <= 0.10
+
+
+# --------------------------------------------------------------------------
+# critical point dynamics (T7)
+# --------------------------------------------------------------------------
+def test_critical_point_dynamics():
+    rc = math.log(2)
+
+    def spread(G):
+        s = OracleSim(lattice=0, nx=33, ny=33, G=G, rho_liquid=rc, noise_amp=0.01, seed=9)
+        s.set_nuclei([])
+        r0 = s.density()
+        s.step(3000)
+        r = s.density()
+        return r0.max() - r0.min(), r.max() - r.min()
+
+    a0, a1 = spread(-3.8)
+    b0, b1 = spread(-4.5)
+    assert a1 < 0.1 * a0  # above G_c: perturbations decay
+    assert b1 > 0.5  # below G_c: phase separation
+
+
+# --------------------------------------------------------------------------
+# initial state (random nucleation with periodic minimum image)
+# --------------------------------------------------------------------------
+def test_nuclei_minimum_image_gauss_counts():
+    # lattice points within radius r of a corner nucleus, counted across the wrap:
+    # Gauss circle N(3) = 29, ball N(2) = 33
+    s = OracleSim(lattice=0, nx=16, ny=12, noise_amp=0.0, rho_liquid=2.0, rho_gas=0.1)
+    s.set_nuclei([[0.0, 0.0, 0.0, 3.0]])
+    assert int(np.sum(s.density() < 1.0)) == 29
+    s3 = OracleSim(lattice=1, nx=8, ny=9, nz=10, noise_amp=0.0, rho_liquid=2.0, rho_gas=0.1)
+    s3.set_nuclei([[7.0, 0.0, 9.0, 2.0]])
+    assert int(np.sum(s3.density() < 1.0)) == 33
+
+
+def test_initial_noise_uses_counter_generator():
+    s = OracleSim(lattice=0, nx=9, ny=5, noise_amp=0.01, rho_liquid=2.0, seed=123)
+    s.set_nuclei([])
+    d = s.density().reshape(-1)
+    expect = 2.0 + 0.01 * (2 * np.array([uniform(123, i) for i in range(45)]) - 1)
+    assert np.abs(d - expect).max() < 1e-15
+
+
+def test_generalised_pseudopotential_scaling():
+    # psi = rho0 (1 - exp(-rho/rho0)) rescales the critical point of Eq. Pequ to
+    # G_c = -4 / rho0 at rho_c = rho0 ln 2; the force closed form keeps its shape
+    for rho0 in (0.5, 2.0):
+        rc, Gc = rho0 * math.log(2), -4.0 / rho0
+        h = 1e-4 * rho0
+        d1 = (p0(rc + h, Gc, rho0) - p0(rc - h, Gc, rho0)) / (2 * h)
+        d2 = (p0(rc + h, Gc, rho0) - 2 * p0(rc, Gc, rho0) + p0(rc - h, Gc, rho0)) / h ** 2
+        assert abs(d1) < 1e-8 and abs(d2) < 1e-5
+        n = 48
+        k = 2 * np.pi / n
+        x = np.arange(n)
+        psi = rho0 * (0.5 + 0.2 * np.sin(k * x))
+        rho = -rho0 * np.log(1 - psi / rho0)
+        s = OracleSim(lattice=0, nx=n, ny=1, G=-5.0, rho0=rho0)
+        s.set_populations(_rest_populations(rho[None], 0))
+        F = s.force(with_film=0)[0, 0]
+        assert np.abs(F - 5.0 * psi * (1 / 3) * 0.2 * rho0 * np.sin(k) * np.cos(k * x)).max() < 1e-13
