@@ -1,0 +1,126 @@
+// lattice.hpp -- velocity sets, weights and storage formats of the GPU path.
+//
+// Kernels work in "kernel coordinates" (x, m, z): x is the contiguous axis, z
+// the axis a workgroup marches along, m the second tile axis.  D3Q19 maps
+// (x, y, z) -> (x, m, z).  D2Q9 maps its (x, y) -> (x, z) with an m axis of
+// extent 1, so one kernel template serves both lattices.
+//
+// D2Q9 weights are the paper's (Sec. 2.1.1: rest 4/9, axes 1/9, diagonals
+// 1/36); D3Q19 is the textbook lattice (rest 1/3, axes 1/18, face diagonals
+// 1/36).  Directions come in opposite pairs (2p-1, 2p), p = 1..(Q-1)/2, so the
+// neighbour-sum force can be accumulated as w_i e_i (psi(x+e_i) - psi(x-e_i)).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flb {
+
+struct D2Q9K {
+  static constexpr int Q = 9;
+  static constexpr int D = 2;
+  static constexpr bool HAS_M = false;
+  // kernel coordinates: lattice (ex, ey) -> (ex, 0, ey)
+  static constexpr int ex[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+  static constexpr int em[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr int ez[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+  static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                  1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  // lattice-coordinate component k (0 = x, 1 = y) of direction i
+  __host__ __device__ static constexpr int comp(int i, int k) { return k == 0 ? ex[i] : ez[i]; }
+};
+
+struct D3Q19K {
+  static constexpr int Q = 19;
+  static constexpr int D = 3;
+  static constexpr bool HAS_M = true;
+  static constexpr int ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int em[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                   1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  __host__ __device__ static constexpr int comp(int i, int k) {
+    return k == 0 ? ex[i] : (k == 1 ? em[i] : ez[i]);
+  }
+};
+
+// Population layout: blocks of 64 consecutive x-cells (one wavefront).  A
+// block holds the Q populations of its cells one after the other (64 values
+// each), so a wavefront's access to one population is one contiguous 64-value
+// run and a block's Q runs share a few DRAM pages.  Block index
+// b = x / 64 + nxb * (m + nm * z) in kernel coordinates (nxb = ceil(nx / 64));
+// population i of lane xl = x % 64 sits at byte
+//   b * block_bytes + pofs(i) + xl * esz(i).
+constexpr int kBlk = 64;
+
+struct Geo {
+  int nx, nm, nz;  // kernel-coordinate extents
+  int nxb;         // blocks per row, ceil(nx / 64)
+  unsigned block_bytes;
+};
+
+// Storage formats: `ct` is the compute type; esz / pofs give the element
+// size and the byte offset of population i's run inside a block; dec / enc
+// convert between the stored element and the compute type.
+struct SF64 {
+  using ct = double;
+  static constexpr bool HALF = false;
+  __host__ __device__ static constexpr unsigned esz(int) { return 8; }
+  __host__ __device__ static constexpr unsigned pofs(int i) { return 512u * i; }
+};
+struct SF32 {
+  using ct = float;
+  static constexpr bool HALF = false;
+  __host__ __device__ static constexpr unsigned esz(int) { return 4; }
+  __host__ __device__ static constexpr unsigned pofs(int i) { return 256u * i; }
+};
+// FP16 of the shifted population f_i - w_i for the moving directions, and the
+// rest population (the largest, never streamed) in FP32; compute in FP32.
+struct SF16S {
+  using ct = float;
+  static constexpr bool HALF = true;
+  __host__ __device__ static constexpr unsigned esz(int i) { return i == 0 ? 4 : 2; }
+  __host__ __device__ static constexpr unsigned pofs(int i) { return i == 0 ? 0u : 256u + 128u * (i - 1); }
+};
+
+template <class S>
+__host__ __device__ constexpr unsigned block_bytes(int Q) {
+  return S::pofs(Q - 1) + kBlk * S::esz(Q - 1);
+}
+
+// byte offset of a cell's block and of its lane inside a run
+__host__ __device__ inline unsigned long long block_of(const Geo& g, int x, int m, int z) {
+  return (unsigned long long)((x >> 6) + (long long)g.nxb * (m + (long long)g.nm * z)) * g.block_bytes;
+}
+
+// generic (global-pointer) access, used outside the step kernel
+template <class L, class S>
+__device__ inline typename S::ct pop_ld(const void* base, const Geo& g, int i, int x, int m, int z) {
+  const char* p = (const char*)base + block_of(g, x, m, z) + S::pofs(i) + (unsigned)(x & 63) * S::esz(i);
+  if constexpr (sizeof(typename S::ct) == 8) return *(const double*)p;
+  else if (S::HALF && i > 0) return (float)*(const _Float16*)p + (float)L::w[i];
+  else return *(const float*)p;
+}
+template <class L, class S>
+__device__ inline void pop_st(void* base, const Geo& g, int i, int x, int m, int z, typename S::ct v) {
+  char* p = (char*)base + block_of(g, x, m, z) + S::pofs(i) + (unsigned)(x & 63) * S::esz(i);
+  if constexpr (sizeof(typename S::ct) == 8) *(double*)p = v;
+  else if (S::HALF && i > 0) *(_Float16*)p = (_Float16)(v - (float)L::w[i]);
+  else *(float*)p = v;
+}
+
+// Device-side run control shared by every launch of one lattice.
+struct Ctl {
+  unsigned done;        // workgroups finished in the current launch
+  int stopped;          // 1 after a rupture with on_rupture == 1
+  long long steps;      // steps completed (selects the A/B buffer)
+  unsigned ev_count;    // rupture events written so far (may exceed capacity)
+  unsigned ev_start;    // first event of the step in flight
+  long long n_ruptures; // successful barrier removals
+  int failed;           // 1 once the FP64 mass reduction saw a non-finite value
+  int n_bubbles;        // labels in the current film maps
+  double mass, mom[3];  // FP64 totals of the state entering the last step
+};
+
+}  // namespace flb

@@ -1,0 +1,185 @@
+// ops.hpp -- initialisation, state import/export, queries and FP64 totals.
+#pragma once
+#include "maps.hpp"
+
+namespace flb {
+
+// Vigna's SplitMix64 output function of one 64-bit state.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+  unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Initial density (Sec. 2.1.3): rho_gas inside any nucleus (periodic minimum
+// image, integer cell centres), rho_liquid elsewhere, plus a (2U - 1) noise.
+// Lattice coordinates (x, y, z); FP64 without contraction so that the inside
+// test rounds exactly like a plain C evaluation.
+__global__ void k_init_density(double* rho, int nx, int ny, int nz, long long N, const double4* nuc, int nn,
+                               double rl, double rg, double amp, unsigned long long seed) {
+#pragma clang fp contract(off)
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
+       c += (long long)gridDim.x * blockDim.x) {
+    const long long x = c % nx, y = (c / nx) % ny, z = c / ((long long)nx * ny);
+    bool inside = false;
+    for (int k = 0; k < nn && !inside; k++) {
+      const double4 q = nuc[k];
+      double dx = (double)x - q.x, dy = (double)y - q.y, dz = (double)z - q.z;
+      dx = dx - (double)nx * floor(dx / (double)nx + 0.5);
+      dy = dy - (double)ny * floor(dy / (double)ny + 0.5);
+      dz = dz - (double)nz * floor(dz / (double)nz + 0.5);
+      const double d2 = dx * dx + dy * dy + dz * dz;
+      if (d2 <= q.w * q.w) inside = true;
+    }
+    const unsigned long long h = splitmix64(seed ^ ((unsigned long long)c * 0x9E3779B97F4A7C15ull));
+    const double u = (double)(h >> 11) * (1.0 / 9007199254740992.0);
+    rho[c] = (inside ? rg : rl) + amp * (2.0 * u - 1.0);
+  }
+}
+
+// Write a state into the pull layout: buffer[i][c] holds f_i(c + e_i).
+// mode 0: f_i = w_i * field[c] (rest equilibrium of a density field);
+// mode 1: f_i = field[i * N + c] (populations in direction order).
+template <class L, class S>
+__global__ void k_pack(void* buf, Geo geo, MapDims d, const double* field, int mode) {
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < d.N;
+       c += (long long)gridDim.x * blockDim.x) {
+    int x, m, z;
+    coords_of(d, c, x, m, z);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+      const long long y = cell_of(d, wrap_any(x + L::ex[i], d.nx), wrap_any(m + L::em[i], d.nm),
+                                  wrap_any(z + L::ez[i], d.nz));
+      using T = typename S::ct;
+      const T v = mode == 0 ? (T)(L::w[i] * field[y]) : (T)field[(long long)i * d.N + y];
+      pop_st<L, S>(buf, geo, i, x, m, z, v);
+    }
+  }
+}
+
+// Current populations f_i(c) = buffer[i][c - e_i] as FP64, direction order.
+template <class L, class S>
+__global__ void k_unpack(const void* b0, const void* b1, const Ctl* ctl, Geo geo, MapDims d, double* out) {
+  const void* src = (ctl->steps & 1) ? b1 : b0;
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < d.N;
+       c += (long long)gridDim.x * blockDim.x) {
+    int x, m, z;
+    coords_of(d, c, x, m, z);
+    typename S::ct f[L::Q];
+    load_pulled<L, S>(src, geo, x, m, z, f);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) out[(long long)i * d.N + c] = (double)f[i];
+  }
+}
+
+// FP64 moments of the current state: rho, then D momentum planes (lattice axes)
+template <class L, class S>
+__global__ void k_moments(const void* b0, const void* b1, const Ctl* ctl, Geo geo, MapDims d,
+                          double* rho, double* j) {
+  const void* src = (ctl->steps & 1) ? b1 : b0;
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < d.N;
+       c += (long long)gridDim.x * blockDim.x) {
+    int x, m, z;
+    coords_of(d, c, x, m, z);
+    typename S::ct f[L::Q];
+    load_pulled<L, S>(src, geo, x, m, z, f);
+    double r = 0.0, jj[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+      const double v = (double)f[i];
+      r += v;
+#pragma unroll
+      for (int k = 0; k < L::D; k++)
+        if (L::comp(i, k)) jj[k] += L::comp(i, k) > 0 ? v : -v;
+    }
+    rho[c] = r;
+    if (j)
+#pragma unroll
+      for (int k = 0; k < L::D; k++) j[(long long)k * d.N + c] = jj[k];
+  }
+}
+
+// u = j/rho (mode 0) or (j + F/2)/rho (mode 1) with the force of the current
+// state under the current film maps, in FP64 from the FP64 moments
+template <class L>
+__global__ void k_velocity(StepArgs a, MapDims d, const double* rho, const double* j, int mode, double* out) {
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < d.N;
+       c += (long long)gridDim.x * blockDim.x) {
+    double F[3] = {0.0, 0.0, 0.0};
+    if (mode == 1) {
+      int x, m, z;
+      coords_of(d, c, x, m, z);
+      const double psic = psi_of(rho[c], a.rho0);
+      unsigned bar = 0;
+      if (a.film_on && a.flag[c]) bar = active_links<L>(a, x, m, z, c);
+      const double pb = a.psi_bar_mode == 0 ? a.psi_bar : psic;
+      for (int i = 1; i < L::Q; i += 2) {
+        const long long yp = cell_of(d, wrap_any(x + L::ex[i], d.nx), wrap_any(m + L::em[i], d.nm),
+                                     wrap_any(z + L::ez[i], d.nz));
+        const long long ym = cell_of(d, wrap_any(x - L::ex[i], d.nx), wrap_any(m - L::em[i], d.nm),
+                                     wrap_any(z - L::ez[i], d.nz));
+        double pp = psi_of(rho[yp], a.rho0), pm = psi_of(rho[ym], a.rho0);
+        if (bar & (1u << i)) pp = pb;
+        if (bar & (1u << (i + 1))) pm = pb;
+        const double dd = L::w[i] * (pp - pm);
+        for (int k = 0; k < L::D; k++) F[k] += L::comp(i, k) * dd;
+      }
+      for (int k = 0; k < L::D; k++) F[k] *= -a.G * psic;
+    }
+    for (int k = 0; k < L::D; k++) out[(long long)k * d.N + c] = (j[(long long)k * d.N + c] + 0.5 * F[k]) / rho[c];
+  }
+}
+
+// FP64 totals: per-block partial sums of up to 4 planes, then one block sums
+// the partials in block order (deterministic)
+constexpr int RED_BLOCK = 256;
+__global__ __launch_bounds__(RED_BLOCK) void k_reduce_partial(const double* planes, int nplanes, long long N,
+                                                              double* partials) {
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long c = blockIdx.x * (long long)RED_BLOCK + threadIdx.x; c < N; c += (long long)gridDim.x * RED_BLOCK)
+    for (int q = 0; q < nplanes; q++) t[q] += planes[(long long)q * N + c];
+  __shared__ double s[RED_BLOCK / 64][4];
+  for (int q = 0; q < 4; q++)
+    for (int off = 32; off > 0; off >>= 1) t[q] += __shfl_down(t[q], off, 64);
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 4; q++) s[threadIdx.x >> 6][q] = t[q];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double v = 0.0;
+    for (int w = 0; w < RED_BLOCK / 64; w++) v += s[w][threadIdx.x];
+    partials[4ll * blockIdx.x + threadIdx.x] = v;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_reduce_final(const double* partials, int nblocks, double* out) {
+  if (threadIdx.x < 4) {
+    double v = 0.0;
+    for (int b = 0; b < nblocks; b++) v += partials[4ll * b + threadIdx.x];
+    out[threadIdx.x] = v;
+  }
+}
+
+// bubble sizes (cells per label) and equivalent-diameter histogram
+__global__ void k_label_sizes(const int* label, long long N, unsigned long long* sizes) {
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
+       c += (long long)gridDim.x * blockDim.x) {
+    const int l = label[c];
+    if (l > 0) atomicAdd(&sizes[l], 1ull);
+  }
+}
+
+__global__ void k_histogram(const unsigned long long* sizes, const int* n_bubbles, int D, int nbins, double width,
+                            unsigned long long* counts) {
+  const int nb = *n_bubbles;
+  for (int b = 1 + blockIdx.x * blockDim.x + threadIdx.x; b <= nb; b += gridDim.x * blockDim.x) {
+    const double v = (double)sizes[b];
+    const double dm = D == 2 ? 2.0 * sqrt(v / 3.141592653589793) : cbrt(6.0 * v / 3.141592653589793);
+    long long k = (long long)floor(dm / width);
+    if (k >= nbins) k = nbins - 1;
+    if (k < 0) k = 0;
+    atomicAdd(&counts[k], 1ull);
+  }
+}
+
+}  // namespace flb

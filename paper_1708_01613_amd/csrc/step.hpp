@@ -1,0 +1,548 @@
+// step.hpp -- the fused Shan-Chen step kernel and the film-link helpers it shares
+// with the query kernels.
+//
+// One launch advances one lattice by one step (Sec. 2.1.1, 2.1.2, 2.1.5):
+// pull populations -> rho, j -> psi(rho) staged in LDS -> neighbour-sum force with
+// the film-barrier substitution -> velocity-shifted BGK -> store.  Populations
+// are structure-of-arrays planes f[i][cell]; the buffer written at step n holds
+// post-collision values at their own cell, and step n+1 pulls f_i(x) from
+// cell x - e_i of it (the streaming equation in pull form, periodic).
+//
+// Work decomposition: a workgroup owns a TX x TM tile of the (x, m) plane and
+// a segment of LZ planes along z.  It marches z: for plane zz it pulls the Q
+// populations of its own cells (kept in registers) and of a one-cell halo ring
+// (summed to rho only), writes rho and psi into a 4-plane LDS ring, and after
+// one barrier collides plane zz-1, whose psi neighbours (planes zz-2..zz) are
+// all in the ring.  Each population is read once per step plus the halo and
+// segment-end planes, and written once.
+#pragma once
+#include "lattice.hpp"
+
+namespace flb {
+
+struct StepArgs {
+  void* buf[2];          // population buffers; buf[steps & 1] holds the current state
+  Geo geo;               // block layout of the population buffers
+  int nx, nm, nz;        // kernel-coordinate extents
+  int tiles_x, tiles_m;  // tile grid of the (x, m) plane
+  int lz;                // planes per z segment
+  int xcd_chunks;        // > 1: consecutive logical tiles share an XCD
+  double tau, G, rho0;
+  double psi_bar;        // psi(rho_liquid), used when psi_bar_mode == 0
+  int psi_bar_mode;
+  int film_on, rupture_warmup, on_rupture;
+  const uint8_t* flag;   // per cell: 1 if it has candidate barrier links
+  const uint32_t* mask;  // per cell: candidate barrier links, bit i = direction i
+  const int2* own;       // per cell: (smallest, largest) nearest bubble label
+  int* alias;            // union-find parents over labels
+  unsigned long long buf_bytes;  // bytes of one population buffer
+  long long* events;     // rupture log, 4 x int64 per event: step, k, k2, 0
+  unsigned ev_cap;
+  Ctl* ctl;
+  double* partials;      // 4 doubles per workgroup
+};
+
+__device__ __forceinline__ int wrap_dec(int a, int n) { return a == 0 ? n - 1 : a - 1; }
+__device__ __forceinline__ int wrap_inc(int a, int n) { return a == n - 1 ? 0 : a + 1; }
+__device__ __forceinline__ int wrap_any(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+__device__ __forceinline__ int uf_root(const int* __restrict__ par, int a) {
+  int p = par[a];
+  while (p != a) {
+    a = p;
+    p = par[a];
+  }
+  return a;
+}
+
+// (low, high) alias roots of a cell's nearest bubbles
+__device__ __forceinline__ int2 root_pair(const int* __restrict__ alias, int2 o) {
+  int a = uf_root(alias, o.x), b = uf_root(alias, o.y);
+  return a < b ? make_int2(a, b) : make_int2(b, a);
+}
+
+// Active barrier links of a flagged cell: candidate links whose two ends still
+// have different alias-root pairs (the barrier between a pair of bubbles is
+// removed once they are aliased by a rupture).
+template <class L>
+__device__ __forceinline__ unsigned active_links(const StepArgs& a, int x, int m, int z, long long c) {
+  unsigned cand = a.mask[c];
+  int2 rp = root_pair(a.alias, a.own[c]);
+  unsigned act = 0;
+#pragma unroll
+  for (int i = 1; i < L::Q; i++) {
+    if (cand & (1u << i)) {
+      int yx = wrap_any(x + L::ex[i], a.nx);
+      int ym = wrap_any(m + L::em[i], a.nm);
+      int yz = wrap_any(z + L::ez[i], a.nz);
+      long long yc = yx + (long long)a.nx * (ym + (long long)a.nm * yz);
+      int2 rq = root_pair(a.alias, a.own[yc]);
+      if (rq.x != rp.x || rq.y != rp.y) act |= 1u << i;
+    }
+  }
+  return act;
+}
+
+template <class T>
+__device__ __forceinline__ T psi_of(T rho, T rho0) {
+  return rho0 * (T(1) - exp(-rho / rho0));
+}
+
+__device__ __forceinline__ double p0_of(double rho, double G, double rho0) {
+  double psi = rho0 * (1.0 - exp(-rho / rho0));
+  return rho / 3.0 + G / 6.0 * psi * psi;
+}
+
+template <class L, class S>
+__device__ __forceinline__ void load_pulled(const void* __restrict__ src, const Geo& g, int x, int m, int z,
+                                            typename S::ct (&out)[L::Q]) {
+  const int xs[3] = {wrap_inc(x, g.nx), x, wrap_dec(x, g.nx)};  // index 1 - e
+  const int ms[3] = {L::HAS_M ? wrap_inc(m, g.nm) : 0, m, L::HAS_M ? wrap_dec(m, g.nm) : 0};
+  const int zs[3] = {wrap_inc(z, g.nz), z, wrap_dec(z, g.nz)};
+#pragma unroll
+  for (int i = 0; i < L::Q; i++)  // pull from x - e_i
+    out[i] = pop_ld<L, S>(src, g, i, xs[1 + L::ex[i]], ms[1 + L::em[i]], zs[1 + L::ez[i]]);
+}
+
+// FP64 second difference of p0 along every active barrier link of a cell, and
+// the rupture events it raises (Sec. 2.1.5, eta_m equation; Sec. 4)
+template <class L, int LH, int LW, class T>
+__device__ __forceinline__ void rupture_test(const StepArgs& a, Ctl* ctl, long long step, unsigned bar, int x, int m, int zc,
+                             long long c, const T (&s_rho)[4][LH][LW], const int (&sl)[3], int lm1, int lx1) {
+  const double G64 = a.G, r064 = a.rho0;
+  const double pc = p0_of((double)s_rho[sl[1]][lm1][lx1], G64, r064);
+  const int2 oc = a.own[c];
+#pragma unroll
+  for (int i = 1; i < L::Q; i++) {
+    if (!(bar & (1u << i))) continue;
+    const int o = (i & 1) ? i + 1 : i - 1;  // opposite direction
+    const double rp = (double)s_rho[sl[1 + L::ez[i]]][lm1 + L::em[i]][lx1 + L::ex[i]];
+    const double rm = (double)s_rho[sl[1 + L::ez[o]]][lm1 + L::em[o]][lx1 + L::ex[o]];
+    const double d2 = p0_of(rp, G64, r064) - 2.0 * pc + p0_of(rm, G64, r064);
+    if (d2 >= 0.0) {
+      const int yx = wrap_any(x + L::ex[i], a.nx), ym = wrap_any(m + L::em[i], a.nm),
+                yz = wrap_any(zc + L::ez[i], a.nz);
+      const int2 oy = a.own[yx + (long long)a.nx * (ym + (long long)a.nm * yz)];
+      const unsigned e = atomicAdd(&ctl->ev_count, 1u);
+      if (e < a.ev_cap) {
+        long long* ev = a.events + 4ll * e;
+        ev[0] = step;
+        ev[1] = min(oc.x, oy.x);
+        ev[2] = max(oc.y, oy.y);
+        ev[3] = 0;
+      }
+    }
+  }
+}
+
+// Population access of the step kernel: one buffer resource per population
+// buffer, a 32-bit per-lane byte offset (block and lane) and the population's
+// run offset inside the block as a constant (BUF, buffers below 2 GiB), or
+// plain global addresses (larger buffers).
+// Lanes outside the lattice store to kDropOffset, past the end of every buffer
+// the buffer path takes (< 2^31 bytes), so the buffer unit discards them; the
+// run offsets are small, so the offset sum cannot wrap into the buffer.
+constexpr unsigned kDropOffset = 0x80000000u;
+constexpr unsigned long long kBufPathLimit = 1ull << 31;
+constexpr unsigned long long kDrop = ~0ull;  // "discard" lane offset before lowering
+// s_waitcnt encoding (gfx9): vmcnt(0), expcnt and lgkmcnt left at their maxima
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+template <class L, class S, bool BUF>
+struct PopIO {
+  using T = typename S::ct;
+  const char* gs;
+  char* gd;
+  __amdgpu_buffer_rsrc_t rs, rd;
+  Geo g;
+
+  __device__ __forceinline__ void init(const void* src, void* dst, const Geo& geo, unsigned long long bytes) {
+    gs = (const char*)src;
+    gd = (char*)dst;
+    g = geo;
+    if (BUF) {
+      rs = __builtin_amdgcn_make_buffer_rsrc((void*)src, (short)0, (int)(unsigned)bytes, 0x00020000);
+      rd = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)(unsigned)bytes, 0x00020000);
+    }
+  }
+  // lane offset of cell (x, m, z): block bytes + lane * esz (esz of the
+  // moving populations; the FP16 format's FP32 rest run uses lane * 4)
+  __device__ __forceinline__ unsigned long long lane_off(int x, int m, int z, int i) const {
+    return block_of(g, x, m, z) + (unsigned)(x & 63) * S::esz(i);
+  }
+  __device__ __forceinline__ T load_at(int i, unsigned long long off) const {
+    const unsigned po = S::pofs(i);
+    const unsigned vo = (unsigned)off;  // buffer path: every offset is below 2^31
+    if constexpr (sizeof(T) == 8) {
+      if (BUF) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, vo, po, 0);
+        return __builtin_bit_cast(double, v);
+      }
+      return *(const double*)(gs + off + po);
+    } else if (S::HALF && i > 0) {
+      _Float16 h;
+      if (BUF) h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, vo, po, 0));
+      else h = *(const _Float16*)(gs + off + po);
+      return (float)h + (float)L::w[i];
+    } else {
+      if (BUF) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, po, 0));
+      return *(const float*)(gs + off + po);
+    }
+  }
+  // store population i of a cell whose lane offset is off (kDrop: discard)
+  __device__ __forceinline__ void store_at(int i, unsigned long long off, T v) const {
+    if (!BUF && off == kDrop) return;
+    const unsigned po = S::pofs(i);
+    const unsigned vo = off == kDrop ? kDropOffset : (unsigned)off;
+    if constexpr (sizeof(T) == 8) {
+      if (BUF) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rd, vo, po, 0);
+      } else {
+        *(double*)(gd + off + po) = v;
+      }
+    } else if (S::HALF && i > 0) {
+      const _Float16 h = (_Float16)(v - (float)L::w[i]);
+      if (BUF) __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), rd, vo, po, 0);
+      else *(_Float16*)(gd + off + po) = h;
+    } else {
+      if (BUF) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rd, vo, po, 0);
+      else *(float*)(gd + off + po) = v;
+    }
+  }
+  // the Q populations pulled into cell (x, m, z): f_i(x) = buffer_i(x - e_i)
+  __device__ __forceinline__ void pull(int x, int m, int z, T (&out)[L::Q]) const {
+    const int xs[3] = {wrap_inc(x, g.nx), x, wrap_dec(x, g.nx)};
+    const int ms[3] = {L::HAS_M ? wrap_inc(m, g.nm) : 0, m, L::HAS_M ? wrap_dec(m, g.nm) : 0};
+    const int zs[3] = {wrap_inc(z, g.nz), z, wrap_dec(z, g.nz)};
+#pragma unroll
+    for (int i = 0; i < L::Q; i++)
+      out[i] = load_at(i, lane_off(xs[1 + L::ex[i]], ms[1 + L::em[i]], zs[1 + L::ez[i]], i));
+  }
+};
+
+// Plane loop: iteration k loads plane z0-1+k (k <= L+1) into one register
+// set, collides plane z0+k-3 (k >= 3) from the set loaded two iterations
+// earlier while the new loads are in flight, then stores rho / psi of the new
+// plane into LDS slot k & 3 and synchronises once.  Slot j & 3 holds plane
+// z0-1+j; a collide at iteration k reads slots k-3..k-1, and the slot written
+// at iteration k was last read before the barrier of iteration k-1.  The three
+// register sets rotate by unrolling the loop three times.
+template <class L, class S, int TX, int TM, bool BUF>
+struct StepBlock {
+  using T = typename S::ct;
+  static constexpr int Q = L::Q;
+  static constexpr int NI = TX * TM;  // interior threads: one cell column each
+  static constexpr int HM = L::HAS_M ? 1 : 0;
+  static constexpr int LW = TX + 2;
+  static constexpr int LH = TM + 2 * HM;
+  // halo waves: one lane per ring cell of a full tile
+  static constexpr int NH = 2 * (TM + 2 * HM) + (HM ? 2 * TX : 0);
+  static constexpr int NT = NI + (NH + 63) / 64 * 64;
+  struct Smem {
+    T psi[4][LH][LW];
+    T rho[4][LH][LW];
+    double red[NT / 64][4];
+    int last;
+  };
+
+  const StepArgs& a;
+  Smem& sm;
+  PopIO<L, S, BUF> io;
+  Ctl* ctl;
+  long long step;
+  int nx, nm, nz, x0, m0, z0, L_, TXe, TMe, lx, lm, x, m, xc, mc, gx, gm, hx, hm;
+  bool act, has_halo, film, test_rupture, tau_one;
+  T G, rho0, tau, omega, psi_bar;
+  double acc_m = 0.0, acc_x = 0.0, acc_y = 0.0, acc_z = 0.0;
+
+  __device__ __forceinline__ StepBlock(const StepArgs& a_, Smem& sm_) : a(a_), sm(sm_) {}
+
+  // interior waves: load the new plane, collide the plane loaded two
+  // iterations ago, publish rho / psi of the new plane
+  __device__ __forceinline__ void iter(int k, T (&ld)[Q], T (&co)[Q], unsigned& fl_ld, unsigned fl_co) {
+    const bool loading = k <= L_ + 1;  // uniform over the workgroup
+    if (loading) {
+      // every interior lane loads (lanes outside the lattice read clamped
+      // cells and never publish), so no divergent branch separates the loads
+      // from the collide that overlaps them; the film flag is read first so
+      // the wait that ends this iteration covers it too
+      const int zl = wrap_any(z0 - 1 + k, nz);
+      if (film) fl_ld = (unsigned)a.flag[(unsigned)(xc + nx * (mc + nm * zl))];
+      io.pull(xc, mc, zl, ld);
+    }
+    // keep the collide between the loads and their first use
+    __builtin_amdgcn_sched_barrier(0);
+    if (k >= 3) collide(k, co, act ? fl_co : 0u);
+    __builtin_amdgcn_sched_barrier(0);
+    // every load and store of this wave retires here (the sum below needs the
+    // loads anyway); starting the next iteration with nothing outstanding
+    // keeps the compiler from waiting on the collide's registers there
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    if (loading) {
+      // the sum runs on every lane (so the wait for the loads is on every
+      // path); only lanes inside the lattice publish it
+      const int slot = k & 3;
+      T r = T(0);
+#pragma unroll
+      for (int i = 0; i < Q; i++) r += ld[i];
+      const T ps = psi_of(r, rho0);
+      if (act) {
+        sm.rho[slot][lm + HM][lx + 1] = r;
+        sm.psi[slot][lm + HM][lx + 1] = ps;
+      }
+    }
+    __syncthreads();
+  }
+
+  // halo waves: rho / psi of the ring cells of every loaded plane
+  __device__ __forceinline__ void halo_loop() {
+    const int kend = L_ + 2;
+    for (int k = 0; k <= kend; ++k) {
+      if (k <= L_ + 1 && has_halo) {
+        T hv[Q];
+        io.pull(gx, gm, wrap_any(z0 - 1 + k, nz), hv);
+        T r = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; i++) r += hv[i];
+        const int slot = k & 3;
+        sm.rho[slot][hm + HM][hx + 1] = r;
+        sm.psi[slot][hm + HM][hx + 1] = psi_of(r, rho0);
+      }
+      __syncthreads();
+    }
+  }
+
+  __device__ __forceinline__ void collide(int k, const T (&f)[Q], unsigned flag) {
+    const int zc = z0 + k - 3;
+    const int sl[3] = {(k - 3) & 3, (k - 2) & 3, (k - 1) & 3};
+    // lanes outside the lattice compute on clamped data and store to an
+    // offset past the end of the buffer, which the buffer unit discards
+    const unsigned c = (unsigned)(xc + nx * (mc + nm * zc));
+    const unsigned long long vo = act ? io.lane_off(x, m, zc, 1) : kDrop;
+    const unsigned long long vo0 = act ? io.lane_off(x, m, zc, 0) : kDrop;
+    T rho = T(0), jx = T(0), jm = T(0), jz = T(0);
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      rho += f[i];
+      if (L::ex[i]) jx += L::ex[i] > 0 ? f[i] : -f[i];
+      if (L::em[i]) jm += L::em[i] > 0 ? f[i] : -f[i];
+      if (L::ez[i]) jz += L::ez[i] > 0 ? f[i] : -f[i];
+    }
+    const int lm1 = lm + HM, lx1 = lx + 1;
+    const T psic = sm.psi[sl[1]][lm1][lx1];
+    unsigned bar = 0;
+    if (flag) bar = active_links<L>(a, x, m, zc, c);
+    const T pbar = a.psi_bar_mode == 0 ? psi_bar : psic;
+    T fx = T(0), fm = T(0), fz = T(0);
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      // pair (i, i+1) with e_{i+1} = -e_i
+      T pp = sm.psi[sl[1 + L::ez[i]]][lm1 + L::em[i]][lx1 + L::ex[i]];
+      T pm = sm.psi[sl[1 - L::ez[i]]][lm1 - L::em[i]][lx1 - L::ex[i]];
+      if (bar) {
+        if (bar & (1u << i)) pp = pbar;
+        if (bar & (1u << (i + 1))) pm = pbar;
+      }
+      const T d = (T)L::w[i] * (pp - pm);
+      if (L::ex[i]) fx += L::ex[i] > 0 ? d : -d;
+      if (L::em[i]) fm += L::em[i] > 0 ? d : -d;
+      if (L::ez[i]) fz += L::ez[i] > 0 ? d : -d;
+    }
+    const T gp = -G * psic;
+    fx *= gp;
+    fm *= gp;
+    fz *= gp;
+    const T inv = T(1) / rho;
+    const T ux = (jx + tau * fx) * inv;
+    const T um = (jm + tau * fm) * inv;
+    const T uz = (jz + tau * fz) * inv;
+    const T base = T(1) - T(1.5) * (ux * ux + um * um + uz * uz);
+    // equilibria in opposite pairs: common part w rho (base + 4.5 (e.u)^2),
+    // odd part w rho 3 e.u; the rest equilibrium is rho minus the moving ones
+    // (equal in exact arithmetic, and it keeps the common rounding of the FP32
+    // weights from adding mass every step)
+    T feq_moving = T(0);
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      T eu = T(0);
+      if (L::ex[i]) eu += L::ex[i] > 0 ? ux : -ux;
+      if (L::em[i]) eu += L::em[i] > 0 ? um : -um;
+      if (L::ez[i]) eu += L::ez[i] > 0 ? uz : -uz;
+      const T wr = (T)L::w[i] * rho;
+      const T even = wr * (base + T(4.5) * eu * eu);
+      const T odd = wr * (T(3) * eu);
+      const T fp = even + odd, fq = even - odd;
+      feq_moving += fp + fq;
+      io.store_at(i, vo, tau_one ? fp : f[i] - (f[i] - fp) * omega);
+      io.store_at(i + 1, vo, tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega);
+    }
+    const T feq0 = rho - feq_moving;
+    io.store_at(0, vo0, tau_one ? feq0 : f[0] - (f[0] - feq0) * omega);
+    if (test_rupture && bar) rupture_test<L, LH, LW, T>(a, ctl, step, bar, x, m, zc, c, sm.rho, sl, lm1, lx1);
+    const double keep = act ? 1.0 : 0.0;
+    acc_m += keep * (double)rho;
+    acc_x += keep * (double)jx;
+    acc_y += keep * (double)(L::HAS_M ? jm : jz);
+    acc_z += keep * (double)(L::HAS_M ? jz : T(0));
+  }
+
+  __device__ __forceinline__ void run() {
+    ctl = a.ctl;
+    step = ctl->steps;
+    io.init(a.buf[step & 1], a.buf[(step + 1) & 1], a.geo, a.buf_bytes);
+    int b = blockIdx.x;
+    const int nblk = gridDim.x;
+    if (a.xcd_chunks > 1) b = (b % a.xcd_chunks) * (nblk / a.xcd_chunks) + b / a.xcd_chunks;
+    const int tx = b % a.tiles_x;
+    const int t2 = b / a.tiles_x;
+    const int tm = t2 % a.tiles_m;
+    const int seg = t2 / a.tiles_m;
+    nx = a.nx;
+    nm = a.nm;
+    nz = a.nz;
+    x0 = tx * TX;
+    m0 = tm * TM;
+    z0 = seg * a.lz;
+    L_ = min(z0 + a.lz, nz) - z0;
+    TXe = min(TX, nx - x0);
+    TMe = min(TM, nm - m0);
+    const bool interior = (int)threadIdx.x < NI;
+    lx = threadIdx.x % TX;
+    lm = threadIdx.x / TX;
+    act = interior && lx < TXe && lm < TMe;
+    x = x0 + lx;
+    m = m0 + lm;
+    xc = min(x, nx - 1);
+    mc = min(m, nm - 1);
+    // halo ring, one lane of the halo waves per cell: two columns (lx = -1,
+    // TXe) over lm in [-HM, TMe - 1 + HM], then (3-D only) two rows (lm = -1,
+    // TMe) over lx in [0, TXe)
+    const int ncol = TMe + 2 * HM;
+    const int nh = 2 * ncol + (HM ? 2 * TXe : 0);
+    const int h = (int)threadIdx.x - NI;
+    has_halo = !interior && h < nh;
+    hx = 0;
+    hm = 0;
+    if (has_halo) {
+      if (h < 2 * ncol) {
+        hx = (h < ncol) ? -1 : TXe;
+        hm = (h < ncol ? h : h - ncol) - HM;
+      } else {
+        const int r2 = h - 2 * ncol;
+        hx = r2 < TXe ? r2 : r2 - TXe;
+        hm = r2 < TXe ? -1 : TMe;
+      }
+    }
+    gx = wrap_any(x0 + hx, nx);
+    gm = wrap_any(m0 + hm, nm);
+    G = (T)a.G;
+    rho0 = (T)a.rho0;
+    tau = (T)a.tau;
+    omega = T(1) / (T)a.tau;
+    tau_one = a.tau == 1.0;
+    film = a.film_on != 0;
+    test_rupture = film && step >= a.rupture_warmup;
+    psi_bar = (T)a.psi_bar;
+
+    if (interior) {
+      T r0[Q], r1[Q], r2[Q];
+      unsigned g0 = 0, g1 = 0, g2 = 0;
+      const int kend = L_ + 2;
+      for (int k = 0; k <= kend; k += 3) {
+        iter(k, r0, r1, g0, g1);
+        if (k + 1 > kend) break;
+        iter(k + 1, r1, r2, g1, g2);
+        if (k + 2 > kend) break;
+        iter(k + 2, r2, r0, g2, g0);
+      }
+    } else {
+      halo_loop();
+    }
+    epilogue(nblk);
+  }
+
+  // FP64 mass / momentum partials of the state entering this step; the last
+  // workgroup to finish forms the deterministic totals, applies the step's
+  // rupture unions and advances the step counter
+  __device__ __forceinline__ void epilogue(int nblk) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      acc_m += __shfl_down(acc_m, off, 64);
+      acc_x += __shfl_down(acc_x, off, 64);
+      acc_y += __shfl_down(acc_y, off, 64);
+      acc_z += __shfl_down(acc_z, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+      sm.red[wave][0] = acc_m;
+      sm.red[wave][1] = acc_x;
+      sm.red[wave][2] = acc_y;
+      sm.red[wave][3] = acc_z;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      double sum = 0.0;
+      for (int wv = 0; wv < NT / 64; wv++) sum += sm.red[wv][threadIdx.x];
+      a.partials[4ll * blockIdx.x + threadIdx.x] = sum;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) sm.last = (atomicAdd(&ctl->done, 1u) == (unsigned)nblk - 1) ? 1 : 0;
+    __syncthreads();
+    if (!sm.last) return;
+    __threadfence();
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int blk = threadIdx.x; blk < nblk; blk += NT)
+#pragma unroll
+      for (int q = 0; q < 4; q++) t[q] += a.partials[4ll * blk + q];
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) t[q] += __shfl_down(t[q], off, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < 4; q++) sm.red[wave][q] = t[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int wv = 0; wv < NT / 64; wv++)
+        for (int q = 0; q < 4; q++) tot[q] += sm.red[wv][q];
+      ctl->mass = tot[0];
+      ctl->mom[0] = tot[1];
+      ctl->mom[1] = tot[2];
+      ctl->mom[2] = tot[3];
+      if (!isfinite(tot[0])) ctl->failed = 1;
+      const unsigned e1 = min(ctl->ev_count, a.ev_cap);
+      bool any = false;
+      for (unsigned e = ctl->ev_start; e < e1; e++) {
+        any = true;
+        const int ra = uf_root(a.alias, (int)a.events[4ll * e + 1]);
+        const int rb = uf_root(a.alias, (int)a.events[4ll * e + 2]);
+        if (ra != rb) {
+          if (ra < rb) a.alias[rb] = ra;
+          else a.alias[ra] = rb;
+          ctl->n_ruptures += 1;
+        }
+      }
+      if (ctl->ev_count > e1) any = true;
+      ctl->ev_start = ctl->ev_count;
+      ctl->steps = step + 1;
+      if (any && a.on_rupture) ctl->stopped = 1;
+      ctl->done = 0;
+      __threadfence();
+    }
+  }
+};
+
+template <class L, class S, int TX, int TM, bool BUF>
+__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF>::NT)) void k_step(StepArgs a) {
+  using SB = StepBlock<L, S, TX, TM, BUF>;
+  __shared__ typename SB::Smem sm;
+  if (a.ctl->stopped) return;
+  SB blk(a, sm);
+  blk.run();
+}
+
+}  // namespace flb

@@ -1,0 +1,272 @@
+"""Thin ctypes binding of libfoamlbm.so (include/foamlbm.h).
+
+The flb_* functions here have the names and argument order of the C ABI and
+only marshal arguments; every step of the method runs in the HIP library.
+`Sim` is a convenience wrapper that takes device memory and the stream from
+PyTorch.  Importing this module fails loudly when the library is not built.
+"""
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libfoamlbm.so")
+
+FLB_OK, FLB_EINVAL, FLB_ENOMEM, FLB_ENUMERIC, FLB_EBUSY, FLB_EHIP, FLB_STOPPED = 0, -1, -2, -3, -4, -5, 1
+FLB_D2Q9, FLB_D3Q19 = 0, 1
+FLB_F64, FLB_F32, FLB_F16S = 0, 1, 2
+STORAGE = {"f64": FLB_F64, "f32": FLB_F32, "f16s": FLB_F16S}
+
+# direction vectors in the library's population order (lattice coordinates)
+DIRECTIONS = {
+    FLB_D2Q9: np.array([(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1), (1, -1), (-1, 1)]),
+    FLB_D3Q19: np.array([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+                         (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1),
+                         (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]),
+}
+
+
+class flb_params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int32), ("storage", C.c_int32),
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("tau", C.c_double), ("G", C.c_double), ("rho0", C.c_double),
+        ("rho_liquid", C.c_double), ("rho_gas", C.c_double), ("noise_amp", C.c_double),
+        ("seed", C.c_uint64),
+        ("film_on", C.c_int32), ("k_own", C.c_int32), ("zone_width", C.c_int32),
+        ("rho_th", C.c_double),
+        ("psi_bar_mode", C.c_int32), ("rupture_warmup", C.c_int32),
+        ("on_rupture", C.c_int32), ("velocity_mode", C.c_int32),
+    ]
+
+
+class flb_nucleus(C.Structure):
+    _fields_ = [("x", C.c_double), ("y", C.c_double), ("z", C.c_double), ("r", C.c_double)]
+
+
+class flb_stats(C.Structure):
+    _fields_ = [("mass", C.c_double), ("mom", C.c_double * 3), ("step", C.c_int64),
+                ("n_bubbles", C.c_int32), ("n_ruptures", C.c_int32), ("stopped", C.c_int32),
+                ("events_lost", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class flb_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"libfoamlbm.so is not built at {LIBPATH}; run __graft_entry__.build() "
+                      "(or python paper_1708_01613_amd/build.py)")
+_lib = C.CDLL(LIBPATH)
+
+_D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_I = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_U = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_L = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_CTX = C.c_void_p
+
+_SIGS = {
+    "flb_default_params": (None, [C.POINTER(flb_params)]),
+    "flb_create": (C.c_int, [C.POINTER(flb_params), C.POINTER(flb_allocator), C.c_void_p, C.POINTER(_CTX)]),
+    "flb_set_nuclei": (C.c_int, [_CTX, C.POINTER(flb_nucleus), C.c_int32]),
+    "flb_step": (C.c_int, [_CTX, C.c_int64]),
+    "flb_get_density": (C.c_int, [_CTX, _D, C.c_size_t]),
+    "flb_get_velocity": (C.c_int, [_CTX, _D, C.c_size_t]),
+    "flb_get_populations": (C.c_int, [_CTX, _D, C.c_size_t]),
+    "flb_set_populations": (C.c_int, [_CTX, _D, C.c_size_t]),
+    "flb_get_stats": (C.c_int, [_CTX, C.POINTER(flb_stats)]),
+    "flb_get_labels": (C.c_int, [_CTX, _I, C.c_size_t, C.POINTER(C.c_int32)]),
+    "flb_label_field": (C.c_int, [_CTX, _D, C.c_size_t, _I, C.POINTER(C.c_int32)]),
+    "flb_get_maps": (C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
+    "flb_get_histogram": (C.c_int, [_CTX, C.c_int32, C.c_double, _L, C.POINTER(C.c_int32)]),
+    "flb_get_rupture_events": (C.c_int, [_CTX, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
+    "flb_set_tuning": (C.c_int, [_CTX, C.c_int32, C.c_int32, C.c_int32]),
+    "flb_get_tuning": (C.c_int, [_CTX] + [C.POINTER(C.c_int32)] * 6),
+    "flb_time_steps": (C.c_int, [_CTX, C.c_int64, C.c_int32, C.POINTER(C.c_double)]),
+    "flb_destroy": (None, [_CTX]),
+    "flb_last_error": (C.c_char_p, []),
+}
+EXPORTED = tuple(_SIGS)
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+
+class FlbError(RuntimeError):
+    def __init__(self, code, what):
+        msg = flb_last_error().decode(errors="replace")
+        super().__init__(f"{what} failed with {code}: {msg}")
+        self.code = code
+
+
+def check(code, what):
+    if code < 0:
+        raise FlbError(code, what)
+    return code
+
+
+def default_params(**kw):
+    p = flb_params()
+    flb_default_params(C.byref(p))
+    for k, v in kw.items():
+        if k == "storage" and isinstance(v, str):
+            v = STORAGE[v]
+        if not hasattr(p, k):
+            raise KeyError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    if p.lattice == FLB_D2Q9:
+        p.nz = 1
+    return p
+
+
+def _torch_allocator(device_index):
+    """Device memory from PyTorch's caching allocator, on the current stream."""
+    import torch
+
+    def _alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device_index,
+                                                      torch.cuda.current_stream(device_index))
+        except Exception:
+            return None
+
+    def _free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+    return flb_allocator(fa, ff, None), (fa, ff)
+
+
+class Sim:
+    """One lattice on the GPU.  Arrays are x-fastest: (ny, nx) or (nz, ny, nx)."""
+
+    def __init__(self, stream=None, use_torch_memory=True, **params):
+        import torch
+
+        self.params = default_params(**params)
+        p = self.params
+        self.D = 2 if p.lattice == FLB_D2Q9 else 3
+        self.Q = 9 if self.D == 2 else 19
+        self.N = p.nx * p.ny * p.nz
+        self.shape = (p.ny, p.nx) if self.D == 2 else (p.nz, p.ny, p.nx)
+        dev = torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._keep = None
+        alloc = None
+        if use_torch_memory:
+            al, self._keep = _torch_allocator(dev)
+            alloc = C.byref(al)
+            self._al = al
+        h = _CTX()
+        check(flb_create(C.byref(p), alloc, C.c_void_p(self.stream.cuda_stream), C.byref(h)), "flb_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            flb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_nuclei(self, nuclei):
+        arr = np.asarray(nuclei, np.float64).reshape(-1, 4)
+        n = arr.shape[0]
+        buf = (flb_nucleus * max(n, 1))()
+        for k in range(n):
+            buf[k] = flb_nucleus(*arr[k])
+        check(flb_set_nuclei(self.h, buf, n), "flb_set_nuclei")
+        return self
+
+    def step(self, n=1):
+        return check(flb_step(self.h, int(n)), "flb_step")
+
+    def density(self):
+        out = np.empty(self.N, np.float64)
+        check(flb_get_density(self.h, out, out.size), "flb_get_density")
+        return out.reshape(self.shape)
+
+    def velocity(self):
+        out = np.empty(self.D * self.N, np.float64)
+        check(flb_get_velocity(self.h, out, out.size), "flb_get_velocity")
+        return out.reshape((self.D,) + self.shape)
+
+    def populations(self):
+        out = np.empty(self.Q * self.N, np.float64)
+        check(flb_get_populations(self.h, out, out.size), "flb_get_populations")
+        return out.reshape((self.Q,) + self.shape)
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(np.asarray(f, np.float64).reshape(-1))
+        check(flb_set_populations(self.h, f, f.size), "flb_set_populations")
+
+    def labels(self):
+        out = np.empty(self.N, np.int32)
+        nb = C.c_int32(0)
+        check(flb_get_labels(self.h, out, out.size, C.byref(nb)), "flb_get_labels")
+        return out.reshape(self.shape), nb.value
+
+    def label_field(self, rho):
+        rho = np.ascontiguousarray(np.asarray(rho, np.float64).reshape(-1))
+        out = np.empty(self.N, np.int32)
+        nb = C.c_int32(0)
+        check(flb_label_field(self.h, rho, rho.size, out, C.byref(nb)), "flb_label_field")
+        return out.reshape(self.shape), nb.value
+
+    def maps(self):
+        arrs = {k: np.empty(self.N, np.int32) for k in ("label", "owner", "owner2", "dist")}
+        mask = np.empty(self.N, np.uint32)
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        check(flb_get_maps(self.h, ptr(arrs["label"]), ptr(arrs["owner"]), ptr(arrs["owner2"]),
+                           ptr(arrs["dist"]), ptr(mask), self.N), "flb_get_maps")
+        out = {k: v.reshape(self.shape) for k, v in arrs.items()}
+        out["mask"] = mask.reshape(self.shape)
+        return out
+
+    def histogram(self, nbins, bin_width):
+        counts = np.empty(nbins, np.int64)
+        nb = C.c_int32(0)
+        check(flb_get_histogram(self.h, nbins, float(bin_width), counts, C.byref(nb)), "flb_get_histogram")
+        return counts, nb.value
+
+    def rupture_events(self):
+        n = C.c_int64(0)
+        check(flb_get_rupture_events(self.h, None, 0, C.byref(n)), "flb_get_rupture_events")
+        out = np.zeros(3 * max(n.value, 1), np.int64)
+        check(flb_get_rupture_events(self.h, out.ctypes.data_as(C.c_void_p), n.value, C.byref(n)),
+              "flb_get_rupture_events")
+        return out[: 3 * min(n.value, out.size // 3)].reshape(-1, 3)
+
+    def set_tuning(self, tile=-1, lz=0, xcd=-1):
+        check(flb_set_tuning(self.h, tile, lz, xcd), "flb_set_tuning")
+
+    def tuning(self):
+        v = [C.c_int32(0) for _ in range(6)]
+        check(flb_get_tuning(self.h, *[C.byref(x) for x in v]), "flb_get_tuning")
+        return dict(zip(("tile", "lz", "xcd", "n_tiles", "tile_x", "tile_m"), (x.value for x in v)))
+
+    def time_steps(self, n, refresh=True):
+        ms = C.c_double(0.0)
+        check(flb_time_steps(self.h, int(n), int(bool(refresh)), C.byref(ms)), "flb_time_steps")
+        return ms.value
+
+    def stats(self):
+        s = flb_stats()
+        check(flb_get_stats(self.h, C.byref(s)), "flb_get_stats")
+        return dict(mass=s.mass, mom=np.array(list(s.mom)), step=s.step, n_bubbles=s.n_bubbles,
+                    n_ruptures=s.n_ruptures, stopped=bool(s.stopped), events_lost=s.events_lost)
+
+
+def psi_liquid(rho_liquid, rho0=1.0):
+    return rho0 * (1.0 - math.exp(-rho_liquid / rho0))

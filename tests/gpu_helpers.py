@@ -1,0 +1,30 @@
+"""Shared helpers of the GPU parity tests (no method arithmetic here)."""
+import numpy as np
+
+from oracle import OracleSim, lattice
+
+
+def oracle_order(kind, gpu_dirs):
+    """Index array mapping the oracle's direction order onto the library's."""
+    e, _ = lattice(kind)
+    D = 2 if kind == 0 else 3
+    return np.array([next(i for i in range(len(e)) if tuple(e[i][:D]) == tuple(v)) for v in gpu_dirs])
+
+
+def oracle_for(params, nuclei):
+    """An oracle run with the same problem definition as a GPU run."""
+    keys = ("lattice", "nx", "ny", "nz", "tau", "G", "rho0", "rho_liquid", "rho_gas", "noise_amp", "seed",
+            "film_on", "k_own", "zone_width", "rho_th", "psi_bar_mode", "rupture_warmup", "on_rupture",
+            "velocity_mode")
+    kw = {k: params[k] for k in keys if k in params}
+    s = OracleSim(**kw)
+    s.set_nuclei(nuclei)
+    return s
+
+
+def max_rel(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def vel_err(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
