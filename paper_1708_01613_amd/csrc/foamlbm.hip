@@ -13,6 +13,7 @@
 
 #include "../../include/foamlbm.h"
 #include "ops.hpp"
+#include "twopass.hpp"
 
 using namespace flb;
 
@@ -51,20 +52,45 @@ void launch_step(const StepArgs& a, int nblk, hipStream_t s) {
                        a);
 }
 
+// two-pass path: k_psi then k_collide
+template <class L, class S>
+void launch_psi(const StepArgs& a, int nblk, hipStream_t s) {
+  if (a.buf_bytes < kBufPathLimit)
+    hipLaunchKernelGGL((k_psi<L, S, true>), dim3(nblk), dim3(TP_NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_psi<L, S, false>), dim3(nblk), dim3(TP_NT), 0, s, a);
+}
+template <class L, class S>
+void launch_collide(const StepArgs& a, int nblk, hipStream_t s) {
+  if (a.buf_bytes < kBufPathLimit)
+    hipLaunchKernelGGL((k_collide<L, S, true>), dim3(nblk), dim3(TP_NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_collide<L, S, false>), dim3(nblk), dim3(TP_NT), 0, s, a);
+}
+
+// step variants: z-march tiles (tx, tm) or the two-pass path (tx = tm = 0)
 struct TileCfg {
   int tx, tm;
-  StepFn fn[3];  // per storage F64, F32, F16S
+  StepFn fn[3];    // z-march kernel, or k_psi, per storage F64, F32, F16S
+  StepFn coll[3];  // k_collide of the two-pass path
 };
 
 template <class L, int TX, int TM>
 constexpr TileCfg make_tile() {
-  return TileCfg{TX, TM, {&launch_step<L, SF64, TX, TM>, &launch_step<L, SF32, TX, TM>,
-                          &launch_step<L, SF16S, TX, TM>}};
+  return TileCfg{TX, TM,
+                 {&launch_step<L, SF64, TX, TM>, &launch_step<L, SF32, TX, TM>, &launch_step<L, SF16S, TX, TM>},
+                 {nullptr, nullptr, nullptr}};
+}
+template <class L>
+constexpr TileCfg make_two_pass() {
+  return TileCfg{0, 0, {&launch_psi<L, SF64>, &launch_psi<L, SF32>, &launch_psi<L, SF16S>},
+                 {&launch_collide<L, SF64>, &launch_collide<L, SF32>, &launch_collide<L, SF16S>}};
 }
 
-const TileCfg kTiles2[] = {make_tile<D2Q9K, 64, 1>(), make_tile<D2Q9K, 128, 1>(), make_tile<D2Q9K, 256, 1>()};
+const TileCfg kTiles2[] = {make_tile<D2Q9K, 64, 1>(), make_tile<D2Q9K, 128, 1>(), make_tile<D2Q9K, 256, 1>(),
+                           make_two_pass<D2Q9K>()};
 const TileCfg kTiles3[] = {make_tile<D3Q19K, 64, 4>(), make_tile<D3Q19K, 64, 8>(), make_tile<D3Q19K, 32, 8>(),
-                           make_tile<D3Q19K, 128, 4>()};
+                           make_tile<D3Q19K, 128, 4>(), make_two_pass<D3Q19K>()};
 constexpr int kNTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
 constexpr int kNTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
 
@@ -90,6 +116,8 @@ struct flb_ctx {
   Ctl* qctl = nullptr;     // always-zero control for query pipelines
   double* partials = nullptr;
   int max_blk = 0;
+  void* psi = nullptr;     // two-pass path: psi and rho arrays (compute type)
+  void* rho = nullptr;
   // tuning
   int tile = -1, lz = 0, xcd = 0;
   // film maps
@@ -137,9 +165,13 @@ struct flb_ctx {
     allocs.clear();
   }
   const TileCfg& tcfg() const { return D == 2 ? kTiles2[tile] : kTiles3[tile]; }
-  int tiles_x() const { return (md.nx + tcfg().tx - 1) / tcfg().tx; }
-  int tiles_m() const { return (md.nm + tcfg().tm - 1) / tcfg().tm; }
-  int nblocks() const { return tiles_x() * tiles_m() * ((md.nz + lz - 1) / lz); }
+  bool two_pass() const { return tcfg().tx == 0; }
+  int tiles_x() const { return two_pass() ? 1 : (md.nx + tcfg().tx - 1) / tcfg().tx; }
+  int tiles_m() const { return two_pass() ? 1 : (md.nm + tcfg().tm - 1) / tcfg().tm; }
+  int nblocks() const {
+    if (two_pass()) return geo.nxb * (int)((md.nm * (long long)md.nz + TP_ROWS - 1) / TP_ROWS);
+    return tiles_x() * tiles_m() * ((md.nz + lz - 1) / lz);
+  }
 };
 
 namespace {
@@ -185,15 +217,21 @@ StepArgs step_args(flb_ctx* c) {
   a.ctl = c->ctl;
   a.partials = c->partials;
   a.buf_bytes = c->fbytes;
+  a.psi = c->psi;
+  a.rho = c->rho;
   return a;
 }
 
 // ---- labels of the current state (or of a density field) into `label` ----
 template <class L, class S>
-int label_pipeline(flb_ctx* c, const Ctl* gate, int* total, int* label, const double* field) {
+int label_pipeline(flb_ctx* c, const Ctl* gate, int* total, int* label, const double* field,
+                   bool from_rho = false) {
   const int B = 256, g = grid_for(c->N, B);
   if (field)
     hipLaunchKernelGGL(k_gas_from_field, dim3(g), dim3(B), 0, c->st, field, c->md, c->p.rho_th, c->par);
+  else if (from_rho)
+    hipLaunchKernelGGL((k_gas_from_rho<typename S::ct>), dim3(g), dim3(B), 0, c->st, gate,
+                       (const typename S::ct*)c->rho, c->md, c->p.rho_th, c->par);
   else
     hipLaunchKernelGGL((k_gas_init<L, S>), dim3(g), dim3(B), 0, c->st, c->f[0], c->f[1], gate, c->geo, c->md,
                        c->p.rho_th, c->par);
@@ -211,7 +249,7 @@ int label_pipeline(flb_ctx* c, const Ctl* gate, int* total, int* label, const do
 
 // ---- film-map refresh before a step ----
 template <class L, class S>
-int refresh_maps(flb_ctx* c) {
+int refresh_maps(flb_ctx* c, bool from_rho) {
   const int B = 256, g = grid_for(c->N, B);
   const int gl = grid_for(c->N + 1, B);
   const Ctl* gate = c->ctl;
@@ -219,7 +257,7 @@ int refresh_maps(flb_ctx* c) {
     hipLaunchKernelGGL(k_copy_int, dim3(g), dim3(B), 0, c->st, gate, c->label, c->label_old, c->N);
     hipLaunchKernelGGL(k_copy_int, dim3(gl), dim3(B), 0, c->st, gate, c->alias, c->alias_old, c->N + 1);
   }
-  int rc = label_pipeline<L, S>(c, gate, &c->ctl->n_bubbles, c->label, nullptr);
+  int rc = label_pipeline<L, S>(c, gate, &c->ctl->n_bubbles, c->label, nullptr, from_rho);
   if (rc) return rc;
   hipLaunchKernelGGL(k_owner_init, dim3(g), dim3(B), 0, c->st, gate, c->md, c->label, c->own, c->dist);
   for (int layer = 1; layer <= c->p.zone_width - 1; layer++)
@@ -234,6 +272,7 @@ int refresh_maps(flb_ctx* c) {
   }
   hipLaunchKernelGGL((k_masks<L>), dim3(g), dim3(B), 0, c->st, gate, c->md, c->p.zone_width, c->own, c->dist,
                      c->alias, c->flag, c->mask);
+  hipLaunchKernelGGL(k_masks_done, dim3(1), dim3(64), 0, c->st, c->ctl);
   HIPCHK(hipGetLastError());
   c->maps_seen = true;
   return FLB_OK;
@@ -244,12 +283,24 @@ int do_steps(flb_ctx* c, int64_t nsteps, bool refresh) {
   const StepArgs a = step_args(c);
   const int nblk = c->nblocks();
   const StepFn fn = c->tcfg().fn[c->p.storage];
+  const StepFn coll = c->tcfg().coll[c->p.storage];
   for (int64_t s = 0; s < nsteps; s++) {
-    if (refresh && c->p.film_on && c->launched % c->p.k_own == 0) {
-      int rc = refresh_maps<L, S>(c);
-      if (rc) return rc;
+    const bool due = refresh && c->p.film_on && c->launched % c->p.k_own == 0;
+    if (coll) {
+      fn(a, nblk, c->st);  // rho / psi of the current state
+      if (due) {
+        int rc = refresh_maps<L, S>(c, true);
+        if (rc) return rc;
+      }
+      coll(a, nblk, c->st);
+    } else {
+      if (due) {
+        int rc = refresh_maps<L, S>(c, false);
+        if (rc) return rc;
+      }
+      fn(a, nblk, c->st);
     }
-    fn(a, nblk, c->st);
+    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(FIN_NT), 0, c->st, a, nblk);
     c->launched++;
   }
   HIPCHK(hipGetLastError());
@@ -398,6 +449,11 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
   ok = ok && (c->ctl = (Ctl*)c->dalloc(sizeof(Ctl)));
   ok = ok && (c->qctl = (Ctl*)c->dalloc(sizeof(Ctl)));
   ok = ok && (c->partials = (double*)c->dalloc(sizeof(double) * 4 * (size_t)c->max_blk));
+  {
+    const size_t tsz = p->storage == FLB_F64 ? 8 : 4;
+    ok = ok && (c->psi = c->dalloc(tsz * (size_t)c->N));
+    ok = ok && (c->rho = c->dalloc(tsz * (size_t)c->N));
+  }
   ok = ok && (c->qd = (double*)c->dalloc(sizeof(double) * 4 * (size_t)c->N));
   ok = ok && (c->qtot = (double*)c->dalloc(sizeof(double) * 4 * 4096));
   ok = ok && (c->par = (int*)c->dalloc(sizeof(int) * (size_t)c->N));
@@ -425,6 +481,7 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
   if (hipMemsetAsync(c->ctl, 0, sizeof(Ctl), c->st) != hipSuccess ||
       hipMemsetAsync(c->qctl, 0, sizeof(Ctl), c->st) != hipSuccess ||
       (p->film_on && hipMemsetAsync(c->flag, 0, (size_t)c->N, c->st) != hipSuccess) ||
+      (p->film_on && hipMemsetAsync(c->mask, 0, sizeof(uint32_t) * (size_t)c->N, c->st) != hipSuccess) ||
       hipStreamSynchronize(c->st) != hipSuccess) {
     c->dfree_all();
     delete c;
@@ -468,7 +525,10 @@ int flb_set_nuclei(flb_ctx* c, const flb_nucleus* nuc, int32_t n) {
   }
   c->launched = 0;
   c->maps_seen = false;
-  if (c->p.film_on) HIPCHK(hipMemsetAsync(c->flag, 0, (size_t)c->N, c->st));
+  if (c->p.film_on) {
+    HIPCHK(hipMemsetAsync(c->flag, 0, (size_t)c->N, c->st));
+    HIPCHK(hipMemsetAsync(c->mask, 0, sizeof(uint32_t) * (size_t)c->N, c->st));
+  }
   return FLB_OK;
 }
 

@@ -120,6 +120,7 @@ struct Ctl {
   long long n_ruptures; // successful barrier removals
   int failed;           // 1 once the FP64 mass reduction saw a non-finite value
   int n_bubbles;        // labels in the current film maps
+  int alias_dirty;      // 1 if a rupture united bubbles since the masks were built
   double mass, mom[3];  // FP64 totals of the state entering the last step
 };
 

@@ -306,4 +306,9 @@ __global__ void k_masks(const Ctl* ctl, MapDims d, int zone_width, const int2* o
   }
 }
 
+// the masks just built reflect the current aliases
+__global__ void k_masks_done(Ctl* ctl) {
+  if (!ctl->stopped && threadIdx.x == 0) ctl->alias_dirty = 0;
+}
+
 }  // namespace flb

@@ -40,6 +40,8 @@ struct StepArgs {
   unsigned ev_cap;
   Ctl* ctl;
   double* partials;      // 4 doubles per workgroup
+  void* psi;             // two-pass path: psi and rho of the current state,
+  void* rho;             // compute type, cell-linear
 };
 
 __device__ __forceinline__ int wrap_dec(int a, int n) { return a == 0 ? n - 1 : a - 1; }
@@ -222,6 +224,96 @@ struct PopIO {
   }
 };
 
+// FP64 mass / momentum partials of the state entering a step: every
+// workgroup reduces its lanes' partials and writes them to its slot.
+template <int NT>
+__device__ __forceinline__ void step_partials(const StepArgs& a, double (&red)[NT / 64][4], double acc_m,
+                                              double acc_x, double acc_y, double acc_z) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    acc_m += __shfl_down(acc_m, off, 64);
+    acc_x += __shfl_down(acc_x, off, 64);
+    acc_y += __shfl_down(acc_y, off, 64);
+    acc_z += __shfl_down(acc_z, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wave][0] = acc_m;
+    red[wave][1] = acc_x;
+    red[wave][2] = acc_y;
+    red[wave][3] = acc_z;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double sum = 0.0;
+    for (int wv = 0; wv < NT / 64; wv++) sum += red[wv][threadIdx.x];
+    a.partials[4ll * blockIdx.x + threadIdx.x] = sum;
+  }
+}
+
+// One workgroup, launched after every step kernel on the same stream (the
+// kernel boundary orders it after all partials and rupture events): totals
+// in workgroup order (deterministic), non-finite check, the step's rupture
+// unions, the stop flag, and the step counter that selects the A/B buffer.
+constexpr int FIN_NT = 1024;
+__global__ __launch_bounds__(FIN_NT) void k_step_finish(StepArgs a, int nblk) {
+  Ctl* ctl = a.ctl;
+  if (ctl->stopped) return;
+  __shared__ double red[FIN_NT / 64][4];
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  // thread t adds workgroups t, t + FIN_NT, ... in that order; four rows are
+  // loaded ahead of their additions to keep loads in flight
+  const double4* part = (const double4*)a.partials;
+  int blk = threadIdx.x;
+  for (; blk + 3 * FIN_NT < nblk; blk += 4 * FIN_NT) {
+    const double4 v0 = part[blk], v1 = part[blk + FIN_NT], v2 = part[blk + 2 * FIN_NT], v3 = part[blk + 3 * FIN_NT];
+    t[0] += v0.x; t[1] += v0.y; t[2] += v0.z; t[3] += v0.w;
+    t[0] += v1.x; t[1] += v1.y; t[2] += v1.z; t[3] += v1.w;
+    t[0] += v2.x; t[1] += v2.y; t[2] += v2.z; t[3] += v2.w;
+    t[0] += v3.x; t[1] += v3.y; t[2] += v3.z; t[3] += v3.w;
+  }
+  for (; blk < nblk; blk += FIN_NT) {
+    const double4 v = part[blk];
+    t[0] += v.x; t[1] += v.y; t[2] += v.z; t[3] += v.w;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; q++)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t[q] += __shfl_down(t[q], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < 4; q++) red[wave][q] = t[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int wv = 0; wv < FIN_NT / 64; wv++)
+      for (int q = 0; q < 4; q++) tot[q] += red[wv][q];
+    ctl->mass = tot[0];
+    ctl->mom[0] = tot[1];
+    ctl->mom[1] = tot[2];
+    ctl->mom[2] = tot[3];
+    if (!isfinite(tot[0])) ctl->failed = 1;
+    const unsigned e1 = min(ctl->ev_count, a.ev_cap);
+    bool any = false;
+    for (unsigned e = ctl->ev_start; e < e1; e++) {
+      any = true;
+      const int ra = uf_root(a.alias, (int)a.events[4ll * e + 1]);
+      const int rb = uf_root(a.alias, (int)a.events[4ll * e + 2]);
+      if (ra != rb) {
+        if (ra < rb) a.alias[rb] = ra;
+        else a.alias[ra] = rb;
+        ctl->n_ruptures += 1;
+        ctl->alias_dirty = 1;
+      }
+    }
+    if (ctl->ev_count > e1) any = true;
+    ctl->ev_start = ctl->ev_count;
+    ctl->steps = ctl->steps + 1;
+    if (any && a.on_rupture) ctl->stopped = 1;
+  }
+}
+
 // Plane loop: iteration k loads plane z0-1+k (k <= L+1) into one register
 // set, collides plane z0+k-3 (k >= 3) from the set loaded two iterations
 // earlier while the new loads are in flight, then stores rho / psi of the new
@@ -253,7 +345,7 @@ struct StepBlock {
   Ctl* ctl;
   long long step;
   int nx, nm, nz, x0, m0, z0, L_, TXe, TMe, lx, lm, x, m, xc, mc, gx, gm, hx, hm;
-  bool act, has_halo, film, test_rupture, tau_one;
+  bool act, has_halo, film, test_rupture, tau_one, alias_dirty;
   T G, rho0, tau, omega, psi_bar;
   double acc_m = 0.0, acc_x = 0.0, acc_y = 0.0, acc_z = 0.0;
 
@@ -269,7 +361,7 @@ struct StepBlock {
       // from the collide that overlaps them; the film flag is read first so
       // the wait that ends this iteration covers it too
       const int zl = wrap_any(z0 - 1 + k, nz);
-      if (film) fl_ld = (unsigned)a.flag[(unsigned)(xc + nx * (mc + nm * zl))];
+      if (film) fl_ld = a.mask[(unsigned)(xc + nx * (mc + nm * zl))];
       io.pull(xc, mc, zl, ld);
     }
     // keep the collide between the loads and their first use
@@ -333,7 +425,9 @@ struct StepBlock {
     const int lm1 = lm + HM, lx1 = lx + 1;
     const T psic = sm.psi[sl[1]][lm1][lx1];
     unsigned bar = 0;
-    if (flag) bar = active_links<L>(a, x, m, zc, c);
+    // candidate links of the last refresh are exact until a rupture unites
+    // two bubbles; only then are aliases resolved link by link
+    if (flag) bar = alias_dirty ? active_links<L>(a, x, m, zc, c) : flag;
     const T pbar = a.psi_bar_mode == 0 ? psi_bar : psic;
     T fx = T(0), fm = T(0), fz = T(0);
 #pragma unroll
@@ -443,6 +537,7 @@ struct StepBlock {
     omega = T(1) / (T)a.tau;
     tau_one = a.tau == 1.0;
     film = a.film_on != 0;
+    alias_dirty = film && ctl->alias_dirty != 0;
     test_rupture = film && step >= a.rupture_warmup;
     psi_bar = (T)a.psi_bar;
 
@@ -463,77 +558,7 @@ struct StepBlock {
     epilogue(nblk);
   }
 
-  // FP64 mass / momentum partials of the state entering this step; the last
-  // workgroup to finish forms the deterministic totals, applies the step's
-  // rupture unions and advances the step counter
-  __device__ __forceinline__ void epilogue(int nblk) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      acc_m += __shfl_down(acc_m, off, 64);
-      acc_x += __shfl_down(acc_x, off, 64);
-      acc_y += __shfl_down(acc_y, off, 64);
-      acc_z += __shfl_down(acc_z, off, 64);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-      sm.red[wave][0] = acc_m;
-      sm.red[wave][1] = acc_x;
-      sm.red[wave][2] = acc_y;
-      sm.red[wave][3] = acc_z;
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-      double sum = 0.0;
-      for (int wv = 0; wv < NT / 64; wv++) sum += sm.red[wv][threadIdx.x];
-      a.partials[4ll * blockIdx.x + threadIdx.x] = sum;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) sm.last = (atomicAdd(&ctl->done, 1u) == (unsigned)nblk - 1) ? 1 : 0;
-    __syncthreads();
-    if (!sm.last) return;
-    __threadfence();
-    double t[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int blk = threadIdx.x; blk < nblk; blk += NT)
-#pragma unroll
-      for (int q = 0; q < 4; q++) t[q] += a.partials[4ll * blk + q];
-#pragma unroll
-    for (int q = 0; q < 4; q++)
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) t[q] += __shfl_down(t[q], off, 64);
-    if (lane == 0)
-#pragma unroll
-      for (int q = 0; q < 4; q++) sm.red[wave][q] = t[q];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double tot[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int wv = 0; wv < NT / 64; wv++)
-        for (int q = 0; q < 4; q++) tot[q] += sm.red[wv][q];
-      ctl->mass = tot[0];
-      ctl->mom[0] = tot[1];
-      ctl->mom[1] = tot[2];
-      ctl->mom[2] = tot[3];
-      if (!isfinite(tot[0])) ctl->failed = 1;
-      const unsigned e1 = min(ctl->ev_count, a.ev_cap);
-      bool any = false;
-      for (unsigned e = ctl->ev_start; e < e1; e++) {
-        any = true;
-        const int ra = uf_root(a.alias, (int)a.events[4ll * e + 1]);
-        const int rb = uf_root(a.alias, (int)a.events[4ll * e + 2]);
-        if (ra != rb) {
-          if (ra < rb) a.alias[rb] = ra;
-          else a.alias[ra] = rb;
-          ctl->n_ruptures += 1;
-        }
-      }
-      if (ctl->ev_count > e1) any = true;
-      ctl->ev_start = ctl->ev_count;
-      ctl->steps = step + 1;
-      if (any && a.on_rupture) ctl->stopped = 1;
-      ctl->done = 0;
-      __threadfence();
-    }
-  }
+  __device__ __forceinline__ void epilogue(int) { step_partials<NT>(a, sm.red, acc_m, acc_x, acc_y, acc_z); }
 };
 
 template <class L, class S, int TX, int TM, bool BUF>
