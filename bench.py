@@ -21,6 +21,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 # algorithmic bytes per lattice update: read Q*s + write Q*s + 1 flag byte
+# (the kernel reads a 4-byte barrier mask instead of the flag byte: 156 B)
+DESIGN_BYTES = 156
 BYTES_PER_UPDATE = {("d3q19", "f32"): 153, ("d3q19", "f16s"): 77, ("d3q19", "f64"): 305,
                     ("d2q9", "f32"): 73, ("d2q9", "f16s"): 37, ("d2q9", "f64"): 145}
 
@@ -29,26 +31,46 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(seconds_hint=20.0):
-    """The FP64 oracle on host cores over a bounded sample of the same workload:
-    a 96^3 box with the same nucleus density, film on, 10 steps (one map refresh)."""
+def cpu_baseline(steps=10):
+    """The FP64 oracle on the host cores over a bounded sample of the same
+    workload: the same 256^3 lattice and nuclei, film on, the first `steps`
+    steps (including the map refresh at step 0)."""
     from oracle import OracleSim
     from paper_1708_01613_amd import inputs
 
-    n = 96
-    params, nuc, _ = inputs.config_foam3d("f32", n=n)
+    params, nuc, _ = inputs.config_foam3d("f32")
+    n = params["nx"]
     kw = {k: params[k] for k in ("lattice", "nx", "ny", "nz", "tau", "G", "rho0", "rho_liquid", "rho_gas",
                                  "noise_amp", "seed", "film_on")}
     s = OracleSim(**kw, k_own=10, zone_width=6, rupture_warmup=200)
     s.set_nuclei(nuc)
-    steps = 10
     t0 = time.perf_counter()
     s.step(steps)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = s.threads()
+    del s
     return {"value": round(n ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"D3Q19 {n}^3 FP64 oracle, {len(nuc)} nuclei (same density), film on, {steps} steps "
-                      f"incl. one map refresh, {dt:.1f} s"}
+            "sample": f"D3Q19 {n}^3 FP64 oracle, the same {len(nuc)} nuclei, film on, first {steps} steps "
+                      f"incl. one map refresh, {dt:.1f} s on {threads} OpenMP threads"}
+
+
+def copy_ceiling(torch, nbytes=1 << 30, reps=20):
+    """Device-to-device copy rate (read + write bytes / time) of a 1 GiB
+    buffer: the practical HBM ceiling the stencil is compared with."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def main():
@@ -93,14 +115,17 @@ def main():
     mlups = N * args.steps / wall / 1e6
     log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.3f} ms/step, {mlups:.0f} MLUPS")
 
-    # dominant kernel alone (maps frozen), HIP events on the library stream
+    # dominant kernel alone: every step-kernel launch bracketed by HIP events
+    # on the library's stream (maps frozen, so no refresh runs in between)
     nk = max(20, min(200, args.steps))
-    kms = sim.time_steps(nk, refresh=False) / nk
+    _, ksum = sim.time_steps(nk, refresh=False, kernel=True)
+    kms = ksum / nk
     bpu = BYTES_PER_UPDATE[("d3q19", "f32")]
     achieved = bpu * N / (kms * 1e-3) / 1e9
     log(f"step kernel {kms:.4f} ms, {achieved:.0f} GB/s algorithmic")
     st = sim.stats()
-
+    copy = copy_ceiling(torch)
+    log(f"device copy ceiling {copy:.0f} GB/s")
     # FP16-shifted storage variant of the same workload (kernel time only)
     variants = {}
     try:
@@ -110,7 +135,7 @@ def main():
         s16 = foamlbm.Sim(**p16)
         s16.set_nuclei(nuc)
         s16.step(10)
-        ms16 = s16.time_steps(nk, refresh=False) / nk
+        ms16 = s16.time_steps(nk, refresh=False, kernel=True)[1] / nk
         variants["d3q19_f16s_kernel"] = {"ms": round(ms16, 4), "MLUPS": round(N / (ms16 * 1e-3) / 1e6, 1),
                                          "GBs_algorithmic": round(77 * N / (ms16 * 1e-3) / 1e9, 1)}
         del s16
@@ -137,8 +162,9 @@ def main():
                    "cells": N, "tuning": tun},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_step<D3Q19K,SF32>", "kernel_ms": round(kms, 4),
-                     "bytes_per_update": bpu},
+                     "kernel": "k_step<D3Q19K,SF32,64,8>", "kernel_ms": round(kms, 4),
+                     "bytes_per_update": bpu, "design_bytes_per_update": DESIGN_BYTES,
+                     "copy_ceiling_GBs": round(copy, 1), "frac_of_copy": round(achieved / copy, 4)},
         "cpu_baseline": cpu,
         "variants": variants,
         "checks": {"mass": st["mass"], "n_bubbles": st["n_bubbles"], "n_ruptures": st["n_ruptures"],

@@ -94,6 +94,11 @@ typedef struct {
   int32_t rupture_warmup;/* first step at which the rupture test runs */
   int32_t on_rupture;    /* 0: remove the pair's barrier and continue; 1: stop after the step */
   int32_t velocity_mode; /* flb_get_velocity: 0 = j/rho, 1 = (j + F/2)/rho */
+  int32_t rupture_filter; /* FP32/FP16S storage: 1 (default) skips the FP64
+                             evaluation of the rupture test where an FP32
+                             evaluation with a rigorous error bound already
+                             proves the second difference negative; 0 always
+                             evaluates in FP64.  Both take identical decisions. */
 } flb_params;
 
 /* Fills p with defaults: D2Q9 F32 64x64x1, tau 1, G -5, rho0 1, rho_liquid 2,
@@ -111,9 +116,9 @@ typedef struct {
   double mom[3];     /* sum of j (FP64) */
   int64_t step;      /* steps completed */
   int32_t n_bubbles; /* bubbles in the film maps of the last refresh (0 if film off) */
-  int32_t n_ruptures;/* barrier removals so far */
+  int32_t n_ruptures;/* barrier removals so far: unions of two bubble classes */
   int32_t stopped;   /* 1 once the run stopped on a rupture (on_rupture == 1) */
-  int32_t events_lost; /* rupture events beyond the log capacity */
+  int32_t events_lost; /* 1 if the rupture log filled up and later records were dropped */
 } flb_stats;
 
 /* Create a context: validates p, allocates device state through alloc (or
@@ -165,8 +170,9 @@ int flb_label_field(flb_ctx* ctx, const double* rho, size_t n, int32_t* out, int
 
 /* Film maps of the last refresh (film_on only), each array of n == nx*ny*nz:
  * labels, the smallest / largest label among the nearest bubbles (0 = none),
- * hop distance to them (-1 = beyond zone_width - 1), and the candidate
- * barrier-link mask (bit i = direction i).  Any pointer may be NULL. */
+ * hop distance to them (-1 = beyond zone_width - 1), and the barrier-link
+ * mask (bit i = direction i): the links built at the refresh, minus those
+ * whose two bubbles a rupture has united since.  Any pointer may be NULL. */
 int flb_get_maps(flb_ctx* ctx, int32_t* label, int32_t* owner, int32_t* owner2, int32_t* dist, uint32_t* mask,
                  size_t n);
 
@@ -175,10 +181,13 @@ int flb_get_maps(flb_ctx* ctx, int32_t* label, int32_t* owner, int32_t* owner2, 
  * floor(d / bin_width), last bin open-ended.  counts[nbins]. */
 int flb_get_histogram(flb_ctx* ctx, int32_t nbins, double bin_width, int64_t* counts, int32_t* n_bubbles);
 
-/* Rupture log: up to cap records of 3 x int64 (step, k, k2) with k < k2 the
- * labels of the film's two bubbles, in the order the device wrote them
- * (several records per step and pair are possible); *n receives the total
- * number written (it may exceed cap, and the device keeps at most 65536). */
+/* Rupture log: up to cap records of 3 x int64 (step, k, k2), k < k2: a
+ * barrier link between bubbles k and k2 (labels of the refresh in force) met
+ * the criterion in that step.  Records come in device order; one pair may
+ * appear several times in a step.  *n receives the number of records kept
+ * (the device keeps the first 65536; flb_stats.events_lost says whether later
+ * ones were dropped).  The unions a record asks for are applied whether or
+ * not it was kept. */
 int flb_get_rupture_events(flb_ctx* ctx, int64_t* out, int64_t cap, int64_t* n);
 
 /* Tuning of the fused step kernel: tile variant index (0..n_tiles-1, -1 keeps
@@ -191,12 +200,97 @@ int flb_get_tuning(flb_ctx* ctx, int32_t* tile, int32_t* lz, int32_t* xcd, int32
 
 /* Runs nsteps steps like flb_step, bracketed by HIP events on the context
  * stream, and returns the elapsed milliseconds in *ms.  With refresh == 0 the
- * film maps are not rebuilt (only the fused step kernel runs), which times
- * that kernel alone. */
-int flb_time_steps(flb_ctx* ctx, int64_t nsteps, int32_t refresh, double* ms);
+ * film maps are not rebuilt, so only the step kernel(s) and the small
+ * per-step finisher run.  If kernel_ms is not NULL, every step-kernel launch
+ * (the fused kernel, or both passes of the two-pass variant) is also
+ * bracketed by its own pair of events and *kernel_ms receives the sum of
+ * those durations, i.e. the time of the step kernel alone. */
+int flb_time_steps(flb_ctx* ctx, int64_t nsteps, int32_t refresh, double* ms, double* kernel_ms);
 
-/* Destroys the context and frees its device state.  NULL is ignored. */
+/* Destroys the context and frees its device state.  NULL, and a context
+ * owned by a batch (see flb_batch_member), are ignored. */
 void flb_destroy(flb_ctx* ctx);
+
+/* ---- Batches: many lattices advanced together ----------------------------
+ * A batch holds `count` member lattices of one lattice type and one storage
+ * format; every other parameter (extents, tau, G, film settings, seed, ...)
+ * may differ per member (params[k]).  A batch step advances every member by
+ * one time step exactly as flb_step would, with one batched step-kernel
+ * launch over all members' workgroups, one batched finisher launch and, when
+ * members have films, one batched rupture-test and one batched mask-pruning
+ * launch (film maps are refreshed per member).  Runs of steps are captured in
+ * a HIP graph and replayed when the stream is not the null stream.  Results
+ * of a member do not depend on the batch it is in.
+ *
+ * Members are contexts owned by the batch: flb_batch_member returns a
+ * borrowed handle on which every flb_get_* query, flb_set_nuclei,
+ * flb_set_populations and flb_step work; flb_destroy ignores it, and
+ * flb_batch_destroy frees all members. */
+typedef struct flb_batch flb_batch;
+
+int flb_batch_create(const flb_params* params, int32_t count, const flb_allocator* alloc, void* hip_stream,
+                     flb_batch** out);
+int flb_batch_size(flb_batch* batch, int32_t* count);
+int flb_batch_member(flb_batch* batch, int32_t k, flb_ctx** out);
+/* Advances every member by nsteps steps (asynchronous, like flb_step). */
+int flb_batch_step(flb_batch* batch, int64_t nsteps);
+/* Batch tuning: z-march tile variant shared by the members (-1 keeps; the
+ * two-pass variant has no batched form), the total workgroup target of a step
+ * launch that sets each member's segment length in proportion to its cells
+ * (0 keeps), the XCD remap (-1 keeps) and the steps per captured graph
+ * (0: no graphs, -1 keeps).  Results do not depend on the tuning. */
+int flb_batch_set_tuning(flb_batch* batch, int32_t tile, int64_t target, int32_t xcd, int32_t graph_steps);
+int flb_batch_get_tuning(flb_batch* batch, int32_t* tile, int64_t* target, int32_t* xcd, int32_t* graph_steps,
+                         int32_t* n_tiles);
+/* Autotuner: times `reps` launches of the batched step kernel for every tile
+ * variant, workgroup target and XCD setting without changing any member
+ * (each trial writes a scratch buffer under a copy of the run control),
+ * keeps the fastest, and returns its time per launch in *best_ms (may be
+ * NULL).  Allocates one scratch population buffer per member while it runs. */
+int flb_batch_autotune(flb_batch* batch, int32_t reps, double* best_ms);
+/* Runs nsteps batch steps bracketed by HIP events; *ms = elapsed time. */
+int flb_batch_time_steps(flb_batch* batch, int64_t nsteps, double* ms);
+void flb_batch_destroy(flb_batch* batch);
+
+/* ---- Server: resident foam jobs advanced together -------------------------
+ * Jobs (a parameter set, nuclei and a step count) queue in submission order.
+ * Each flb_server_pump is one scheduling round: it admits queued jobs, in
+ * order, while the device bytes of all admitted jobs stay within
+ * pool_bytes and fewer than max_jobs are resident (a job that does not fit
+ * waits, and so do the jobs behind it); it advances every running job by the
+ * same number of steps, chunk_steps or fewer so that no job passes its last
+ * step, with batched launches (one batch per lattice type and storage, runs
+ * of graph_steps steps replayed from captured HIP graphs); and it retires the
+ * jobs that are done: their final density and statistics are copied to host
+ * memory and their device memory is released.  The round synchronises the
+ * stream before it returns.  A job's results are exactly those of the same
+ * job run alone with flb_create / flb_set_nuclei / flb_step. */
+typedef struct flb_server flb_server;
+typedef struct {
+  int64_t pool_bytes;  /* device bytes the resident jobs may hold together */
+  int32_t max_jobs;    /* resident jobs at most */
+  int32_t chunk_steps; /* steps per round at most */
+  int32_t graph_steps; /* steps per captured graph (0: no graphs) */
+} flb_server_config;
+enum { FLB_JOB_QUEUED = 0, FLB_JOB_RUNNING = 1, FLB_JOB_DONE = 2, FLB_JOB_FAILED = 3 };
+
+/* pool 64 GiB, 256 jobs, chunks of 100 steps, graphs of 20 steps */
+void flb_server_default_config(flb_server_config* cfg);
+int flb_server_create(const flb_server_config* cfg, const flb_allocator* alloc, void* hip_stream,
+                      flb_server** out);
+/* Queues a job; *id receives its handle.  FLB_EBUSY if the job alone needs
+ * more device bytes than the pool (it could never be admitted). */
+int flb_server_submit(flb_server* srv, const flb_params* p, const flb_nucleus* nuclei, int32_t n, int64_t steps,
+                      int64_t* id);
+/* One scheduling round (see above).  Any output pointer may be NULL. */
+int flb_server_pump(flb_server* srv, int32_t* n_running, int32_t* n_queued, int64_t* n_done);
+int flb_server_job(flb_server* srv, int64_t id, int32_t* state, int64_t* steps_done);
+/* Final density (n == nx*ny*nz, x fastest) and statistics of a done job. */
+int flb_server_result(flb_server* srv, int64_t id, double* density, size_t n, flb_stats* stats);
+/* Forgets a done or failed job. */
+int flb_server_release(flb_server* srv, int64_t id);
+int flb_server_usage(flb_server* srv, int64_t* used_bytes, int64_t* pool_bytes);
+void flb_server_destroy(flb_server* srv);
 
 /* Message describing the last error on this thread ("" if none). */
 const char* flb_last_error(void);

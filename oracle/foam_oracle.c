@@ -31,6 +31,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_MAXQ 19
 
@@ -129,6 +132,15 @@ static long nbr(const or_sim* s, long c, int i, int sign) {
 static double psi_of(const or_params* p, double rho) {
   /* Sec. 2.1.2, Eq. pseudopotential, generalised to rho0 (1 - e^{-rho/rho0}). */
   return p->rho0 * (1.0 - exp(-rho / p->rho0));
+}
+
+/* OpenMP threads the loops of this file use (1 without OpenMP). */
+int or_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 double or_p0(double rho, double G, double rho0) {

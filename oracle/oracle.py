@@ -72,6 +72,7 @@ def _load():
         "or_events": (C.c_long, [_P, _L, C.c_long]),
         "or_histogram": (None, [_P, _I, C.c_int32, C.c_int32, C.c_double, _L, _L]),
         "or_p0": (C.c_double, [C.c_double, C.c_double, C.c_double]),
+        "or_threads": (C.c_int, []),
         "or_splitmix64": (C.c_uint64, [C.c_uint64]),
         "or_uniform": (C.c_double, [C.c_uint64, C.c_uint64]),
     }
@@ -223,6 +224,10 @@ class OracleSim:
     @property
     def n_ruptures(self):
         return self._lib.or_n_ruptures(self._h)
+
+    def threads(self):
+        """OpenMP threads the oracle runs on."""
+        return self._lib.or_threads()
 
     def events(self):
         n = self._lib.or_events(self._h, np.zeros(3, np.int64), 0)

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "foamlbm.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("foamlbm.hip", "batch.hip", "server.hip")]
 LIB = os.path.join(HERE, "libfoamlbm.so")
 
 FLAGS = [
@@ -16,7 +16,7 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["hipcc", *FLAGS, SRC, "-o", LIB + ".tmp"]
+    cmd = ["hipcc", *FLAGS, *SRCS, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

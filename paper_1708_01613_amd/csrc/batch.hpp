@@ -1,0 +1,343 @@
+// batch.hpp -- many lattices advanced together: batch state and launches.
+//
+// Members are ordinary contexts of one lattice type and one storage format;
+// their extents and parameters may differ.  One step of the batch is one
+// batched step-kernel launch over every member's workgroups (member k owns the
+// launch's workgroups [first[k], first[k+1])), one batched finisher launch
+// with a workgroup per member, and with films a batched rupture-test launch
+// and a batched mask-pruning launch; film-map refreshes stay per member.  So
+// the launch count per step does not grow with the number of lattices, and the
+// GPU is filled by all members at once instead of one small lattice at a time.
+// Runs of steps are captured in a HIP graph and replayed.
+#pragma once
+#include "runtime.hpp"
+
+namespace flb_rt {
+
+using BatchStepFn = void (*)(const StepArgs*, const int*, int, int, bool, hipStream_t);
+
+template <class L, class S, int TX, int TM>
+void launch_step_batch(const StepArgs* tab, const int* first, int nmem, int nblk, bool buf, hipStream_t s) {
+  if (buf)
+    hipLaunchKernelGGL((k_step_batch<L, S, TX, TM, true>), dim3(nblk), dim3(StepBlock<L, S, TX, TM, true>::NT), 0, s,
+                       tab, first, nmem);
+  else
+    hipLaunchKernelGGL((k_step_batch<L, S, TX, TM, false>), dim3(nblk), dim3(StepBlock<L, S, TX, TM, false>::NT), 0,
+                       s, tab, first, nmem);
+}
+
+// batched launchers of the z-march tile variants, in the order of the
+// single-lattice tile tables (the two-pass variant has no batched form)
+template <class L, int TX, int TM>
+struct BatchTile {
+  static constexpr BatchStepFn fn[3] = {&launch_step_batch<L, SF64, TX, TM>, &launch_step_batch<L, SF32, TX, TM>,
+                                        &launch_step_batch<L, SF16S, TX, TM>};
+};
+inline const BatchStepFn* const kBatch2[] = {BatchTile<D2Q9K, 64, 1>::fn, BatchTile<D2Q9K, 128, 1>::fn,
+                                      BatchTile<D2Q9K, 256, 1>::fn};
+inline const BatchStepFn* const kBatch3[] = {BatchTile<D3Q19K, 64, 4>::fn, BatchTile<D3Q19K, 64, 8>::fn,
+                                      BatchTile<D3Q19K, 32, 8>::fn, BatchTile<D3Q19K, 128, 4>::fn};
+constexpr int kNBatch2 = sizeof(kBatch2) / sizeof(kBatch2[0]);
+constexpr int kNBatch3 = sizeof(kBatch3) / sizeof(kBatch3[0]);
+
+inline long long lcm_ll(long long a, long long b) {
+  long long x = a, y = b;
+  while (y) {
+    const long long t = x % y;
+    x = y;
+    y = t;
+  }
+  return a / x * b;
+}
+
+}  // namespace flb_rt
+
+struct flb_batch {
+  std::vector<flb_ctx*> m;
+  bool owns_members = true;  // false for a server's view over its jobs' contexts
+  flb_allocator al;
+  bool have_al = false;
+  hipStream_t st = nullptr;
+  int D = 0, storage = 0;
+  // tuning shared by the members
+  int tile = 0;
+  long long target = 2048;  // workgroups of the whole batch step launch
+  int xcd = 0;
+  bool buf = true;  // every member's buffers take the buffer-resource path
+  // device tables
+  std::vector<void*> allocs;
+  StepArgs* tab = nullptr;
+  int* first = nullptr;
+  int nblk = 0;
+  std::vector<int> film;  // indices of film members
+  StepArgs* ftab = nullptr;
+  PruneArgs* ptab = nullptr;
+  int* ffirst = nullptr;
+  int fblk = 0;
+  bool dirty = true;
+  // graphs
+  int graph_steps = 16;
+  hipGraphExec_t gexec = nullptr;
+  long long gperiod = 0;
+  std::vector<long long> gkey;
+
+  void* dalloc(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    void* ptr = nullptr;
+    if (have_al) ptr = al.alloc(bytes, al.user);
+    else if (hipMalloc(&ptr, bytes) != hipSuccess) ptr = nullptr;
+    if (ptr) allocs.push_back(ptr);
+    return ptr;
+  }
+  void dfree(void* ptr) {
+    if (!ptr) return;
+    if (have_al) al.free(ptr, al.user);
+    else (void)hipFree(ptr);
+    auto it = std::find(allocs.begin(), allocs.end(), ptr);
+    if (it != allocs.end()) allocs.erase(it);
+  }
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    gperiod = 0;
+    gkey.clear();
+  }
+  int n_tiles() const { return D == 2 ? flb_rt::kNBatch2 : flb_rt::kNBatch3; }
+  flb_rt::BatchStepFn step_fn() const { return (D == 2 ? flb_rt::kBatch2 : flb_rt::kBatch3)[tile][storage]; }
+};
+
+namespace flb_rt {
+
+// per-member tuning from the batch tuning: each member gets a share of the
+// target workgroups in proportion to its cells
+inline void apply_tuning(flb_batch* b) {
+  long long total = 0;
+  for (flb_ctx* c : b->m) total += c->N;
+  for (flb_ctx* c : b->m) {
+    c->tile = b->tile;
+    const long long share = std::max<long long>(1, (long long)((double)b->target * (double)c->N / (double)total));
+    c->lz = lz_for_target(c, share);
+    c->xcd = b->xcd;
+  }
+}
+
+// device tables of the members' arguments and workgroup ranges
+inline int rebuild(flb_batch* b) {
+  apply_tuning(b);
+  const int n = (int)b->m.size();
+  std::vector<StepArgs> tab(n);
+  std::vector<int> first(n + 1, 0);
+  b->buf = true;
+  for (int k = 0; k < n; k++) {
+    tab[k] = step_args(b->m[k]);
+    first[k + 1] = first[k] + b->m[k]->nblocks();
+    if (b->m[k]->fbytes >= kBufPathLimit) b->buf = false;
+  }
+  b->film.clear();
+  for (int k = 0; k < n; k++)
+    if (b->m[k]->p.film_on) b->film.push_back(k);
+  const int nf = (int)b->film.size();
+  std::vector<StepArgs> ftab(nf);
+  std::vector<PruneArgs> ptab(nf);
+  std::vector<int> ffirst(nf + 1, 0);
+  for (int j = 0; j < nf; j++) {
+    flb_ctx* c = b->m[b->film[j]];
+    ftab[j] = tab[b->film[j]];
+    ptab[j] = prune_args(c);
+    ffirst[j + 1] = ffirst[j] + list_grid(c->N);
+  }
+  if (!b->tab) {
+    b->tab = (StepArgs*)b->dalloc(sizeof(StepArgs) * n);
+    b->first = (int*)b->dalloc(sizeof(int) * (n + 1));
+    if (nf) {
+      b->ftab = (StepArgs*)b->dalloc(sizeof(StepArgs) * nf);
+      b->ptab = (PruneArgs*)b->dalloc(sizeof(PruneArgs) * nf);
+      b->ffirst = (int*)b->dalloc(sizeof(int) * (nf + 1));
+    }
+    if (!b->tab || !b->first || (nf && (!b->ftab || !b->ptab || !b->ffirst)))
+      return fail(FLB_ENOMEM, "batch table allocation failed");
+  }
+  HIPCHK(hipMemcpyAsync(b->tab, tab.data(), sizeof(StepArgs) * n, hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipMemcpyAsync(b->first, first.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, b->st));
+  if (nf) {
+    HIPCHK(hipMemcpyAsync(b->ftab, ftab.data(), sizeof(StepArgs) * nf, hipMemcpyHostToDevice, b->st));
+    HIPCHK(hipMemcpyAsync(b->ptab, ptab.data(), sizeof(PruneArgs) * nf, hipMemcpyHostToDevice, b->st));
+    HIPCHK(hipMemcpyAsync(b->ffirst, ffirst.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, b->st));
+  }
+  HIPCHK(hipStreamSynchronize(b->st));
+  b->nblk = first[n];
+  b->fblk = ffirst[nf];
+  b->dirty = false;
+  b->drop_graph();
+  return FLB_OK;
+}
+
+// one step of every member (no synchronisation, capturable)
+template <class L, class S>
+int batch_one_step(flb_batch* b) {
+  for (int k : b->film) {
+    flb_ctx* c = b->m[k];
+    if (c->launched % c->p.k_own == 0) {
+      int rc = refresh_maps<L, S>(c, false);
+      if (rc) return rc;
+    }
+  }
+  const int n = (int)b->m.size();
+  b->step_fn()(b->tab, b->first, n, b->nblk, b->buf, b->st);
+  const int nf = (int)b->film.size();
+  if (nf) {
+    hipLaunchKernelGGL((k_rupture_batch<L, typename S::ct>), dim3(b->fblk), dim3(MAP_NT), 0, b->st, b->ftab,
+                       b->ffirst, nf);
+    hipLaunchKernelGGL((k_mask_prune_batch<L>), dim3(b->fblk), dim3(MAP_NT), 0, b->st, b->ptab, b->ffirst, nf);
+  }
+  hipLaunchKernelGGL(k_step_finish_batch, dim3(n), dim3(FIN_NT), 0, b->st, b->tab, b->first);
+  HIPCHK(hipGetLastError());
+  for (flb_ctx* c : b->m) c->launched++;
+  return FLB_OK;
+}
+
+// the refresh phase of every film member, and whether it has maps to carry
+// aliases from; a captured run of steps replays correctly only from the same
+// phases
+inline std::vector<long long> phase_key(const flb_batch* b) {
+  std::vector<long long> key;
+  for (int k : b->film) key.push_back(2 * (b->m[k]->launched % b->m[k]->p.k_own) + (b->m[k]->maps_seen ? 1 : 0));
+  return key;
+}
+
+inline long long graph_period(const flb_batch* b) {
+  long long per = b->graph_steps;
+  for (int k : b->film) {
+    per = lcm_ll(per, b->m[k]->p.k_own);
+    if (per > 4096) return 0;
+  }
+  return per;
+}
+
+template <class L, class S>
+int batch_steps(flb_batch* b, int64_t nsteps) {
+  if (b->dirty) {
+    int rc = rebuild(b);
+    if (rc) return rc;
+  }
+  int64_t done = 0;
+  // graphs need a capturable (non-null) stream
+  const long long per = (b->graph_steps > 0 && b->st) ? graph_period(b) : 0;
+  while (per > 0 && nsteps - done >= per) {
+    const std::vector<long long> key = phase_key(b);
+    if (!b->gexec || b->gperiod != per || key != b->gkey) {
+      // capture `per` steps; the host bookkeeping advances as the steps are
+      // recorded, and the graph launch below performs them
+      b->drop_graph();
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+      int rc = FLB_OK;
+      for (long long s = 0; s < per && !rc; s++) rc = batch_one_step<L, S>(b);
+      hipError_t e = hipStreamEndCapture(b->st, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(FLB_EHIP, "graph capture: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        b->gexec = nullptr;
+        return fail(FLB_EHIP, "graph instantiation: %s", hipGetErrorString(e));
+      }
+      b->gperiod = per;
+      b->gkey = key;
+    } else {
+      for (flb_ctx* c : b->m) c->launched += per;
+    }
+    HIPCHK(hipGraphLaunch(b->gexec, b->st));
+    done += per;
+  }
+  for (; done < nsteps; done++) {
+    int rc = batch_one_step<L, S>(b);
+    if (rc) return rc;
+  }
+  return FLB_OK;
+}
+
+#define FLB_BATCH_DISPATCH(b, FN, ...)                                                     \
+  ((b)->D == 2 ? ((b)->storage == FLB_F64   ? FN<D2Q9K, SF64>(__VA_ARGS__)                \
+                  : (b)->storage == FLB_F32 ? FN<D2Q9K, SF32>(__VA_ARGS__)                \
+                                            : FN<D2Q9K, SF16S>(__VA_ARGS__))              \
+               : ((b)->storage == FLB_F64   ? FN<D3Q19K, SF64>(__VA_ARGS__)               \
+                  : (b)->storage == FLB_F32 ? FN<D3Q19K, SF32>(__VA_ARGS__)               \
+                                            : FN<D3Q19K, SF16S>(__VA_ARGS__)))
+
+// Times `reps` launches of the batched step kernel with the current tuning
+// without changing any member: each member's launch reads its current buffer
+// and writes a scratch buffer, under a copy of its run control.
+inline int time_trial(flb_batch* b, int reps, void* const* scratch, Ctl* sctl, float* ms) {
+  int rc = rebuild(b);
+  if (rc) return rc;
+  const int n = (int)b->m.size();
+  std::vector<StepArgs> tab(n);
+  for (int k = 0; k < n; k++) {
+    flb_ctx* c = b->m[k];
+    tab[k] = step_args(c);
+    Ctl h;
+    rc = read_ctl(c, &h);
+    if (rc) return rc;
+    const int cur = (int)(h.steps & 1);  // the buffer the kernel will read
+    tab[k].buf[cur] = c->f[cur];
+    tab[k].buf[1 - cur] = scratch[k];
+    tab[k].ctl = sctl + k;
+    HIPCHK(hipMemcpyAsync(sctl + k, c->ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, b->st));
+  }
+  HIPCHK(hipMemcpyAsync(b->tab, tab.data(), sizeof(StepArgs) * n, hipMemcpyHostToDevice, b->st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  b->step_fn()(b->tab, b->first, n, b->nblk, b->buf, b->st);  // warm-up launch
+  hipError_t e = hipEventRecord(e0, b->st);
+  for (int r = 0; r < reps && e == hipSuccess; r++) b->step_fn()(b->tab, b->first, n, b->nblk, b->buf, b->st);
+  if (e == hipSuccess) e = hipEventRecord(e1, b->st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->dirty = true;  // the device table holds the trial arguments
+  if (e != hipSuccess) return fail(FLB_EHIP, "autotune timing: %s", hipGetErrorString(e));
+  return FLB_OK;
+}
+
+}  // namespace flb_rt
+
+namespace flb_rt {
+
+// A batch over existing contexts of one lattice type and storage, which it
+// does not own (a server's running jobs).  Tables are built on first use.
+inline flb_batch* batch_view(const std::vector<flb_ctx*>& ms, hipStream_t st, const flb_allocator* al) {
+  flb_batch* b = new (std::nothrow) flb_batch();
+  if (!b) return nullptr;
+  b->owns_members = false;
+  b->m = ms;
+  if (al) {
+    b->al = *al;
+    b->have_al = true;
+  }
+  b->st = st;
+  b->D = ms[0]->D;
+  b->storage = ms[0]->p.storage;
+  b->tile = b->D == 2 ? 0 : 1;
+  b->target = b->D == 2 ? 2048 : 512;
+  return b;
+}
+
+inline void batch_free(flb_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->st);
+  b->drop_graph();
+  for (void* p : b->allocs) {
+    if (b->have_al) b->al.free(p, b->al.user);
+    else (void)hipFree(p);
+  }
+  b->allocs.clear();
+  delete b;
+}
+
+}  // namespace flb_rt

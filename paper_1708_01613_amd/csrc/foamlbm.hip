@@ -1,376 +1,8 @@
-// foamlbm.hip -- host runtime and C ABI (include/foamlbm.h) of the gfx950 path.
-#include <hip/hip_runtime.h>
+// foamlbm.hip -- C ABI (include/foamlbm.h) of the gfx950 path: single lattices.
+#include "runtime.hpp"
 
-#include <math.h>
-#include <stdarg.h>
-#include <stdio.h>
-#include <string.h>
+using namespace flb_rt;
 
-#include <algorithm>
-#include <new>
-#include <string>
-#include <vector>
-
-#include "../../include/foamlbm.h"
-#include "ops.hpp"
-#include "twopass.hpp"
-
-using namespace flb;
-
-namespace {
-
-thread_local std::string g_err;
-
-int fail(int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return code;
-}
-
-#define HIPCHK(expr)                                                                  \
-  do {                                                                                \
-    hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess) return fail(FLB_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-// ---------------------------------------------------------------------------
-// step-kernel variants: tile shapes per lattice
-// ---------------------------------------------------------------------------
-using StepFn = void (*)(const StepArgs&, int, hipStream_t);
-
-// buffers below 2 GiB use buffer-resource loads with 32-bit offsets
-template <class L, class S, int TX, int TM>
-void launch_step(const StepArgs& a, int nblk, hipStream_t s) {
-  if (a.buf_bytes < kBufPathLimit)
-    hipLaunchKernelGGL((k_step<L, S, TX, TM, true>), dim3(nblk), dim3(StepBlock<L, S, TX, TM, true>::NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_step<L, S, TX, TM, false>), dim3(nblk), dim3(StepBlock<L, S, TX, TM, false>::NT), 0, s,
-                       a);
-}
-
-// two-pass path: k_psi then k_collide
-template <class L, class S>
-void launch_psi(const StepArgs& a, int nblk, hipStream_t s) {
-  if (a.buf_bytes < kBufPathLimit)
-    hipLaunchKernelGGL((k_psi<L, S, true>), dim3(nblk), dim3(TP_NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_psi<L, S, false>), dim3(nblk), dim3(TP_NT), 0, s, a);
-}
-template <class L, class S>
-void launch_collide(const StepArgs& a, int nblk, hipStream_t s) {
-  if (a.buf_bytes < kBufPathLimit)
-    hipLaunchKernelGGL((k_collide<L, S, true>), dim3(nblk), dim3(TP_NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_collide<L, S, false>), dim3(nblk), dim3(TP_NT), 0, s, a);
-}
-
-// step variants: z-march tiles (tx, tm) or the two-pass path (tx = tm = 0)
-struct TileCfg {
-  int tx, tm;
-  StepFn fn[3];    // z-march kernel, or k_psi, per storage F64, F32, F16S
-  StepFn coll[3];  // k_collide of the two-pass path
-};
-
-template <class L, int TX, int TM>
-constexpr TileCfg make_tile() {
-  return TileCfg{TX, TM,
-                 {&launch_step<L, SF64, TX, TM>, &launch_step<L, SF32, TX, TM>, &launch_step<L, SF16S, TX, TM>},
-                 {nullptr, nullptr, nullptr}};
-}
-template <class L>
-constexpr TileCfg make_two_pass() {
-  return TileCfg{0, 0, {&launch_psi<L, SF64>, &launch_psi<L, SF32>, &launch_psi<L, SF16S>},
-                 {&launch_collide<L, SF64>, &launch_collide<L, SF32>, &launch_collide<L, SF16S>}};
-}
-
-const TileCfg kTiles2[] = {make_tile<D2Q9K, 64, 1>(), make_tile<D2Q9K, 128, 1>(), make_tile<D2Q9K, 256, 1>(),
-                           make_two_pass<D2Q9K>()};
-const TileCfg kTiles3[] = {make_tile<D3Q19K, 64, 4>(), make_tile<D3Q19K, 64, 8>(), make_tile<D3Q19K, 32, 8>(),
-                           make_tile<D3Q19K, 128, 4>(), make_two_pass<D3Q19K>()};
-constexpr int kNTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
-constexpr int kNTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
-
-int grid_for(long long n, int block) {
-  long long g = (n + block - 1) / block;
-  return (int)std::min<long long>(std::max<long long>(g, 1), 65536);
-}
-
-}  // namespace
-
-struct flb_ctx {
-  flb_params p;
-  flb_allocator al;
-  bool have_al = false;
-  hipStream_t st = nullptr;
-  int Q = 0, D = 0;
-  MapDims md;              // kernel-coordinate extents
-  long long N = 0;         // cells
-  Geo geo;                 // population block layout
-  size_t fbytes = 0;       // bytes of one population buffer
-  void* f[2] = {nullptr, nullptr};
-  Ctl* ctl = nullptr;      // run control of the step kernel
-  Ctl* qctl = nullptr;     // always-zero control for query pipelines
-  double* partials = nullptr;
-  int max_blk = 0;
-  void* psi = nullptr;     // two-pass path: psi and rho arrays (compute type)
-  void* rho = nullptr;
-  // tuning
-  int tile = -1, lz = 0, xcd = 0;
-  // film maps
-  uint8_t* flag = nullptr;
-  uint8_t* dist = nullptr;
-  uint32_t* mask = nullptr;
-  int2* own = nullptr;
-  int* label = nullptr;
-  int* label_old = nullptr;
-  int* alias = nullptr;
-  int* alias_old = nullptr;
-  int* rep = nullptr;
-  int* par = nullptr;
-  int* rank = nullptr;
-  int* counts = nullptr;
-  long long* events = nullptr;
-  unsigned ev_cap = 1u << 16;
-  bool maps_seen = false;  // a refresh has run since the last set_nuclei
-  // query scratch
-  double* qd = nullptr;    // (1 + 3) * N doubles
-  int* qlabel = nullptr;
-  unsigned long long* qsizes = nullptr;
-  unsigned long long* qhist = nullptr;
-  int qhist_cap = 0;
-  double* qtot = nullptr;  // 4 doubles
-  long long launched = 0;
-  std::vector<void*> allocs;
-
-  void* dalloc(size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    void* ptr = nullptr;
-    if (have_al) {
-      ptr = al.alloc(bytes, al.user);
-    } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
-      ptr = nullptr;
-    }
-    if (ptr) allocs.push_back(ptr);
-    return ptr;
-  }
-  void dfree_all() {
-    for (void* ptr : allocs) {
-      if (have_al) al.free(ptr, al.user);
-      else (void)hipFree(ptr);
-    }
-    allocs.clear();
-  }
-  const TileCfg& tcfg() const { return D == 2 ? kTiles2[tile] : kTiles3[tile]; }
-  bool two_pass() const { return tcfg().tx == 0; }
-  int tiles_x() const { return two_pass() ? 1 : (md.nx + tcfg().tx - 1) / tcfg().tx; }
-  int tiles_m() const { return two_pass() ? 1 : (md.nm + tcfg().tm - 1) / tcfg().tm; }
-  int nblocks() const {
-    if (two_pass()) return geo.nxb * (int)((md.nm * (long long)md.nz + TP_ROWS - 1) / TP_ROWS);
-    return tiles_x() * tiles_m() * ((md.nz + lz - 1) / lz);
-  }
-};
-
-namespace {
-
-void default_tuning(flb_ctx* c) {
-  c->tile = c->D == 2 ? 1 : 1;  // D2Q9 128x1, D3Q19 64x8
-  const long long cols = (long long)c->tiles_x() * c->tiles_m();
-  // aim at ~2048 workgroups (8 per CU) without segments shorter than 8 planes
-  long long nseg = std::max<long long>(1, 2048 / std::max<long long>(cols, 1));
-  int lz = (int)std::max<long long>(8, (c->md.nz + nseg - 1) / nseg);
-  c->lz = std::min(lz, c->md.nz);
-  c->xcd = 0;
-}
-
-StepArgs step_args(flb_ctx* c) {
-  StepArgs a;
-  memset(&a, 0, sizeof a);
-  a.buf[0] = c->f[0];
-  a.buf[1] = c->f[1];
-  a.geo = c->geo;
-  a.nx = c->md.nx;
-  a.nm = c->md.nm;
-  a.nz = c->md.nz;
-  a.tiles_x = c->tiles_x();
-  a.tiles_m = c->tiles_m();
-  a.lz = c->lz;
-  const int nblk = c->nblocks();
-  a.xcd_chunks = (c->xcd > 1 && nblk % c->xcd == 0) ? c->xcd : 1;
-  a.tau = c->p.tau;
-  a.G = c->p.G;
-  a.rho0 = c->p.rho0;
-  a.psi_bar = c->p.rho0 * (1.0 - exp(-c->p.rho_liquid / c->p.rho0));
-  a.psi_bar_mode = c->p.psi_bar_mode;
-  a.film_on = c->p.film_on;
-  a.rupture_warmup = c->p.rupture_warmup;
-  a.on_rupture = c->p.on_rupture;
-  a.flag = c->flag;
-  a.mask = c->mask;
-  a.own = c->own;
-  a.alias = c->alias;
-  a.events = c->events;
-  a.ev_cap = c->ev_cap;
-  a.ctl = c->ctl;
-  a.partials = c->partials;
-  a.buf_bytes = c->fbytes;
-  a.psi = c->psi;
-  a.rho = c->rho;
-  return a;
-}
-
-// ---- labels of the current state (or of a density field) into `label` ----
-template <class L, class S>
-int label_pipeline(flb_ctx* c, const Ctl* gate, int* total, int* label, const double* field,
-                   bool from_rho = false) {
-  const int B = 256, g = grid_for(c->N, B);
-  if (field)
-    hipLaunchKernelGGL(k_gas_from_field, dim3(g), dim3(B), 0, c->st, field, c->md, c->p.rho_th, c->par);
-  else if (from_rho)
-    hipLaunchKernelGGL((k_gas_from_rho<typename S::ct>), dim3(g), dim3(B), 0, c->st, gate,
-                       (const typename S::ct*)c->rho, c->md, c->p.rho_th, c->par);
-  else
-    hipLaunchKernelGGL((k_gas_init<L, S>), dim3(g), dim3(B), 0, c->st, c->f[0], c->f[1], gate, c->geo, c->md,
-                       c->p.rho_th, c->par);
-  hipLaunchKernelGGL((k_cc_hook<L>), dim3(g), dim3(B), 0, c->st, gate, c->md, c->par);
-  hipLaunchKernelGGL(k_cc_compress, dim3(g), dim3(B), 0, c->st, gate, c->md, c->par);
-  const int nrb = (int)((c->N + RANK_BLOCK - 1) / RANK_BLOCK);
-  hipLaunchKernelGGL(k_count_roots, dim3(nrb), dim3(RANK_BLOCK), 0, c->st, gate, c->md, c->par, c->counts);
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, c->st, gate, c->counts, nrb, total);
-  hipLaunchKernelGGL(k_write_rank, dim3(nrb), dim3(RANK_BLOCK), 0, c->st, gate, c->md, c->par, c->counts,
-                     c->rank);
-  hipLaunchKernelGGL(k_write_labels, dim3(g), dim3(B), 0, c->st, gate, c->md, c->par, c->rank, label);
-  HIPCHK(hipGetLastError());
-  return FLB_OK;
-}
-
-// ---- film-map refresh before a step ----
-template <class L, class S>
-int refresh_maps(flb_ctx* c, bool from_rho) {
-  const int B = 256, g = grid_for(c->N, B);
-  const int gl = grid_for(c->N + 1, B);
-  const Ctl* gate = c->ctl;
-  if (c->maps_seen) {
-    hipLaunchKernelGGL(k_copy_int, dim3(g), dim3(B), 0, c->st, gate, c->label, c->label_old, c->N);
-    hipLaunchKernelGGL(k_copy_int, dim3(gl), dim3(B), 0, c->st, gate, c->alias, c->alias_old, c->N + 1);
-  }
-  int rc = label_pipeline<L, S>(c, gate, &c->ctl->n_bubbles, c->label, nullptr, from_rho);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_owner_init, dim3(g), dim3(B), 0, c->st, gate, c->md, c->label, c->own, c->dist);
-  for (int layer = 1; layer <= c->p.zone_width - 1; layer++)
-    hipLaunchKernelGGL((k_owner_layer<L>), dim3(g), dim3(B), 0, c->st, gate, c->md, layer, c->own, c->dist);
-  hipLaunchKernelGGL(k_alias_reset, dim3(gl), dim3(B), 0, c->st, gate, c->alias, c->rep, (int)c->N);
-  if (c->maps_seen) {
-    hipLaunchKernelGGL(k_alias_carry1, dim3(g), dim3(B), 0, c->st, gate, c->md, c->label, c->label_old,
-                       c->alias_old, c->rep);
-    hipLaunchKernelGGL(k_alias_carry2, dim3(g), dim3(B), 0, c->st, gate, c->md, c->label, c->label_old,
-                       c->alias_old, c->rep, c->alias);
-    hipLaunchKernelGGL(k_alias_compress, dim3(gl), dim3(B), 0, c->st, gate, c->alias);
-  }
-  hipLaunchKernelGGL((k_masks<L>), dim3(g), dim3(B), 0, c->st, gate, c->md, c->p.zone_width, c->own, c->dist,
-                     c->alias, c->flag, c->mask);
-  hipLaunchKernelGGL(k_masks_done, dim3(1), dim3(64), 0, c->st, c->ctl);
-  HIPCHK(hipGetLastError());
-  c->maps_seen = true;
-  return FLB_OK;
-}
-
-template <class L, class S>
-int do_steps(flb_ctx* c, int64_t nsteps, bool refresh) {
-  const StepArgs a = step_args(c);
-  const int nblk = c->nblocks();
-  const StepFn fn = c->tcfg().fn[c->p.storage];
-  const StepFn coll = c->tcfg().coll[c->p.storage];
-  for (int64_t s = 0; s < nsteps; s++) {
-    const bool due = refresh && c->p.film_on && c->launched % c->p.k_own == 0;
-    if (coll) {
-      fn(a, nblk, c->st);  // rho / psi of the current state
-      if (due) {
-        int rc = refresh_maps<L, S>(c, true);
-        if (rc) return rc;
-      }
-      coll(a, nblk, c->st);
-    } else {
-      if (due) {
-        int rc = refresh_maps<L, S>(c, false);
-        if (rc) return rc;
-      }
-      fn(a, nblk, c->st);
-    }
-    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(FIN_NT), 0, c->st, a, nblk);
-    c->launched++;
-  }
-  HIPCHK(hipGetLastError());
-  return FLB_OK;
-}
-
-template <class L, class S>
-int do_pack(flb_ctx* c, const double* field_dev, int mode, int which) {
-  const int B = 256, g = grid_for(c->N, B);
-  hipLaunchKernelGGL((k_pack<L, S>), dim3(g), dim3(B), 0, c->st, c->f[which], c->geo, c->md, field_dev, mode);
-  HIPCHK(hipGetLastError());
-  return FLB_OK;
-}
-
-template <class L, class S>
-int do_moments(flb_ctx* c, bool with_j) {
-  const int B = 256, g = grid_for(c->N, B);
-  hipLaunchKernelGGL((k_moments<L, S>), dim3(g), dim3(B), 0, c->st, c->f[0], c->f[1], c->ctl, c->geo, c->md, c->qd,
-                     with_j ? c->qd + c->N : nullptr);
-  HIPCHK(hipGetLastError());
-  return FLB_OK;
-}
-
-template <class L, class S>
-int do_unpack(flb_ctx* c, double* out_dev) {
-  const int B = 256, g = grid_for(c->N, B);
-  hipLaunchKernelGGL((k_unpack<L, S>), dim3(g), dim3(B), 0, c->st, c->f[0], c->f[1], c->ctl, c->geo, c->md,
-                     out_dev);
-  HIPCHK(hipGetLastError());
-  return FLB_OK;
-}
-
-// dispatch a templated operation on (lattice, storage)
-#define FLB_DISPATCH(c, FN, ...)                                                           \
-  ((c)->D == 2 ? ((c)->p.storage == FLB_F64   ? FN<D2Q9K, SF64>(__VA_ARGS__)              \
-                  : (c)->p.storage == FLB_F32 ? FN<D2Q9K, SF32>(__VA_ARGS__)              \
-                                              : FN<D2Q9K, SF16S>(__VA_ARGS__))            \
-               : ((c)->p.storage == FLB_F64   ? FN<D3Q19K, SF64>(__VA_ARGS__)             \
-                  : (c)->p.storage == FLB_F32 ? FN<D3Q19K, SF32>(__VA_ARGS__)             \
-                                              : FN<D3Q19K, SF16S>(__VA_ARGS__)))
-
-int validate(const flb_params* p) {
-  if (!p) return fail(FLB_EINVAL, "params is NULL");
-  if (p->lattice != FLB_D2Q9 && p->lattice != FLB_D3Q19) return fail(FLB_EINVAL, "lattice must be 0 or 1");
-  if (p->storage < FLB_F64 || p->storage > FLB_F16S) return fail(FLB_EINVAL, "storage must be 0, 1 or 2");
-  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(FLB_EINVAL, "extents must be >= 1");
-  if (p->lattice == FLB_D2Q9 && p->nz != 1) return fail(FLB_EINVAL, "D2Q9 requires nz == 1");
-  const long long N = (long long)p->nx * p->ny * p->nz;
-  if (N > (1ll << 28)) return fail(FLB_EINVAL, "lattice too large (%lld cells > 2^28)", N);
-  if (!(p->tau > 0.5) || !isfinite(p->tau)) return fail(FLB_EINVAL, "tau must be > 0.5");
-  if (!(p->rho0 > 0) || !isfinite(p->rho0)) return fail(FLB_EINVAL, "rho0 must be > 0");
-  if (!isfinite(p->G) || !isfinite(p->rho_liquid) || !isfinite(p->rho_gas) || !isfinite(p->noise_amp) ||
-      !isfinite(p->rho_th))
-    return fail(FLB_EINVAL, "non-finite parameter");
-  if (p->film_on != 0 && p->film_on != 1) return fail(FLB_EINVAL, "film_on must be 0 or 1");
-  if (p->k_own < 1) return fail(FLB_EINVAL, "k_own must be >= 1");
-  if (p->zone_width < 1 || p->zone_width > 15) return fail(FLB_EINVAL, "zone_width must be in 1..15");
-  if (p->psi_bar_mode != 0 && p->psi_bar_mode != 1) return fail(FLB_EINVAL, "psi_bar_mode must be 0 or 1");
-  if (p->on_rupture != 0 && p->on_rupture != 1) return fail(FLB_EINVAL, "on_rupture must be 0 or 1");
-  if (p->velocity_mode != 0 && p->velocity_mode != 1) return fail(FLB_EINVAL, "velocity_mode must be 0 or 1");
-  return FLB_OK;
-}
-
-int read_ctl(flb_ctx* c, Ctl* out) {
-  HIPCHK(hipMemcpyAsync(out, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
-  return FLB_OK;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -397,6 +29,7 @@ void flb_default_params(flb_params* p) {
   p->rupture_warmup = 200;
   p->on_rupture = 0;
   p->velocity_mode = 0;
+  p->rupture_filter = 1;
 }
 
 const char* flb_last_error(void) { return g_err.c_str(); }
@@ -465,6 +98,7 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     ok = ok && (c->flag = (uint8_t*)c->dalloc((size_t)c->N));
     ok = ok && (c->dist = (uint8_t*)c->dalloc((size_t)c->N));
     ok = ok && (c->mask = (uint32_t*)c->dalloc(sizeof(uint32_t) * (size_t)c->N));
+    ok = ok && (c->flist = (int*)c->dalloc(sizeof(int) * (size_t)c->N));
     ok = ok && (c->own = (int2*)c->dalloc(sizeof(int2) * (size_t)c->N));
     ok = ok && (c->label = (int*)c->dalloc(sizeof(int) * (size_t)c->N));
     ok = ok && (c->label_old = (int*)c->dalloc(sizeof(int) * (size_t)c->N));
@@ -472,6 +106,8 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     ok = ok && (c->alias_old = (int*)c->dalloc(sizeof(int) * (size_t)(c->N + 1)));
     ok = ok && (c->rep = (int*)c->dalloc(sizeof(int) * (size_t)(c->N + 1)));
     ok = ok && (c->events = (long long*)c->dalloc(sizeof(long long) * 4 * (size_t)c->ev_cap));
+    c->nwords = (long long)((c->md.nx + 63) / 64) * c->md.nm * c->md.nz;
+    ok = ok && (c->bits = (unsigned long long*)c->dalloc(sizeof(unsigned long long) * 3 * (size_t)c->nwords));
   }
   if (!ok) {
     c->dfree_all();
@@ -492,7 +128,7 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
 }
 
 void flb_destroy(flb_ctx* c) {
-  if (!c) return;
+  if (!c || c->in_batch) return;
   (void)hipStreamSynchronize(c->st);
   c->dfree_all();
   delete c;
@@ -518,11 +154,7 @@ int flb_set_nuclei(flb_ctx* c, const flb_nucleus* nuc, int32_t n) {
   int rc = FLB_DISPATCH(c, do_pack, c, c->qd, 0, 0);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->st));
-  if (dn) {
-    if (c->have_al) c->al.free(dn, c->al.user);
-    else (void)hipFree(dn);
-    c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void*)dn));
-  }
+  c->dfree(dn);
   c->launched = 0;
   c->maps_seen = false;
   if (c->p.film_on) {
@@ -538,24 +170,39 @@ int flb_step(flb_ctx* c, int64_t nsteps) {
   return FLB_DISPATCH(c, do_steps, c, nsteps, true);
 }
 
-int flb_time_steps(flb_ctx* c, int64_t nsteps, int32_t refresh, double* ms) {
+int flb_time_steps(flb_ctx* c, int64_t nsteps, int32_t refresh, double* ms, double* kernel_ms) {
   if (!c || !ms) return fail(FLB_EINVAL, "NULL argument");
   if (nsteps < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  hipError_t e = hipEventRecord(e0, c->st);
+  if (kernel_ms && nsteps > 100000) return fail(FLB_EINVAL, "nsteps must be <= 100000 with kernel_ms");
+  // per-launch events for the kernel time, created up front
+  std::vector<hipEvent_t> kev(kernel_ms ? 4 * (size_t)nsteps : 0, nullptr);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (size_t k = 0; k < kev.size() && e == hipSuccess; k++) e = hipEventCreate(&kev[k]);
   int rc = FLB_OK;
-  if (e == hipSuccess) rc = FLB_DISPATCH(c, do_steps, c, nsteps, refresh != 0);
+  if (e == hipSuccess) e = hipEventRecord(e0, c->st);
+  if (e == hipSuccess) rc = FLB_DISPATCH(c, do_steps, c, nsteps, refresh != 0, kernel_ms ? kev.data() : nullptr);
   if (e == hipSuccess && !rc) e = hipEventRecord(e1, c->st);
   if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
   float f = 0.f;
   if (e == hipSuccess && !rc) e = hipEventElapsedTime(&f, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  double ksum = 0.0;
+  const bool two = c->two_pass();
+  for (int64_t s = 0; s < nsteps && kernel_ms && e == hipSuccess && !rc; s++) {
+    float a = 0.f, b = 0.f;
+    e = hipEventElapsedTime(&a, kev[4 * s], kev[4 * s + 1]);
+    if (e == hipSuccess && two) e = hipEventElapsedTime(&b, kev[4 * s + 2], kev[4 * s + 3]);
+    ksum += (double)a + (double)b;
+  }
+  for (hipEvent_t ev : kev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   if (rc) return rc;
   if (e != hipSuccess) return fail(FLB_EHIP, "timing: %s", hipGetErrorString(e));
   *ms = f;
+  if (kernel_ms) *kernel_ms = ksum;
   return FLB_OK;
 }
 
@@ -636,6 +283,7 @@ int flb_get_maps(flb_ctx* c, int32_t* label, int32_t* owner, int32_t* owner2, in
     if (owner) owner[k] = own[k].x;
     if (owner2) owner2[k] = own[k].y;
     if (dist) dist[k] = d8[k] == 255 ? -1 : d8[k];
+    if (mask) mask[k] &= kLinkBits;  // link bits only
   }
   return FLB_OK;
 }
@@ -676,7 +324,7 @@ int flb_get_rupture_events(flb_ctx* c, int64_t* out, int64_t cap, int64_t* n) {
   Ctl h;
   int rc = read_ctl(c, &h);
   if (rc) return rc;
-  *n = c->p.film_on ? (int64_t)h.ev_count : 0;
+  *n = c->p.film_on ? (int64_t)std::min<unsigned>(h.ev_count, c->ev_cap) : 0;
   const int64_t have = std::min<int64_t>(*n, c->ev_cap);
   const int64_t m = std::min<int64_t>(have, cap);
   if (m > 0) {
@@ -717,9 +365,7 @@ int flb_get_velocity(flb_ctx* c, double* out, size_t n) {
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(out, vel, sizeof(double) * n, hipMemcpyDeviceToHost, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-  if (c->have_al) c->al.free(vel, c->al.user);
-  else (void)hipFree(vel);
-  c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void*)vel));
+  c->dfree(vel);
   if (e != hipSuccess) return fail(FLB_EHIP, "velocity query: %s", hipGetErrorString(e));
   return FLB_OK;
 }
@@ -733,9 +379,7 @@ int flb_get_populations(flb_ctx* c, double* out, size_t n) {
   hipError_t e = hipSuccess;
   if (!rc) e = hipMemcpyAsync(out, tmp, sizeof(double) * n, hipMemcpyDeviceToHost, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-  if (c->have_al) c->al.free(tmp, c->al.user);
-  else (void)hipFree(tmp);
-  c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void*)tmp));
+  c->dfree(tmp);
   if (rc) return rc;
   if (e != hipSuccess) return fail(FLB_EHIP, "population query: %s", hipGetErrorString(e));
   return FLB_OK;
@@ -752,9 +396,7 @@ int flb_set_populations(flb_ctx* c, const double* in, size_t n) {
   hipError_t e = hipMemcpyAsync(tmp, in, sizeof(double) * n, hipMemcpyHostToDevice, c->st);
   if (e == hipSuccess) rc = FLB_DISPATCH(c, do_pack, c, tmp, 1, (int)(h.steps & 1));
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-  if (c->have_al) c->al.free(tmp, c->al.user);
-  else (void)hipFree(tmp);
-  c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void*)tmp));
+  c->dfree(tmp);
   if (e != hipSuccess) return fail(FLB_EHIP, "population import: %s", hipGetErrorString(e));
   return rc;
 }
@@ -781,9 +423,10 @@ int flb_get_stats(flb_ctx* c, flb_stats* out) {
   out->n_bubbles = c->p.film_on ? h.n_bubbles : 0;
   out->n_ruptures = (int32_t)h.n_ruptures;
   out->stopped = h.stopped;
-  out->events_lost = h.ev_count > c->ev_cap ? (int32_t)(h.ev_count - c->ev_cap) : 0;
+  out->events_lost = h.ev_full;
   if (h.failed || !isfinite(tot[0])) return fail(FLB_ENUMERIC, "non-finite mass");
   return FLB_OK;
 }
 
 }  // extern "C"
+

@@ -110,17 +110,26 @@ __device__ inline void pop_st(void* base, const Geo& g, int i, int x, int m, int
   else *(float*)p = v;
 }
 
+// Barrier mask word of a cell: bit i (1 <= i < Q) marks an active barrier link
+// in direction i; kRhoBit marks a cell whose density the rupture test reads
+// (an end or an outer neighbour of a barrier link), so the step kernel stores
+// its density only there.
+constexpr uint32_t kRhoBit = 1u << 31;
+constexpr uint32_t kLinkBits = ~kRhoBit;
+
 // Device-side run control shared by every launch of one lattice.
 struct Ctl {
   unsigned done;        // workgroups finished in the current launch
   int stopped;          // 1 after a rupture with on_rupture == 1
   long long steps;      // steps completed (selects the A/B buffer)
-  unsigned ev_count;    // rupture events written so far (may exceed capacity)
-  unsigned ev_start;    // first event of the step in flight
-  long long n_ruptures; // successful barrier removals
+  unsigned ev_count;    // rupture-log records written so far (<= capacity)
+  int ev_full;          // 1 once a record found the log full
+  long long n_ruptures; // successful barrier removals (unions of two classes)
   int failed;           // 1 once the FP64 mass reduction saw a non-finite value
   int n_bubbles;        // labels in the current film maps
-  int alias_dirty;      // 1 if a rupture united bubbles since the masks were built
+  int alias_dirty;      // 1 if ruptures of this step united bubbles (masks need pruning)
+  int step_events;      // 1 if the rupture test of this step found a link
+  unsigned n_flagged;   // cells with barrier links at the last refresh (list length)
   double mass, mom[3];  // FP64 totals of the state entering the last step
 };
 

@@ -16,7 +16,7 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
 // image, integer cell centres), rho_liquid elsewhere, plus a (2U - 1) noise.
 // Lattice coordinates (x, y, z); FP64 without contraction so that the inside
 // test rounds exactly like a plain C evaluation.
-__global__ void k_init_density(double* rho, int nx, int ny, int nz, long long N, const double4* nuc, int nn,
+static __global__ void k_init_density(double* rho, int nx, int ny, int nz, long long N, const double4* nuc, int nn,
                                double rl, double rg, double amp, unsigned long long seed) {
 #pragma clang fp contract(off)
   for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
@@ -134,7 +134,7 @@ __global__ void k_velocity(StepArgs a, MapDims d, const double* rho, const doubl
 // FP64 totals: per-block partial sums of up to 4 planes, then one block sums
 // the partials in block order (deterministic)
 constexpr int RED_BLOCK = 256;
-__global__ __launch_bounds__(RED_BLOCK) void k_reduce_partial(const double* planes, int nplanes, long long N,
+static __global__ __launch_bounds__(RED_BLOCK) void k_reduce_partial(const double* planes, int nplanes, long long N,
                                                               double* partials) {
   double t[4] = {0.0, 0.0, 0.0, 0.0};
   for (long long c = blockIdx.x * (long long)RED_BLOCK + threadIdx.x; c < N; c += (long long)gridDim.x * RED_BLOCK)
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(RED_BLOCK) void k_reduce_partial(const double* plan
   }
 }
 
-__global__ __launch_bounds__(64) void k_reduce_final(const double* partials, int nblocks, double* out) {
+static __global__ __launch_bounds__(64) void k_reduce_final(const double* partials, int nblocks, double* out) {
   if (threadIdx.x < 4) {
     double v = 0.0;
     for (int b = 0; b < nblocks; b++) v += partials[4ll * b + threadIdx.x];
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(64) void k_reduce_final(const double* partials, int
 }
 
 // bubble sizes (cells per label) and equivalent-diameter histogram
-__global__ void k_label_sizes(const int* label, long long N, unsigned long long* sizes) {
+static __global__ void k_label_sizes(const int* label, long long N, unsigned long long* sizes) {
   for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
        c += (long long)gridDim.x * blockDim.x) {
     const int l = label[c];
@@ -169,7 +169,7 @@ __global__ void k_label_sizes(const int* label, long long N, unsigned long long*
   }
 }
 
-__global__ void k_histogram(const unsigned long long* sizes, const int* n_bubbles, int D, int nbins, double width,
+static __global__ void k_histogram(const unsigned long long* sizes, const int* n_bubbles, int D, int nbins, double width,
                             unsigned long long* counts) {
   const int nb = *n_bubbles;
   for (int b = 1 + blockIdx.x * blockDim.x + threadIdx.x; b <= nb; b += gridDim.x * blockDim.x) {

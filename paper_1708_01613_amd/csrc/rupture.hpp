@@ -1,0 +1,122 @@
+// rupture.hpp -- the film-rupture test (Sec. 2.1.5, eta_m criterion; Sec. 5,
+// Fig. plot), as a kernel of its own that runs after the step kernel.
+//
+// On every active barrier link (x, i) of a step from rupture_warmup on, the
+// FP64 second difference of the bulk pressure p0 = rho/3 + (G/6) psi^2 along
+// the link direction, D2 = p0(rho(x+e_i)) - 2 p0(rho(x)) + p0(rho(x-e_i)), is
+// tested for D2 >= 0; each hit appends (step, smaller owner, larger owner2) of
+// the link's two ends to the event log.  The densities are those of the state
+// entering the step, which the step kernel (or k_psi) leaves in a cell-linear
+// array (only at cells the refresh marked with kRhoBit).  The test walks the
+// list of cells that had barrier links at the refresh.  Keeping it out of the
+// step kernel keeps its sparse, divergent FP64 work off the streaming
+// kernel's critical path.
+#pragma once
+#include "maps.hpp"
+
+namespace flb {
+
+// A hit on link (x, i) unites the pair (k, k2) = (smaller owner, larger
+// owner2 of the two ends) in the alias union-find at once.  No test of this
+// step reads the aliases (the links to test are the mask, pruned before the
+// step), so the barrier still goes away only from the next step on; the
+// union-find keeps the smallest label as root, so the classes, their roots
+// and the number of successful unions do not depend on the order in which
+// the unions land.  A wavefront merges its lanes' identical pairs first, and
+// the log keeps one record per distinct (step, k, k2) of a wavefront until it
+// is full.
+template <class L, class T>
+__device__ __forceinline__ void rupture_cells(const StepArgs& a, unsigned bid, unsigned nb) {
+  Ctl* ctl = a.ctl;
+  if (ctl->stopped) return;
+  const long long step = ctl->steps;
+  if (!a.film_on || step < a.rupture_warmup) return;
+  const T* rho = (const T*)a.rho;
+  const double G64 = a.G, r064 = a.rho0;
+  const float g6 = (float)(G64 / 6.0), r0f = (float)r064;
+  const MapDims d{a.nx, a.nm, a.nz, (long long)a.nx * a.nm * a.nz};
+  const int lane = threadIdx.x & 63;
+  for_list(ctl->n_flagged, bid, nb, [&](unsigned idx, bool act) {
+        // every lane of the wavefront runs the loop below (inactive ones with
+        // an empty mask), so the pair merging sees the whole wavefront
+        const unsigned c = act ? (unsigned)a.flist[idx] : 0u;
+        const unsigned mk = act ? a.mask[c] & kLinkBits : 0u;
+        const ListCell q(d, c);
+        const T rc = mk ? rho[c] : T(1);
+        T psc = T(0);
+        if constexpr (sizeof(T) == 4) psc = psi_of(rc, r0f);
+        double pc = 0.0;
+        bool have_pc = false;
+        int2 oc = make_int2(0, 0);
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) {
+          if (!(mk & (1u << i))) continue;
+          const unsigned yp = q.nb(d, L::ex[i], L::em[i], L::ez[i]);
+          const unsigned ym = q.nb(d, -L::ex[i], -L::em[i], -L::ez[i]);
+          const T rp = rho[yp], rm = rho[ym];
+          bool hit = false;
+          if (sizeof(T) != 4 || !a.rupture_filter ||
+              d2_may_be_nonneg((float)rp, (float)rc, (float)rm, psi_of((float)rp, r0f), (float)psc,
+                               psi_of((float)rm, r0f), g6, r0f)) {
+            if (!have_pc) {
+              pc = p0_of((double)rc, G64, r064);
+              oc = a.own[c];
+              have_pc = true;
+            }
+            hit = p0_of((double)rp, G64, r064) - 2.0 * pc + p0_of((double)rm, G64, r064) >= 0.0;
+          }
+          int k = 0, k2 = 0;
+          if (hit) {
+            const int2 oy = a.own[yp];
+            k = min(oc.x, oy.x);
+            k2 = max(oc.y, oy.y);
+          }
+          // merge identical pairs of the wavefront, then one lane per pair
+          // unites, logs and counts
+          unsigned long long todo = __ballot(hit);
+          while (todo) {
+            const int ld = first_lane(todo);
+            const int k0 = __shfl(k, ld, 64), k20 = __shfl(k2, ld, 64);
+            if (lane == ld) {
+              ctl->step_events = 1;
+              if (uf_unite(a.alias, k0, k20)) {
+                atomicAdd((unsigned long long*)&ctl->n_ruptures, 1ull);
+                ctl->alias_dirty = 1;
+              }
+              if (__atomic_load_n(&ctl->ev_count, __ATOMIC_RELAXED) < a.ev_cap) {
+                const unsigned e = atomicAdd(&ctl->ev_count, 1u);
+                if (e < a.ev_cap) {
+                  long long* ev = a.events + 4ll * e;
+                  ev[0] = step;
+                  ev[1] = k0;
+                  ev[2] = k20;
+                  ev[3] = 0;
+                } else {
+                  ctl->ev_full = 1;
+                }
+              } else {
+                ctl->ev_full = 1;
+              }
+            }
+            if (hit && k == k0 && k2 == k20) hit = false;
+            todo = __ballot(hit);
+          }
+        }
+      });
+}
+
+template <class L, class T>
+__global__ __launch_bounds__(MAP_NT) void k_rupture(StepArgs a) {
+  rupture_cells<L, T>(a, blockIdx.x, gridDim.x);
+}
+
+// batched: workgroups [first[k], first[k+1]) test member k
+template <class L, class T>
+__global__ __launch_bounds__(MAP_NT) void k_rupture_batch(const StepArgs* __restrict__ tab,
+                                                          const int* __restrict__ first, int nmem) {
+  const int k = batch_member(first, nmem, blockIdx.x);
+  const StepArgs a = tab[k];
+  rupture_cells<L, T>(a, blockIdx.x - first[k], first[k + 1] - first[k]);
+}
+
+}  // namespace flb

@@ -1,0 +1,261 @@
+// server.hip -- a request loop that keeps foam simulations resident on the
+// device and advances them together (flb_server_* in include/foamlbm.h).
+//
+// Jobs queue in arrival order.  Each scheduling round admits queued jobs, in
+// order, while the device bytes of the admitted jobs stay within the pool
+// budget (and below the job limit), then advances every running job by the
+// same number of steps -- the chunk, shortened so that no job passes its last
+// step -- with batched launches, one batch per lattice type and storage, so
+// jobs that arrived at different times share every launch.  A job whose
+// steps are done is retired at the end of the round: its final density and
+// statistics are copied to host memory and its device memory is released, so
+// the next round can admit more.  A job's fields are exactly those of the
+// same job run alone.
+#include <deque>
+#include <map>
+
+#include "batch.hpp"
+
+using namespace flb_rt;
+
+namespace {
+
+struct Job {
+  int64_t id = 0;
+  flb_params p;
+  std::vector<flb_nucleus> nuc;
+  int64_t steps = 0, done = 0;
+  int32_t state = FLB_JOB_QUEUED;
+  flb_ctx* c = nullptr;
+  size_t bytes = 0;
+  std::vector<double> density;
+  flb_stats stats;
+  std::string err;
+};
+
+}  // namespace
+
+struct flb_server {
+  flb_server_config cfg;
+  flb_allocator al;
+  bool have_al = false;
+  hipStream_t st = nullptr;
+  int64_t next_id = 1;
+  size_t used = 0;
+  int64_t n_done = 0;
+  std::deque<Job*> queue;
+  std::vector<Job*> running;
+  std::map<int64_t, Job*> jobs;
+  flb_batch* view[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  std::vector<flb_ctx*> vm[2][3];
+};
+
+namespace {
+
+int admit(flb_server* s) {
+  while (!s->queue.empty() && (int)s->running.size() < s->cfg.max_jobs) {
+    Job* j = s->queue.front();
+    if (s->used + ctx_footprint(&j->p) > (size_t)s->cfg.pool_bytes) break;  // in order: wait for room
+    s->queue.pop_front();
+    int rc = flb_create(&j->p, s->have_al ? &s->al : nullptr, s->st, &j->c);
+    if (!rc) rc = flb_set_nuclei(j->c, j->nuc.data(), (int32_t)j->nuc.size());
+    if (rc) {
+      j->err = g_err;
+      if (j->c) flb_destroy(j->c);
+      j->c = nullptr;
+      j->state = FLB_JOB_FAILED;
+      continue;
+    }
+    j->bytes = j->c->bytes;
+    s->used += j->bytes;
+    j->state = FLB_JOB_RUNNING;
+    s->running.push_back(j);
+  }
+  return FLB_OK;
+}
+
+// batch views over the running jobs, rebuilt where membership changed
+int sync_views(flb_server* s) {
+  std::vector<flb_ctx*> want[2][3];
+  for (Job* j : s->running) want[j->c->D == 2 ? 0 : 1][j->c->p.storage].push_back(j->c);
+  for (int d = 0; d < 2; d++)
+    for (int t = 0; t < 3; t++) {
+      if (want[d][t] == s->vm[d][t] && (s->view[d][t] || want[d][t].empty())) continue;
+      batch_free(s->view[d][t]);
+      s->view[d][t] = nullptr;
+      s->vm[d][t] = want[d][t];
+      if (want[d][t].empty()) continue;
+      s->view[d][t] = batch_view(want[d][t], s->st, s->have_al ? &s->al : nullptr);
+      if (!s->view[d][t]) return fail(FLB_ENOMEM, "host allocation failed");
+      s->view[d][t]->graph_steps = s->cfg.graph_steps;
+    }
+  return FLB_OK;
+}
+
+void retire(flb_server* s, Job* j) {
+  j->density.resize((size_t)j->c->N);
+  int rc = flb_get_density(j->c, j->density.data(), j->density.size());
+  if (!rc) rc = flb_get_stats(j->c, &j->stats);
+  if (rc) {
+    j->err = g_err;
+    j->state = FLB_JOB_FAILED;
+  } else {
+    j->state = FLB_JOB_DONE;
+  }
+  s->used -= j->bytes;
+  flb_destroy(j->c);
+  j->c = nullptr;
+  s->n_done++;
+}
+
+}  // namespace
+
+extern "C" {
+
+void flb_server_default_config(flb_server_config* cfg) {
+  if (!cfg) return;
+  cfg->pool_bytes = (int64_t)64 << 30;
+  cfg->max_jobs = 256;
+  cfg->chunk_steps = 100;
+  cfg->graph_steps = 20;
+}
+
+int flb_server_create(const flb_server_config* cfg, const flb_allocator* alloc, void* hip_stream,
+                      flb_server** out) {
+  g_err.clear();
+  if (!out || !cfg) return fail(FLB_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (cfg->pool_bytes <= 0) return fail(FLB_EINVAL, "pool_bytes must be > 0");
+  if (cfg->max_jobs < 1 || cfg->max_jobs > (1 << 16)) return fail(FLB_EINVAL, "max_jobs must be in 1..65536");
+  if (cfg->chunk_steps < 1) return fail(FLB_EINVAL, "chunk_steps must be >= 1");
+  if (cfg->graph_steps < 0 || cfg->graph_steps > 4096) return fail(FLB_EINVAL, "graph_steps must be in 0..4096");
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(FLB_EINVAL, "allocator needs alloc and free");
+  flb_server* s = new (std::nothrow) flb_server();
+  if (!s) return fail(FLB_ENOMEM, "host allocation failed");
+  s->cfg = *cfg;
+  if (alloc) {
+    s->al = *alloc;
+    s->have_al = true;
+  }
+  s->st = (hipStream_t)hip_stream;
+  *out = s;
+  return FLB_OK;
+}
+
+int flb_server_submit(flb_server* s, const flb_params* p, const flb_nucleus* nuc, int32_t n, int64_t steps,
+                      int64_t* id) {
+  if (!s || !p || !id) return fail(FLB_EINVAL, "NULL argument");
+  if (n < 0 || (n > 0 && !nuc)) return fail(FLB_EINVAL, "bad nuclei array");
+  if (steps < 0) return fail(FLB_EINVAL, "steps must be >= 0");
+  int rc = validate(p);
+  if (rc) return rc;
+  const size_t fp = ctx_footprint(p);
+  if (fp > (size_t)s->cfg.pool_bytes)
+    return fail(FLB_EBUSY, "job needs %zu device bytes, more than the pool of %lld", fp,
+                (long long)s->cfg.pool_bytes);
+  Job* j = new (std::nothrow) Job();
+  if (!j) return fail(FLB_ENOMEM, "host allocation failed");
+  j->id = s->next_id++;
+  j->p = *p;
+  j->nuc.assign(nuc, nuc + n);
+  j->steps = steps;
+  memset(&j->stats, 0, sizeof j->stats);
+  s->jobs[j->id] = j;
+  s->queue.push_back(j);
+  *id = j->id;
+  return FLB_OK;
+}
+
+int flb_server_pump(flb_server* s, int32_t* n_running, int32_t* n_queued, int64_t* n_done) {
+  if (!s) return fail(FLB_EINVAL, "server is NULL");
+  int rc = admit(s);
+  if (rc) return rc;
+  // jobs of zero steps finish at once
+  for (size_t k = 0; k < s->running.size();) {
+    if (s->running[k]->steps == 0) {
+      retire(s, s->running[k]);
+      s->running.erase(s->running.begin() + (long)k);
+    } else {
+      k++;
+    }
+  }
+  if (!s->running.empty()) {
+    int64_t r = s->cfg.chunk_steps;
+    for (Job* j : s->running) r = std::min<int64_t>(r, j->steps - j->done);
+    rc = sync_views(s);
+    if (rc) return rc;
+    for (int d = 0; d < 2 && !rc; d++)
+      for (int t = 0; t < 3 && !rc; t++)
+        if (s->view[d][t]) rc = FLB_BATCH_DISPATCH(s->view[d][t], batch_steps, s->view[d][t], r);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->st));
+    std::vector<Job*> still;
+    for (Job* j : s->running) {
+      j->done += r;
+      if (j->done >= j->steps) retire(s, j);
+      else still.push_back(j);
+    }
+    s->running.swap(still);
+  }
+  if (n_running) *n_running = (int32_t)s->running.size();
+  if (n_queued) *n_queued = (int32_t)s->queue.size();
+  if (n_done) *n_done = s->n_done;
+  return FLB_OK;
+}
+
+int flb_server_job(flb_server* s, int64_t id, int32_t* state, int64_t* steps_done) {
+  if (!s) return fail(FLB_EINVAL, "server is NULL");
+  auto it = s->jobs.find(id);
+  if (it == s->jobs.end()) return fail(FLB_EINVAL, "unknown job %lld", (long long)id);
+  if (state) *state = it->second->state;
+  if (steps_done) *steps_done = it->second->done;
+  return FLB_OK;
+}
+
+int flb_server_result(flb_server* s, int64_t id, double* density, size_t n, flb_stats* stats) {
+  if (!s) return fail(FLB_EINVAL, "server is NULL");
+  auto it = s->jobs.find(id);
+  if (it == s->jobs.end()) return fail(FLB_EINVAL, "unknown job %lld", (long long)id);
+  Job* j = it->second;
+  if (j->state == FLB_JOB_FAILED) return fail(FLB_EHIP, "job %lld failed: %s", (long long)id, j->err.c_str());
+  if (j->state != FLB_JOB_DONE) return fail(FLB_EINVAL, "job %lld is not done", (long long)id);
+  if (density) {
+    if (n != j->density.size()) return fail(FLB_EINVAL, "n must be %zu", j->density.size());
+    memcpy(density, j->density.data(), sizeof(double) * n);
+  }
+  if (stats) *stats = j->stats;
+  return FLB_OK;
+}
+
+int flb_server_release(flb_server* s, int64_t id) {
+  if (!s) return fail(FLB_EINVAL, "server is NULL");
+  auto it = s->jobs.find(id);
+  if (it == s->jobs.end()) return fail(FLB_EINVAL, "unknown job %lld", (long long)id);
+  Job* j = it->second;
+  if (j->state == FLB_JOB_QUEUED || j->state == FLB_JOB_RUNNING)
+    return fail(FLB_EBUSY, "job %lld is still queued or running", (long long)id);
+  s->jobs.erase(it);
+  delete j;
+  return FLB_OK;
+}
+
+int flb_server_usage(flb_server* s, int64_t* used_bytes, int64_t* pool_bytes) {
+  if (!s) return fail(FLB_EINVAL, "server is NULL");
+  if (used_bytes) *used_bytes = (int64_t)s->used;
+  if (pool_bytes) *pool_bytes = s->cfg.pool_bytes;
+  return FLB_OK;
+}
+
+void flb_server_destroy(flb_server* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->st);
+  for (int d = 0; d < 2; d++)
+    for (int t = 0; t < 3; t++) batch_free(s->view[d][t]);
+  for (auto& kv : s->jobs) {
+    if (kv.second->c) flb_destroy(kv.second->c);
+    delete kv.second;
+  }
+  delete s;
+}
+
+}  // extern "C"

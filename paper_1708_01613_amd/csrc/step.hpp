@@ -31,8 +31,10 @@ struct StepArgs {
   double psi_bar;        // psi(rho_liquid), used when psi_bar_mode == 0
   int psi_bar_mode;
   int film_on, rupture_warmup, on_rupture;
+  int rupture_filter;    // 1: FP32 sign filter before the FP64 rupture test
   const uint8_t* flag;   // per cell: 1 if it has candidate barrier links
-  const uint32_t* mask;  // per cell: candidate barrier links, bit i = direction i
+  const uint32_t* mask;  // per cell: active barrier links (bit i = direction i) and kRhoBit
+  const int* flist;      // cells with barrier links at the last refresh (ctl->n_flagged)
   const int2* own;       // per cell: (smallest, largest) nearest bubble label
   int* alias;            // union-find parents over labels
   unsigned long long buf_bytes;  // bytes of one population buffer
@@ -58,6 +60,51 @@ __device__ __forceinline__ int uf_root(const int* __restrict__ par, int a) {
 }
 
 // (low, high) alias roots of a cell's nearest bubbles
+// ---- union-find with roots at the smallest index ----
+// Parents only ever move to smaller indices (a root is hooked under a smaller
+// root; path halving replaces a parent by its own parent), so every pointer
+// stays an ancestor and concurrent finds remain correct.  Roots are written
+// only by the hooking CAS.
+__device__ __forceinline__ int uf_find_live(int* par, int a) {
+  int p = __atomic_load_n(&par[a], __ATOMIC_RELAXED);
+  while (p != a) {
+    a = p;
+    p = __atomic_load_n(&par[a], __ATOMIC_RELAXED);
+  }
+  return a;
+}
+
+__device__ __forceinline__ int uf_find_halve(int* par, int a) {
+  int cur = __atomic_load_n(&par[a], __ATOMIC_RELAXED);
+  if (cur == a) return a;
+  int prev = a, next;
+  while (cur > (next = __atomic_load_n(&par[cur], __ATOMIC_RELAXED))) {
+    __atomic_store_n(&par[prev], next, __ATOMIC_RELAXED);
+    prev = cur;
+    cur = next;
+  }
+  return cur;
+}
+
+// unite the sets of a and b, hooking the larger root under the smaller one;
+// true if this call did the hook.  The resulting partition and its roots do
+// not depend on the order in which concurrent calls land.
+__device__ inline bool uf_unite(int* par, int a, int b) {
+  while (true) {
+    a = uf_find_halve(par, a);
+    b = uf_find_halve(par, b);
+    if (a == b) return false;
+    if (a < b) {
+      int t = a;
+      a = b;
+      b = t;
+    }
+    const int old = atomicCAS(&par[a], a, b);
+    if (old == a) return true;
+    a = old;
+  }
+}
+
 __device__ __forceinline__ int2 root_pair(const int* __restrict__ alias, int2 o) {
   int a = uf_root(alias, o.x), b = uf_root(alias, o.y);
   return a < b ? make_int2(a, b) : make_int2(b, a);
@@ -106,35 +153,28 @@ __device__ __forceinline__ void load_pulled(const void* __restrict__ src, const 
     out[i] = pop_ld<L, S>(src, g, i, xs[1 + L::ex[i]], ms[1 + L::em[i]], zs[1 + L::ez[i]]);
 }
 
-// FP64 second difference of p0 along every active barrier link of a cell, and
-// the rupture events it raises (Sec. 2.1.5, eta_m equation; Sec. 4)
-template <class L, int LH, int LW, class T>
-__device__ __forceinline__ void rupture_test(const StepArgs& a, Ctl* ctl, long long step, unsigned bar, int x, int m, int zc,
-                             long long c, const T (&s_rho)[4][LH][LW], const int (&sl)[3], int lm1, int lx1) {
-  const double G64 = a.G, r064 = a.rho0;
-  const double pc = p0_of((double)s_rho[sl[1]][lm1][lx1], G64, r064);
-  const int2 oc = a.own[c];
-#pragma unroll
-  for (int i = 1; i < L::Q; i++) {
-    if (!(bar & (1u << i))) continue;
-    const int o = (i & 1) ? i + 1 : i - 1;  // opposite direction
-    const double rp = (double)s_rho[sl[1 + L::ez[i]]][lm1 + L::em[i]][lx1 + L::ex[i]];
-    const double rm = (double)s_rho[sl[1 + L::ez[o]]][lm1 + L::em[o]][lx1 + L::ex[o]];
-    const double d2 = p0_of(rp, G64, r064) - 2.0 * pc + p0_of(rm, G64, r064);
-    if (d2 >= 0.0) {
-      const int yx = wrap_any(x + L::ex[i], a.nx), ym = wrap_any(m + L::em[i], a.nm),
-                yz = wrap_any(zc + L::ez[i], a.nz);
-      const int2 oy = a.own[yx + (long long)a.nx * (ym + (long long)a.nm * yz)];
-      const unsigned e = atomicAdd(&ctl->ev_count, 1u);
-      if (e < a.ev_cap) {
-        long long* ev = a.events + 4ll * e;
-        ev[0] = step;
-        ev[1] = min(oc.x, oy.x);
-        ev[2] = max(oc.y, oy.y);
-        ev[3] = 0;
-      }
-    }
-  }
+// Sign filter for the FP64 rupture test, FP32 compute types only.  From the
+// FP32 rho and psi already staged for the force, D2 = p0(r+) - 2 p0(rc) +
+// p0(r-) with p0 = rho/3 + (G/6) psi^2 is formed in FP32 together with a bound
+// on its distance from the FP64 value of the same formula at the same FP32
+// densities.  The bound is 64 ulp of the sum of the magnitudes of every term,
+// where each psi also carries its own evaluation error (at most
+// rho0 (|rho/rho0| + 5) ulp for an exp accurate to 2 ulp); that is several
+// times what the few FP32 roundings involved can reach.  A value below minus
+// the bound proves the FP64 value negative, so no event is possible and the
+// FP64 evaluation is skipped; anything else goes to the FP64 formula, which
+// alone decides.  Densities outside (0, 64 rho0] always go to FP64.
+__device__ __forceinline__ bool d2_may_be_nonneg(float rp, float rc, float rm, float pp, float pc, float pm,
+                                                 float g6, float rho0) {
+  const float lim = 64.0f * rho0;
+  if (!(rp > 0.0f && rc > 0.0f && rm > 0.0f && rp <= lim && rc <= lim && rm <= lim)) return true;
+  const float d2 = ((rp + rm) - 2.0f * rc) * (1.0f / 3.0f) + g6 * ((pp * pp + pm * pm) - 2.0f * pc * pc);
+  const float ag = fabsf(g6);
+  const float ep = 2.0f * pp * (rp + 5.0f * rho0), ec = 2.0f * pc * (rc + 5.0f * rho0),
+              em = 2.0f * pm * (rm + 5.0f * rho0);
+  const float mag = (rp + 2.0f * rc + rm) * (1.0f / 3.0f) +
+                    ag * ((pp * pp + 2.0f * pc * pc + pm * pm) + (ep + 2.0f * ec + em));
+  return d2 >= -64.0f * 5.9604645e-08f * mag;
 }
 
 // Population access of the step kernel: one buffer resource per population
@@ -227,7 +267,7 @@ struct PopIO {
 // FP64 mass / momentum partials of the state entering a step: every
 // workgroup reduces its lanes' partials and writes them to its slot.
 template <int NT>
-__device__ __forceinline__ void step_partials(const StepArgs& a, double (&red)[NT / 64][4], double acc_m,
+__device__ __forceinline__ void step_partials(const StepArgs& a, int slot, double (&red)[NT / 64][4], double acc_m,
                                               double acc_x, double acc_y, double acc_z) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -247,19 +287,18 @@ __device__ __forceinline__ void step_partials(const StepArgs& a, double (&red)[N
   if (threadIdx.x < 4) {
     double sum = 0.0;
     for (int wv = 0; wv < NT / 64; wv++) sum += red[wv][threadIdx.x];
-    a.partials[4ll * blockIdx.x + threadIdx.x] = sum;
+    a.partials[4ll * slot + threadIdx.x] = sum;
   }
 }
 
-// One workgroup, launched after every step kernel on the same stream (the
-// kernel boundary orders it after all partials and rupture events): totals
-// in workgroup order (deterministic), non-finite check, the step's rupture
-// unions, the stop flag, and the step counter that selects the A/B buffer.
+// One workgroup, the last launch of every step on the stream (after the step
+// kernel, the rupture test and the mask pruning): FP64 totals in workgroup
+// order (deterministic), the non-finite check, the stop flag, and the step
+// counter that selects the A/B buffer.
 constexpr int FIN_NT = 1024;
-__global__ __launch_bounds__(FIN_NT) void k_step_finish(StepArgs a, int nblk) {
+__device__ __forceinline__ void step_finish(const StepArgs& a, int nblk, double (&red)[FIN_NT / 64][4]) {
   Ctl* ctl = a.ctl;
   if (ctl->stopped) return;
-  __shared__ double red[FIN_NT / 64][4];
   double t[4] = {0.0, 0.0, 0.0, 0.0};
   // thread t adds workgroups t, t + FIN_NT, ... in that order; four rows are
   // loaded ahead of their additions to keep loads in flight
@@ -294,24 +333,43 @@ __global__ __launch_bounds__(FIN_NT) void k_step_finish(StepArgs a, int nblk) {
     ctl->mom[1] = tot[2];
     ctl->mom[2] = tot[3];
     if (!isfinite(tot[0])) ctl->failed = 1;
-    const unsigned e1 = min(ctl->ev_count, a.ev_cap);
-    bool any = false;
-    for (unsigned e = ctl->ev_start; e < e1; e++) {
-      any = true;
-      const int ra = uf_root(a.alias, (int)a.events[4ll * e + 1]);
-      const int rb = uf_root(a.alias, (int)a.events[4ll * e + 2]);
-      if (ra != rb) {
-        if (ra < rb) a.alias[rb] = ra;
-        else a.alias[ra] = rb;
-        ctl->n_ruptures += 1;
-        ctl->alias_dirty = 1;
-      }
-    }
-    if (ctl->ev_count > e1) any = true;
-    ctl->ev_start = ctl->ev_count;
+  }
+  if (threadIdx.x == 0) {
+    // the rupture kernel of this step has applied its unions and the mask
+    // pruning has consumed them; the flags start clear for the next step
+    const bool any = ctl->step_events != 0;
+    ctl->step_events = 0;
+    ctl->alias_dirty = 0;
     ctl->steps = ctl->steps + 1;
     if (any && a.on_rupture) ctl->stopped = 1;
   }
+}
+
+static __global__ __launch_bounds__(FIN_NT) void k_step_finish(StepArgs a, int nblk) {
+  __shared__ double red[FIN_NT / 64][4];
+  step_finish(a, nblk, red);
+}
+
+// ---- batched launches: many lattices of one lattice type and storage ----
+// Workgroups [first[k], first[k+1]) of a batched step launch advance member k
+// with its own arguments tab[k]; the finisher launch has one workgroup per
+// member.  A member is found by binary search over `first` (nmem + 1 entries).
+__device__ __forceinline__ int batch_member(const int* __restrict__ first, int nmem, int b) {
+  int lo = 0, hi = nmem;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+static __global__ __launch_bounds__(FIN_NT) void k_step_finish_batch(const StepArgs* __restrict__ tab,
+                                                              const int* __restrict__ first) {
+  __shared__ double red[FIN_NT / 64][4];
+  const int k = blockIdx.x;
+  const StepArgs a = tab[k];
+  step_finish(a, first[k + 1] - first[k], red);
 }
 
 // Plane loop: iteration k loads plane z0-1+k (k <= L+1) into one register
@@ -345,7 +403,7 @@ struct StepBlock {
   Ctl* ctl;
   long long step;
   int nx, nm, nz, x0, m0, z0, L_, TXe, TMe, lx, lm, x, m, xc, mc, gx, gm, hx, hm;
-  bool act, has_halo, film, test_rupture, tau_one, alias_dirty;
+  bool act, has_halo, film, test_rupture, tau_one;
   T G, rho0, tau, omega, psi_bar;
   double acc_m = 0.0, acc_x = 0.0, acc_y = 0.0, acc_z = 0.0;
 
@@ -424,10 +482,9 @@ struct StepBlock {
     }
     const int lm1 = lm + HM, lx1 = lx + 1;
     const T psic = sm.psi[sl[1]][lm1][lx1];
-    unsigned bar = 0;
-    // candidate links of the last refresh are exact until a rupture unites
-    // two bubbles; only then are aliases resolved link by link
-    if (flag) bar = alias_dirty ? active_links<L>(a, x, m, zc, c) : flag;
+    // the mask holds exactly the active barrier links: it is rebuilt at every
+    // refresh and pruned after every step whose ruptures united bubbles
+    const unsigned bar = flag & kLinkBits;
     const T pbar = a.psi_bar_mode == 0 ? psi_bar : psic;
     T fx = T(0), fm = T(0), fz = T(0);
 #pragma unroll
@@ -474,7 +531,9 @@ struct StepBlock {
     }
     const T feq0 = rho - feq_moving;
     io.store_at(0, vo0, tau_one ? feq0 : f[0] - (f[0] - feq0) * omega);
-    if (test_rupture && bar) rupture_test<L, LH, LW, T>(a, ctl, step, bar, x, m, zc, c, sm.rho, sl, lm1, lx1);
+    // the rupture test runs in its own kernel after this one, on the
+    // densities of the state entering the step
+    if (test_rupture && act && (flag & kRhoBit)) ((T*)a.rho)[c] = rho;
     const double keep = act ? 1.0 : 0.0;
     acc_m += keep * (double)rho;
     acc_x += keep * (double)jx;
@@ -482,12 +541,12 @@ struct StepBlock {
     acc_z += keep * (double)(L::HAS_M ? jz : T(0));
   }
 
-  __device__ __forceinline__ void run() {
+  // b: workgroup index within this lattice's launch of nblk workgroups
+  __device__ __forceinline__ void run(const int b_launch, const int nblk) {
     ctl = a.ctl;
     step = ctl->steps;
     io.init(a.buf[step & 1], a.buf[(step + 1) & 1], a.geo, a.buf_bytes);
-    int b = blockIdx.x;
-    const int nblk = gridDim.x;
+    int b = b_launch;
     if (a.xcd_chunks > 1) b = (b % a.xcd_chunks) * (nblk / a.xcd_chunks) + b / a.xcd_chunks;
     const int tx = b % a.tiles_x;
     const int t2 = b / a.tiles_x;
@@ -537,7 +596,6 @@ struct StepBlock {
     omega = T(1) / (T)a.tau;
     tau_one = a.tau == 1.0;
     film = a.film_on != 0;
-    alias_dirty = film && ctl->alias_dirty != 0;
     test_rupture = film && step >= a.rupture_warmup;
     psi_bar = (T)a.psi_bar;
 
@@ -555,10 +613,9 @@ struct StepBlock {
     } else {
       halo_loop();
     }
-    epilogue(nblk);
+    // partials slot: the launch-order index, which the finisher sums in order
+    step_partials<NT>(a, b_launch, sm.red, acc_m, acc_x, acc_y, acc_z);
   }
-
-  __device__ __forceinline__ void epilogue(int) { step_partials<NT>(a, sm.red, acc_m, acc_x, acc_y, acc_z); }
 };
 
 template <class L, class S, int TX, int TM, bool BUF>
@@ -567,7 +624,20 @@ __global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF>::NT)) void k_step(Ste
   __shared__ typename SB::Smem sm;
   if (a.ctl->stopped) return;
   SB blk(a, sm);
-  blk.run();
+  blk.run(blockIdx.x, gridDim.x);
+}
+
+template <class L, class S, int TX, int TM, bool BUF>
+__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF>::NT)) void k_step_batch(const StepArgs* __restrict__ tab,
+                                                                                  const int* __restrict__ first,
+                                                                                  int nmem) {
+  using SB = StepBlock<L, S, TX, TM, BUF>;
+  __shared__ typename SB::Smem sm;
+  const int k = batch_member(first, nmem, blockIdx.x);
+  const StepArgs a = tab[k];
+  if (a.ctl->stopped) return;
+  SB blk(a, sm);
+  blk.run(blockIdx.x - first[k], first[k + 1] - first[k]);
 }
 
 }  // namespace flb

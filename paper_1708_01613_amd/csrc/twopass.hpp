@@ -36,7 +36,6 @@ struct CellArray {
   __device__ __forceinline__ T operator[](unsigned c) const {
     if constexpr (BUF) {
       if constexpr (sizeof(T) == 8) {
-        typedef unsigned u2 __attribute__((ext_vector_type(2)));
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, c * 8u, 0u, 0));
       } else {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, c * 4u, 0u, 0));
@@ -117,11 +116,7 @@ __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
     return (unsigned)(xs[1 + ex] + nx * (ms[1 + em] + nm * zs[1 + ez]));
   };
   const T psic = psi[c];
-  unsigned bar = 0;
-  if (a.film_on && act) {
-    const unsigned cand = a.mask[c];
-    if (cand) bar = ctl->alias_dirty ? active_links<L>(a, xc, m, z, c) : cand;
-  }
+  const unsigned bar = (a.film_on && act) ? a.mask[c] & kLinkBits : 0u;  // exact active links
   const T pbar = a.psi_bar_mode == 0 ? (T)a.psi_bar : psic;
   T fx = T(0), fm = T(0), fz = T(0);
 #pragma unroll
@@ -169,33 +164,9 @@ __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
   const T feq0 = rho - feq_moving;
   io.store_at(0, vo0, tau_one ? feq0 : f[0] - (f[0] - feq0) * omega);
 
-  if (bar && a.film_on && step >= a.rupture_warmup) {
-    // FP64 second difference of p0 along every active barrier link
-    const T* rhoa = (const T*)a.rho;
-    const double G64 = a.G, r064 = a.rho0;
-    const double pc = p0_of((double)rho, G64, r064);
-    const int2 oc = a.own[c];
-#pragma unroll
-    for (int i = 1; i < Q; i++) {
-      if (!(bar & (1u << i))) continue;
-      const unsigned yp = nb(L::ex[i], L::em[i], L::ez[i]);
-      const unsigned ym = nb(-L::ex[i], -L::em[i], -L::ez[i]);
-      const double d2 = p0_of((double)rhoa[yp], G64, r064) - 2.0 * pc + p0_of((double)rhoa[ym], G64, r064);
-      if (d2 >= 0.0) {
-        const int2 oy = a.own[yp];
-        const unsigned e = atomicAdd(&ctl->ev_count, 1u);
-        if (e < a.ev_cap) {
-          long long* ev = a.events + 4ll * e;
-          ev[0] = step;
-          ev[1] = min(oc.x, oy.x);
-          ev[2] = max(oc.y, oy.y);
-          ev[3] = 0;
-        }
-      }
-    }
-  }
+  // the rupture test runs in its own kernel, on the rho array of k_psi
   const double keep = act ? 1.0 : 0.0;
-  step_partials<TP_NT>(a, red, keep * (double)rho, keep * (double)jx, keep * (double)(L::HAS_M ? jm : jz),
+  step_partials<TP_NT>(a, blockIdx.x, red, keep * (double)rho, keep * (double)jx, keep * (double)(L::HAS_M ? jm : jz),
                        keep * (double)(L::HAS_M ? jz : T(0)));
 }
 

@@ -39,6 +39,7 @@ class flb_params(C.Structure):
         ("rho_th", C.c_double),
         ("psi_bar_mode", C.c_int32), ("rupture_warmup", C.c_int32),
         ("on_rupture", C.c_int32), ("velocity_mode", C.c_int32),
+        ("rupture_filter", C.c_int32),
     ]
 
 
@@ -51,6 +52,13 @@ class flb_stats(C.Structure):
                 ("n_bubbles", C.c_int32), ("n_ruptures", C.c_int32), ("stopped", C.c_int32),
                 ("events_lost", C.c_int32)]
 
+
+class flb_server_config(C.Structure):
+    _fields_ = [("pool_bytes", C.c_int64), ("max_jobs", C.c_int32), ("chunk_steps", C.c_int32),
+                ("graph_steps", C.c_int32)]
+
+
+FLB_JOB_QUEUED, FLB_JOB_RUNNING, FLB_JOB_DONE, FLB_JOB_FAILED = 0, 1, 2, 3
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -88,9 +96,31 @@ _SIGS = {
     "flb_get_rupture_events": (C.c_int, [_CTX, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
     "flb_set_tuning": (C.c_int, [_CTX, C.c_int32, C.c_int32, C.c_int32]),
     "flb_get_tuning": (C.c_int, [_CTX] + [C.POINTER(C.c_int32)] * 6),
-    "flb_time_steps": (C.c_int, [_CTX, C.c_int64, C.c_int32, C.POINTER(C.c_double)]),
+    "flb_time_steps": (C.c_int, [_CTX, C.c_int64, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "flb_destroy": (None, [_CTX]),
     "flb_last_error": (C.c_char_p, []),
+    "flb_batch_create": (C.c_int, [C.POINTER(flb_params), C.c_int32, C.POINTER(flb_allocator), C.c_void_p,
+                                   C.POINTER(C.c_void_p)]),
+    "flb_batch_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "flb_batch_member": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(_CTX)]),
+    "flb_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "flb_batch_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int32, C.c_int32]),
+    "flb_batch_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "flb_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
+    "flb_batch_time_steps": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double)]),
+    "flb_batch_destroy": (None, [C.c_void_p]),
+    "flb_server_default_config": (None, [C.POINTER(flb_server_config)]),
+    "flb_server_create": (C.c_int, [C.POINTER(flb_server_config), C.POINTER(flb_allocator), C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "flb_server_submit": (C.c_int, [C.c_void_p, C.POINTER(flb_params), C.POINTER(flb_nucleus), C.c_int32,
+                                    C.c_int64, C.POINTER(C.c_int64)]),
+    "flb_server_pump": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "flb_server_job": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "flb_server_result": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_size_t, C.POINTER(flb_stats)]),
+    "flb_server_release": (C.c_int, [C.c_void_p, C.c_int64]),
+    "flb_server_usage": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "flb_server_destroy": (None, [C.c_void_p]),
 }
 EXPORTED = tuple(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
@@ -169,7 +199,25 @@ class Sim:
         check(flb_create(C.byref(p), alloc, C.c_void_p(self.stream.cuda_stream), C.byref(h)), "flb_create")
         self.h = h
 
+    @classmethod
+    def _member(cls, handle, params, owner):
+        """A borrowed view of a batch member (the batch owns the context)."""
+        self = cls.__new__(cls)
+        self.params = params
+        p = params
+        self.D = 2 if p.lattice == FLB_D2Q9 else 3
+        self.Q = 9 if self.D == 2 else 19
+        self.N = p.nx * p.ny * p.nz
+        self.shape = (p.ny, p.nx) if self.D == 2 else (p.nz, p.ny, p.nx)
+        self.stream = owner.stream
+        self._owner = owner
+        self.h = handle
+        return self
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self.h = None  # owned by its batch
+            return
         if getattr(self, "h", None) is not None and self.h.value:
             flb_destroy(self.h)
             self.h = None
@@ -256,10 +304,13 @@ class Sim:
         check(flb_get_tuning(self.h, *[C.byref(x) for x in v]), "flb_get_tuning")
         return dict(zip(("tile", "lz", "xcd", "n_tiles", "tile_x", "tile_m"), (x.value for x in v)))
 
-    def time_steps(self, n, refresh=True):
+    def time_steps(self, n, refresh=True, kernel=False):
+        """Milliseconds for n steps; with kernel=True, (total, step-kernel sum)."""
         ms = C.c_double(0.0)
-        check(flb_time_steps(self.h, int(n), int(bool(refresh)), C.byref(ms)), "flb_time_steps")
-        return ms.value
+        kms = C.c_double(0.0)
+        check(flb_time_steps(self.h, int(n), int(bool(refresh)), C.byref(ms), C.byref(kms) if kernel else None),
+              "flb_time_steps")
+        return (ms.value, kms.value) if kernel else ms.value
 
     def stats(self):
         s = flb_stats()
@@ -270,3 +321,161 @@ class Sim:
 
 def psi_liquid(rho_liquid, rho0=1.0):
     return rho0 * (1.0 - math.exp(-rho_liquid / rho0))
+
+
+class Batch:
+    """Many lattices of one lattice type and storage advanced together
+    (batched launches, replayed from captured HIP graphs).  `members` is a
+    list of parameter dicts; `batch.members[k]` is a Sim view of member k."""
+
+    def __init__(self, members, stream=None, use_torch_memory=True):
+        import torch
+
+        plist = [default_params(**m) for m in members]
+        n = len(plist)
+        arr = (flb_params * n)(*plist)
+        dev = torch.cuda.current_device()
+        # a stream of its own (default priority): graphs cannot be captured on
+        # the null stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(dev)
+        self._keep = None
+        alloc = None
+        if use_torch_memory:
+            al, self._keep = _torch_allocator(dev)
+            alloc = C.byref(al)
+            self._al = al
+        h = C.c_void_p()
+        check(flb_batch_create(arr, n, alloc, C.c_void_p(self.stream.cuda_stream), C.byref(h)), "flb_batch_create")
+        self.h = h
+        self.members = []
+        for k in range(n):
+            mh = _CTX()
+            check(flb_batch_member(self.h, k, C.byref(mh)), "flb_batch_member")
+            self.members.append(Sim._member(mh, plist[k], self))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            for m in self.members:
+                m.h = None
+            flb_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.members)
+
+    def step(self, n=1):
+        return check(flb_batch_step(self.h, int(n)), "flb_batch_step")
+
+    def set_tuning(self, tile=-1, target=0, xcd=-1, graph_steps=-1):
+        check(flb_batch_set_tuning(self.h, tile, target, xcd, graph_steps), "flb_batch_set_tuning")
+
+    def tuning(self):
+        t, x, g, nt = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        tg = C.c_int64()
+        check(flb_batch_get_tuning(self.h, C.byref(t), C.byref(tg), C.byref(x), C.byref(g), C.byref(nt)),
+              "flb_batch_get_tuning")
+        return dict(tile=t.value, target=tg.value, xcd=x.value, graph_steps=g.value, n_tiles=nt.value)
+
+    def autotune(self, reps=5):
+        ms = C.c_double(0.0)
+        check(flb_batch_autotune(self.h, int(reps), C.byref(ms)), "flb_batch_autotune")
+        return ms.value
+
+    def time_steps(self, n):
+        ms = C.c_double(0.0)
+        check(flb_batch_time_steps(self.h, int(n), C.byref(ms)), "flb_batch_time_steps")
+        return ms.value
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+def _nuclei_array(nuclei):
+    arr = np.asarray(nuclei, np.float64).reshape(-1, 4)
+    buf = (flb_nucleus * max(arr.shape[0], 1))()
+    for k in range(arr.shape[0]):
+        buf[k] = flb_nucleus(*arr[k])
+    return buf, arr.shape[0]
+
+
+class Server:
+    """Resident foam jobs advanced together (continuous batching): submit()
+    queues a job, pump() runs one scheduling round, result() returns the final
+    density and statistics of a finished job."""
+
+    def __init__(self, pool_bytes=None, max_jobs=None, chunk_steps=None, graph_steps=None, stream=None,
+                 use_torch_memory=True):
+        import torch
+
+        cfg = flb_server_config()
+        flb_server_default_config(C.byref(cfg))
+        for k, v in (("pool_bytes", pool_bytes), ("max_jobs", max_jobs), ("chunk_steps", chunk_steps),
+                     ("graph_steps", graph_steps)):
+            if v is not None:
+                setattr(cfg, k, int(v))
+        self.cfg = cfg
+        dev = torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.Stream(dev)
+        self._keep = None
+        alloc = None
+        if use_torch_memory:
+            al, self._keep = _torch_allocator(dev)
+            alloc = C.byref(al)
+            self._al = al
+        h = C.c_void_p()
+        check(flb_server_create(C.byref(cfg), alloc, C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+              "flb_server_create")
+        self.h = h
+        self._shape = {}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            flb_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, steps, nuclei, **params):
+        p = default_params(**params)
+        buf, n = _nuclei_array(nuclei)
+        jid = C.c_int64()
+        check(flb_server_submit(self.h, C.byref(p), buf, n, int(steps), C.byref(jid)), "flb_server_submit")
+        self._shape[jid.value] = (p.ny, p.nx) if p.lattice == FLB_D2Q9 else (p.nz, p.ny, p.nx)
+        return jid.value
+
+    def pump(self):
+        r, q, d = C.c_int32(), C.c_int32(), C.c_int64()
+        check(flb_server_pump(self.h, C.byref(r), C.byref(q), C.byref(d)), "flb_server_pump")
+        return r.value, q.value, d.value
+
+    def state(self, jid):
+        st, done = C.c_int32(), C.c_int64()
+        check(flb_server_job(self.h, int(jid), C.byref(st), C.byref(done)), "flb_server_job")
+        return st.value, done.value
+
+    def result(self, jid):
+        shape = self._shape[jid]
+        out = np.empty(int(np.prod(shape)), np.float64)
+        s = flb_stats()
+        check(flb_server_result(self.h, int(jid), out.ctypes.data_as(C.c_void_p), out.size, C.byref(s)),
+              "flb_server_result")
+        return out.reshape(shape), dict(mass=s.mass, step=s.step, n_bubbles=s.n_bubbles, n_ruptures=s.n_ruptures)
+
+    def release(self, jid):
+        check(flb_server_release(self.h, int(jid)), "flb_server_release")
+        self._shape.pop(jid, None)
+
+    def usage(self):
+        u, p = C.c_int64(), C.c_int64()
+        check(flb_server_usage(self.h, C.byref(u), C.byref(p)), "flb_server_usage")
+        return u.value, p.value

@@ -42,9 +42,10 @@ def test_params_default_and_validation_without_device():
     p = F.default_params()
     assert (p.lattice, p.storage, p.nx, p.ny, p.nz) == (0, 1, 64, 64, 1)
     assert abs(p.rho_th - 0.6931471805599453) < 1e-16 and p.k_own == 10 and p.zone_width == 6
+    assert p.rupture_filter == 1
     h = C.c_void_p()
     bad = [dict(tau=0.5), dict(lattice=2), dict(nx=0), dict(zone_width=16), dict(k_own=0),
-           dict(storage=3), dict(rho0=0.0), dict(psi_bar_mode=2)]
+           dict(storage=3), dict(rho0=0.0), dict(psi_bar_mode=2), dict(rupture_filter=2)]
     for kw in bad:
         q = F.default_params(**kw)
         rc = F.flb_create(C.byref(q), None, None, C.byref(h))

@@ -1,0 +1,124 @@
+"""Batched launches: every member of a batch advances exactly as it does
+alone (marked gpu).  Results of the step are bit-identical because a cell's
+arithmetic does not depend on the tiling or on which launch carries it; the
+FP64 totals may differ in the last bits (another workgroup partition)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def flb():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1708_01613_amd import foamlbm
+
+    return foamlbm
+
+
+def _say(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _two_bubbles(nx, ny, R, gap):
+    cx, cy = nx / 2.0, ny / 2.0
+    return [[cx - R - gap / 2 - 0.5, cy, 0, R], [cx + R + gap / 2 + 0.5, cy, 0, R]]
+
+
+def _members_2d(storage):
+    rng = np.random.default_rng(5)
+    out = []
+    for k, (nx, ny) in enumerate([(64, 64), (96, 64), (70, 45), (128, 100), (33, 80), (200, 150)]):
+        film = k % 2 == 0
+        p = dict(lattice=0, storage=storage, nx=nx, ny=ny, G=float(rng.uniform(-6.0, -4.8)), rho_liquid=2.3,
+                 rho_gas=0.11, seed=10 + k, film_on=int(film), k_own=int(rng.integers(1, 6)), rupture_warmup=40)
+        if film:
+            nuc = _two_bubbles(nx, ny, min(nx, ny) / 5.0, 2.0)
+        else:
+            nuc = [[float(rng.uniform(0, nx)), float(rng.uniform(0, ny)), 0.0, float(rng.uniform(3, 8))]
+                   for _ in range(4)]
+        out.append((p, nuc))
+    return out
+
+
+def _solo(flb, p, nuc, steps):
+    s = flb.Sim(**p)
+    s.set_nuclei(nuc)
+    s.step(steps)
+    return s
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batch_members_match_solo_runs(flb, storage):
+    members = _members_2d(storage)
+    _say(f"batch of {len(members)} D2Q9 {storage}")
+    b = flb.Batch([p for p, _ in members])
+    for k, (_, nuc) in enumerate(members):
+        b.members[k].set_nuclei(nuc)
+    steps = 75  # four graph replays of 16 steps plus eager steps
+    b.step(steps)
+    b.synchronize()
+    any_rupture = False
+    for k, (p, nuc) in enumerate(members):
+        s = _solo(flb, p, nuc, steps)
+        m = b.members[k]
+        assert np.array_equal(m.populations(), s.populations()), k
+        sm, ss = m.stats(), s.stats()
+        assert sm["step"] == ss["step"] == steps
+        assert sm["n_ruptures"] == ss["n_ruptures"]
+        assert abs(sm["mass"] - ss["mass"]) <= 1e-9 * abs(ss["mass"])
+        if p["film_on"]:
+            assert {tuple(r) for r in m.rupture_events().tolist()} == {tuple(r) for r in s.rupture_events().tolist()}
+            any_rupture |= ss["n_ruptures"] > 0
+    assert any_rupture
+
+
+def test_batch_3d_and_eager_equals_graph(flb):
+    rng = np.random.default_rng(9)
+    members = []
+    for k, (nx, ny, nz) in enumerate([(32, 32, 32), (48, 20, 28), (64, 40, 24)]):
+        p = dict(lattice=1, storage="f32", nx=nx, ny=ny, nz=nz, G=-5.5, rho_liquid=2.3, rho_gas=0.11, seed=k,
+                 film_on=1, k_own=4, rupture_warmup=20)
+        nuc = [[float(rng.uniform(0, nx)), float(rng.uniform(0, ny)), float(rng.uniform(0, nz)),
+                float(rng.uniform(3, 6))] for _ in range(5)]
+        members.append((p, nuc))
+    _say("batch of 3 D3Q19 f32, graph vs eager")
+    outs = []
+    for graph_steps in (16, 0):
+        b = flb.Batch([p for p, _ in members])
+        b.set_tuning(graph_steps=graph_steps)
+        for k, (_, nuc) in enumerate(members):
+            b.members[k].set_nuclei(nuc)
+        b.step(40)
+        outs.append([m.populations() for m in b.members])
+        b.close()
+    for k, (p, nuc) in enumerate(members):
+        s = _solo(flb, p, nuc, 40)
+        f = s.populations()
+        assert np.array_equal(outs[0][k], f) and np.array_equal(outs[1][k], f), k
+
+
+def test_batch_autotune_leaves_state_unchanged(flb):
+    members = _members_2d("f32")
+    _say("batch autotune")
+    b = flb.Batch([p for p, _ in members])
+    for k, (_, nuc) in enumerate(members):
+        b.members[k].set_nuclei(nuc)
+    b.step(7)
+    before = [m.populations() for m in b.members]
+    st_before = [m.stats()["step"] for m in b.members]
+    ms = b.autotune(reps=2)
+    assert ms > 0
+    t = b.tuning()
+    assert 0 <= t["tile"] < t["n_tiles"]
+    for k, m in enumerate(b.members):
+        assert np.array_equal(m.populations(), before[k]) and m.stats()["step"] == st_before[k]
+    b.step(13)
+    for k, (p, nuc) in enumerate(members):
+        s = _solo(flb, p, nuc, 20)
+        assert np.array_equal(b.members[k].populations(), s.populations()), k

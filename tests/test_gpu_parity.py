@@ -265,3 +265,51 @@ def test_velocity_mode_1_parity(flb):
     p, nuc = _two_bubble_params(flb, velocity_mode=1, rupture_warmup=10 ** 6, k_own=5)
     g, o = _run_pair(flb, p, nuc, 23)
     assert vel_err(g.velocity(), o.velocity()) <= 1e-12
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_rupture_filter_takes_fp64_decisions(flb, storage):
+    # the FP32 sign filter only skips FP64 evaluations it has proven negative:
+    # event logs and states are identical with and without it
+    p, nuc = _two_bubble_params(flb, storage=storage)
+    runs = []
+    for filt in (1, 0):
+        g = flb.Sim(**dict(p, rupture_filter=filt))
+        g.set_nuclei(nuc)
+        g.step(300)
+        runs.append((g.rupture_events(), g.populations(), g.stats()["n_ruptures"]))
+    (e1, f1, n1), (e0, f0, n0) = runs
+    assert len(e0) > 0 and n0 > 0
+    assert sorted(map(tuple, e1.tolist())) == sorted(map(tuple, e0.tolist()))
+    assert n1 == n0
+    assert np.array_equal(f1, f0)
+
+
+def _compare_maps(flb, kind, g, o):
+    gm, om = g.maps(), o.maps()
+    for key in ("label", "owner", "owner2", "dist"):
+        assert np.array_equal(gm[key], om[key]), key
+    order = oracle_order(kind, flb.DIRECTIONS[kind])
+    omask = np.zeros_like(gm["mask"])
+    for i, j in enumerate(order):
+        omask |= ((om["mask"] >> np.uint32(j)) & np.uint32(1)) << np.uint32(i)
+    assert np.array_equal(gm["mask"], omask)
+    return gm
+
+
+@pytest.mark.parametrize("kind,dims", [(0, (150, 77, 1)), (1, (70, 21, 19)), (1, (130, 9, 37))])
+def test_film_maps_bit_exact_ragged_many_bubbles(flb, kind, dims):
+    # many bubbles over lattices whose extents are not multiples of the tile
+    # and segment sizes, so components, BFS fronts and barriers cross tile
+    # edges and the periodic wrap
+    nx, ny, nz = dims
+    rng = np.random.default_rng(11 + kind)
+    nb = 14 if kind == 0 else 10
+    nuc = [[float(rng.uniform(0, nx)), float(rng.uniform(0, ny)), float(rng.uniform(0, nz)) if kind else 0.0,
+            float(rng.uniform(3, 7))] for _ in range(nb)]
+    p = _case(flb, lattice=kind, storage="f64", nx=nx, ny=ny, nz=nz, G=-5.5, rho_liquid=2.3, rho_gas=0.11,
+              film_on=1, k_own=3, rupture_warmup=10 ** 6, seed=4)
+    g, o = _run_pair(flb, p, nuc, 7)
+    gm = _compare_maps(flb, kind, g, o)
+    assert g.stats()["n_bubbles"] > 1 and np.count_nonzero(gm["mask"]) > 0
+    assert max_rel(g.density(), o.density()) <= 1e-12

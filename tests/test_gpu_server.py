@@ -1,0 +1,97 @@
+"""The job server: jobs that arrive while others run are admitted as memory
+frees up, share batched launches, and finish with exactly the fields they
+have when run alone (marked gpu)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def flb():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1708_01613_amd import foamlbm
+
+    return foamlbm
+
+
+def _say(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _jobs():
+    rng = np.random.default_rng(21)
+    jobs = []
+    for k in range(7):
+        d3 = k % 3 == 2
+        if d3:
+            n = int(rng.integers(24, 40))
+            p = dict(lattice=1, storage="f32", nx=n, ny=n + 3, nz=n - 2)
+            nuc = [[float(rng.uniform(0, n)), float(rng.uniform(0, n)), float(rng.uniform(0, n - 2)),
+                    float(rng.uniform(3, 6))] for _ in range(4)]
+        else:
+            n = int(rng.integers(48, 120))
+            p = dict(lattice=0, storage="f32", nx=n, ny=n - 5)
+            nuc = [[float(rng.uniform(0, n)), float(rng.uniform(0, n - 5)), 0.0, float(rng.uniform(3, 9))]
+                   for _ in range(5)]
+        p.update(G=float(rng.uniform(-6.0, -4.8)), rho_liquid=2.3, rho_gas=0.11, seed=100 + k,
+                 film_on=int(k % 2 == 0), k_own=5, rupture_warmup=30)
+        steps = int(rng.integers(20, 90))
+        jobs.append((p, nuc, steps))
+    return jobs
+
+
+def test_jobs_in_the_mix_equal_jobs_alone(flb):
+    jobs = _jobs()
+    _say(f"server with {len(jobs)} mixed jobs, staggered arrivals, small pool")
+    # a pool that holds about three of these jobs at once, so later jobs wait
+    srv = flb.Server(pool_bytes=3 * 40 * 1024 * 1024, chunk_steps=16, graph_steps=8)
+    ids = []
+    for k, (p, nuc, steps) in enumerate(jobs):
+        ids.append(srv.submit(steps, nuc, **p))
+        if k % 2 == 1:
+            srv.pump()  # jobs arrive while others run
+    rounds = 0
+    while True:
+        running, queued, done = srv.pump()
+        rounds += 1
+        assert rounds < 1000
+        if running == 0 and queued == 0:
+            break
+    assert done == len(jobs)
+    used, pool = srv.usage()
+    assert used == 0
+    for k, (p, nuc, steps) in enumerate(jobs):
+        st, sd = srv.state(ids[k])
+        assert st == flb.FLB_JOB_DONE and sd == steps
+        rho, stats = srv.result(ids[k])
+        solo = flb.Sim(**p)
+        solo.set_nuclei(nuc)
+        solo.step(steps)
+        assert np.array_equal(rho, solo.density()), k
+        assert stats["step"] == steps
+        srv.release(ids[k])
+
+
+def test_job_larger_than_pool_is_refused(flb):
+    srv = flb.Server(pool_bytes=1 << 20)
+    with pytest.raises(flb.FlbError) as e:
+        srv.submit(10, [[8, 8, 0, 3]], lattice=0, storage="f32", nx=256, ny=256)
+    assert e.value.code == flb.FLB_EBUSY
+
+
+def test_zero_step_job_finishes(flb):
+    srv = flb.Server()
+    jid = srv.submit(0, [[16, 16, 0, 5]], lattice=0, storage="f32", nx=40, ny=40)
+    srv.pump()
+    st, sd = srv.state(jid)
+    assert st == flb.FLB_JOB_DONE and sd == 0
+    rho, _ = srv.result(jid)
+    s = flb.Sim(lattice=0, storage="f32", nx=40, ny=40)
+    s.set_nuclei([[16, 16, 0, 5]])
+    assert np.array_equal(rho, s.density())
