@@ -54,6 +54,71 @@ def cpu_baseline(steps=10):
                       f"incl. one map refresh, {dt:.1f} s on {threads} OpenMP threads"}
 
 
+# rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the step kernel on this
+# workload; its traffic is reported only while the kernel sources are the
+# ones it was measured on
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_step_d3q19_256_f32_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1708_01613_amd", "csrc", f) for f in ("step.hpp", "lattice.hpp")]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def batched_and_served(args):
+    """Reduced forms of the batched-ensemble and served-stream workloads:
+    64 uneven D2Q9 lattices (batched vs one-by-one), and a Poisson stream of
+    mixed D2Q9/D3Q19 jobs (server vs first-come first-served)."""
+    import torch
+
+    from paper_1708_01613_amd import inputs, serve
+
+    out = {}
+    members, _ = inputs.config_ensemble()
+    cells = sum(p["nx"] * p["ny"] for p, _ in members)
+    for mode in ("batched", "sequential"):
+        r = serve.ensemble(members, args.ensemble_steps, mode=mode)
+        log(f"ensemble {mode}: {r['MLUPS']:.0f} MLUPS")
+        out[f"ensemble_{mode}"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+        torch.cuda.empty_cache()
+    out["ensemble"] = {"lattices": len(members), "cells": cells, "steps": args.ensemble_steps,
+                       "speedup": round(out["ensemble_batched"]["MLUPS"] / out["ensemble_sequential"]["MLUPS"], 2)}
+    trace = inputs.arrival_trace(n_requests=args.serve_jobs)
+    for j in trace:
+        j["steps"] = args.serve_steps
+    for mode in ("server", "sequential"):
+        r = serve.served(trace, mode=mode)
+        log(f"served {mode}: {r['MLUPS']:.0f} MLUPS p50 {r['p50_s']:.2f}s p99 {r['p99_s']:.2f}s")
+        out[f"served_{mode}"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+        torch.cuda.empty_cache()
+    out["served"] = {"jobs": len(trace), "rate_per_s": 20.0, "steps_per_job": args.serve_steps}
+    return out
+
+
 def copy_ceiling(torch, nbytes=1 << 30, reps=20):
     """Device-to-device copy rate (read + write bytes / time) of a 1 GiB
     buffer: the practical HBM ceiling the stencil is compared with."""
@@ -80,9 +145,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="cube side (the workload is 256)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--tile", type=int, default=-1)
+    ap.add_argument("--tile", type=int, default=-1, help="fixed tile variant (default: autotune)")
     ap.add_argument("--lz", type=int, default=0)
     ap.add_argument("--xcd", type=int, default=-1)
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and served measurements")
+    ap.add_argument("--ensemble-steps", type=int, default=1000)
+    ap.add_argument("--serve-jobs", type=int, default=48)
+    ap.add_argument("--serve-steps", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -98,8 +167,12 @@ def main():
     params.update(k_own=10, zone_width=6, rupture_warmup=200)
     log(f"creating {params['nx']}^3 D3Q19 f32 lattice, {len(nuc)} nuclei")
     sim = foamlbm.Sim(**params)
-    sim.set_tuning(args.tile, args.lz, args.xcd)
     sim.set_nuclei(nuc)
+    if args.tile >= 0:
+        sim.set_tuning(args.tile, args.lz, args.xcd)
+    else:
+        tuned = sim.autotune(reps=3)
+        log(f"autotuned step kernel {tuned:.4f} ms")
     N = params["nx"] * params["ny"] * params["nz"]
     tun = sim.tuning()
     log(f"tuning {tun}")
@@ -143,6 +216,7 @@ def main():
     except Exception as exc:  # a variant failing must not hide the main line
         variants["d3q19_f16s_kernel"] = {"error": str(exc)}
 
+    forms = None if args.no_forms else batched_and_served(args)
     cpu = None if args.no_cpu else cpu_baseline()
     line = {
         "metric": "MLUPS & %HBM peak (D3Q19 256^3 FP32); batched MLUPS + p50/p99 latency",
@@ -161,12 +235,14 @@ def main():
                                "tau=1, film barrier + rupture on, maps every 10 steps",
                    "cells": N, "tuning": tun},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_step<D3Q19K,SF32,64,8>", "kernel_ms": round(kms, 4),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "kernel": (f"k_step<D3Q19K,SF32,{tun['tile_x']},{tun['tile_m']}>" if tun["tile_x"]
+                                else "k_psi+k_collide<D3Q19K,SF32>"), "kernel_ms": round(kms, 4),
                      "bytes_per_update": bpu, "design_bytes_per_update": DESIGN_BYTES,
                      "copy_ceiling_GBs": round(copy, 1), "frac_of_copy": round(achieved / copy, 4)},
         "cpu_baseline": cpu,
         "variants": variants,
+        "batched_and_served": forms,
         "checks": {"mass": st["mass"], "n_bubbles": st["n_bubbles"], "n_ruptures": st["n_ruptures"],
                    "step": st["step"]},
     }

@@ -198,6 +198,14 @@ int flb_set_tuning(flb_ctx* ctx, int32_t tile, int32_t lz, int32_t xcd);
 int flb_get_tuning(flb_ctx* ctx, int32_t* tile, int32_t* lz, int32_t* xcd, int32_t* n_tiles,
                    int32_t* tile_x, int32_t* tile_m);
 
+/* Autotuner: times `reps` launches of the step kernel(s) for every tile
+ * variant, segment length and XCD setting, keeps the fastest and returns its
+ * time per step in *best_ms (may be NULL).  The state is not changed: each
+ * trial reads the current populations and writes a scratch buffer (one
+ * population buffer, allocated while it runs) under a copy of the run
+ * control. */
+int flb_autotune(flb_ctx* ctx, int32_t reps, double* best_ms);
+
 /* Runs nsteps steps like flb_step, bracketed by HIP events on the context
  * stream, and returns the elapsed milliseconds in *ms.  With refresh == 0 the
  * film maps are not rebuilt, so only the step kernel(s) and the small
@@ -256,8 +264,9 @@ void flb_batch_destroy(flb_batch* batch);
  * Jobs (a parameter set, nuclei and a step count) queue in submission order.
  * Each flb_server_pump is one scheduling round: it admits queued jobs, in
  * order, while the device bytes of all admitted jobs stay within
- * pool_bytes and fewer than max_jobs are resident (a job that does not fit
- * waits, and so do the jobs behind it); it advances every running job by the
+ * pool_bytes, fewer than max_jobs are resident and the running jobs hold at
+ * most max_cells lattice cells (a job larger than max_cells runs once nothing
+ * else does; a job that does not fit waits, and so do the jobs behind it); it advances every running job by the
  * same number of steps, chunk_steps or fewer so that no job passes its last
  * step, with batched launches (one batch per lattice type and storage, runs
  * of graph_steps steps replayed from captured HIP graphs); and it retires the
@@ -271,10 +280,12 @@ typedef struct {
   int32_t max_jobs;    /* resident jobs at most */
   int32_t chunk_steps; /* steps per round at most */
   int32_t graph_steps; /* steps per captured graph (0: no graphs) */
+  int64_t max_cells;   /* lattice cells of the running jobs at most: enough
+                          to fill the GPU; more only lengthens every job */
 } flb_server_config;
 enum { FLB_JOB_QUEUED = 0, FLB_JOB_RUNNING = 1, FLB_JOB_DONE = 2, FLB_JOB_FAILED = 3 };
 
-/* pool 64 GiB, 256 jobs, chunks of 100 steps, graphs of 20 steps */
+/* pool 64 GiB, 256 jobs, chunks of 100 steps, graphs of 20 steps, 2^24 cells */
 void flb_server_default_config(flb_server_config* cfg);
 int flb_server_create(const flb_server_config* cfg, const flb_allocator* alloc, void* hip_stream,
                       flb_server** out);

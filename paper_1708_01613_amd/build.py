@@ -15,13 +15,15 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["hipcc", *FLAGS, *SRCS, "-o", LIB + ".tmp"]
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile the library to `out`; `defines` are extra -D options (the
+    compile-time switches of the kernels, e.g. FLB_ST_CPOL=2)."""
+    cmd = ["hipcc", *FLAGS, *[f"-D{d}" for d in defines], *SRCS, "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

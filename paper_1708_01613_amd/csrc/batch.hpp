@@ -74,6 +74,7 @@ struct flb_batch {
   PruneArgs* ptab = nullptr;
   int* ffirst = nullptr;
   int fblk = 0;
+  flb_rt::MapSet fms;  // film refresh of the film members, one launch per map kernel
   bool dirty = true;
   // graphs
   int graph_steps = 16;
@@ -164,6 +165,12 @@ inline int rebuild(flb_batch* b) {
     HIPCHK(hipMemcpyAsync(b->ptab, ptab.data(), sizeof(PruneArgs) * nf, hipMemcpyHostToDevice, b->st));
     HIPCHK(hipMemcpyAsync(b->ffirst, ffirst.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, b->st));
   }
+  if (nf) {
+    std::vector<MapArgs> margs;
+    for (int k : b->film) margs.push_back(map_args(b->m[k], false, GAS_POP));
+    int rc = mapset_build(b->fms, margs, b->D, [b](size_t bytes) { return b->dalloc(bytes); }, b->st);
+    if (rc) return rc;
+  }
   HIPCHK(hipStreamSynchronize(b->st));
   b->nblk = first[n];
   b->fblk = ffirst[nf];
@@ -175,12 +182,13 @@ inline int rebuild(flb_batch* b) {
 // one step of every member (no synchronisation, capturable)
 template <class L, class S>
 int batch_one_step(flb_batch* b) {
-  for (int k : b->film) {
-    flb_ctx* c = b->m[k];
-    if (c->launched % c->p.k_own == 0) {
-      int rc = refresh_maps<L, S>(c, false);
-      if (rc) return rc;
-    }
+  // one batched refresh when any film member is due; the map kernels skip
+  // the members that are not
+  bool due = false;
+  for (int k : b->film) due = due || b->m[k]->launched % b->m[k]->p.k_own == 0;
+  if (due) {
+    int rc = map_pipeline<L, S>(b->fms, b->st, GAS_POP, true);
+    if (rc) return rc;
   }
   const int n = (int)b->m.size();
   b->step_fn()(b->tab, b->first, n, b->nblk, b->buf, b->st);
@@ -201,7 +209,7 @@ int batch_one_step(flb_batch* b) {
 // phases
 inline std::vector<long long> phase_key(const flb_batch* b) {
   std::vector<long long> key;
-  for (int k : b->film) key.push_back(2 * (b->m[k]->launched % b->m[k]->p.k_own) + (b->m[k]->maps_seen ? 1 : 0));
+  for (int k : b->film) key.push_back(b->m[k]->launched % b->m[k]->p.k_own);
   return key;
 }
 

@@ -156,7 +156,6 @@ int flb_set_nuclei(flb_ctx* c, const flb_nucleus* nuc, int32_t n) {
   HIPCHK(hipStreamSynchronize(c->st));
   c->dfree(dn);
   c->launched = 0;
-  c->maps_seen = false;
   if (c->p.film_on) {
     HIPCHK(hipMemsetAsync(c->flag, 0, (size_t)c->N, c->st));
     HIPCHK(hipMemsetAsync(c->mask, 0, sizeof(uint32_t) * (size_t)c->N, c->st));
@@ -220,6 +219,85 @@ int flb_set_tuning(flb_ctx* c, int32_t tile, int32_t lz, int32_t xcd) {
   return FLB_OK;
 }
 
+int flb_autotune(flb_ctx* c, int32_t reps, double* best_ms) {
+  if (!c) return fail(FLB_EINVAL, "ctx is NULL");
+  if (reps < 1 || reps > 1000) return fail(FLB_EINVAL, "reps must be in 1..1000");
+  Ctl h;
+  int rc = read_ctl(c, &h);
+  if (rc) return rc;
+  const int cur = (int)(h.steps & 1);
+  void* scratch = c->dalloc(c->fbytes);
+  Ctl* sctl = (Ctl*)c->dalloc(sizeof(Ctl));
+  if (!scratch || !sctl) {
+    c->dfree(scratch);
+    c->dfree(sctl);
+    return fail(FLB_ENOMEM, "autotune scratch allocation failed");
+  }
+  const int save_tile = c->tile, save_lz = c->lz, save_xcd = c->xcd;
+  int bt = save_tile, bl = save_lz, bx = save_xcd;
+  float best = 1e30f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const int nt = c->D == 2 ? kNTiles2 : kNTiles3;
+  const int lzs[] = {8, 16, 32, 64, 128, 256, 512};
+  for (int t = 0; t < nt && e == hipSuccess; t++) {
+    c->tile = t;
+    std::vector<int> cand;
+    if (c->two_pass()) cand.push_back(c->md.nz);
+    else
+      for (int l : lzs) cand.push_back(std::min(l, c->md.nz));
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    for (int lz : cand)
+      for (int xc : {0, 8}) {
+        if (e != hipSuccess) break;
+        c->lz = lz;
+        c->xcd = xc;
+        const int nblk = c->nblocks();
+        if (nblk > c->max_blk) continue;
+        StepArgs a = step_args(c);
+        a.buf[cur] = c->f[cur];
+        a.buf[1 - cur] = scratch;
+        a.ctl = sctl;
+        e = hipMemcpyAsync(sctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, c->st);
+        const StepFn fn = c->tcfg().fn[c->p.storage], coll = c->tcfg().coll[c->p.storage];
+        auto launch = [&]() {
+          fn(a, nblk, c->st);
+          if (coll) coll(a, nblk, c->st);
+        };
+        if (e == hipSuccess) launch();  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, c->st);
+        for (int r = 0; r < reps && e == hipSuccess; r++) launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, c->st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms < best) {
+          best = ms;
+          bt = t;
+          bl = lz;
+          bx = xc;
+        }
+      }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(c->st);
+  c->dfree(scratch);
+  c->dfree(sctl);
+  c->tile = bt;
+  c->lz = bl;
+  c->xcd = bx;
+  if (e != hipSuccess) {
+    c->tile = save_tile;
+    c->lz = save_lz;
+    c->xcd = save_xcd;
+    return fail(FLB_EHIP, "autotune: %s", hipGetErrorString(e));
+  }
+  if (best_ms) *best_ms = best / reps;
+  return FLB_OK;
+}
+
 int flb_get_tuning(flb_ctx* c, int32_t* tile, int32_t* lz, int32_t* xcd, int32_t* n_tiles, int32_t* tile_x,
                    int32_t* tile_m) {
   if (!c) return fail(FLB_EINVAL, "ctx is NULL");
@@ -235,8 +313,7 @@ int flb_get_tuning(flb_ctx* c, int32_t* tile, int32_t* lz, int32_t* xcd, int32_t
 int flb_get_labels(flb_ctx* c, int32_t* out, size_t n, int32_t* n_bubbles) {
   if (!c || !out) return fail(FLB_EINVAL, "NULL argument");
   if (n != (size_t)c->N) return fail(FLB_EINVAL, "n must be nx*ny*nz = %lld", c->N);
-  HIPCHK(hipMemsetAsync(c->qctl, 0, sizeof(Ctl), c->st));
-  int rc = FLB_DISPATCH(c, label_pipeline, c, c->qctl, &c->qctl->n_bubbles, c->qlabel, (const double*)nullptr);
+  int rc = FLB_DISPATCH(c, label_query, c, false);
   if (rc) return rc;
   int nb = 0;
   HIPCHK(hipMemcpyAsync(out, c->qlabel, sizeof(int) * n, hipMemcpyDeviceToHost, c->st));
@@ -250,8 +327,7 @@ int flb_label_field(flb_ctx* c, const double* rho, size_t n, int32_t* out, int32
   if (!c || !rho || !out) return fail(FLB_EINVAL, "NULL argument");
   if (n != (size_t)c->N) return fail(FLB_EINVAL, "n must be nx*ny*nz = %lld", c->N);
   HIPCHK(hipMemcpyAsync(c->qd, rho, sizeof(double) * n, hipMemcpyHostToDevice, c->st));
-  HIPCHK(hipMemsetAsync(c->qctl, 0, sizeof(Ctl), c->st));
-  int rc = FLB_DISPATCH(c, label_pipeline, c, c->qctl, &c->qctl->n_bubbles, c->qlabel, (const double*)c->qd);
+  int rc = FLB_DISPATCH(c, label_query, c, true);
   if (rc) return rc;
   int nb = 0;
   HIPCHK(hipMemcpyAsync(out, c->qlabel, sizeof(int) * n, hipMemcpyDeviceToHost, c->st));
@@ -297,8 +373,7 @@ int flb_get_histogram(flb_ctx* c, int32_t nbins, double bin_width, int64_t* coun
     if (!c->qhist) return fail(FLB_ENOMEM, "histogram allocation failed");
     c->qhist_cap = nbins;
   }
-  HIPCHK(hipMemsetAsync(c->qctl, 0, sizeof(Ctl), c->st));
-  int rc = FLB_DISPATCH(c, label_pipeline, c, c->qctl, &c->qctl->n_bubbles, c->qlabel, (const double*)nullptr);
+  int rc = FLB_DISPATCH(c, label_query, c, false);
   if (rc) return rc;
   HIPCHK(hipMemsetAsync(c->qsizes, 0, sizeof(unsigned long long) * (size_t)(c->N + 1), c->st));
   HIPCHK(hipMemsetAsync(c->qhist, 0, sizeof(unsigned long long) * (size_t)nbins, c->st));

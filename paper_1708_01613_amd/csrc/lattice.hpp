@@ -130,6 +130,8 @@ struct Ctl {
   int alias_dirty;      // 1 if ruptures of this step united bubbles (masks need pruning)
   int step_events;      // 1 if the rupture test of this step found a link
   unsigned n_flagged;   // cells with barrier links at the last refresh (list length)
+  int maps_seen;        // 1 once a refresh has built maps (the next one carries aliases)
+  int nb_old;           // labels of the previous refresh, during a refresh
   double mass, mom[3];  // FP64 totals of the state entering the last step
 };
 

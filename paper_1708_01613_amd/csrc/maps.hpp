@@ -10,10 +10,20 @@
 //              at zone_width - 1 hops.
 //  alias     : union-find over labels; a rupture unites a pair; at a refresh,
 //              new bubbles overlapping old bubbles of one alias class are united.
-//  masks     : link i of cell c is a candidate barrier iff both ends are owned,
-//              their alias-root pairs differ and dist(c) + dist(c+e_i) + 1 <=
+//  masks     : link i of cell c is a barrier iff both ends are owned, their
+//              alias-root pairs differ and dist(c) + dist(c+e_i) + 1 <=
 //              zone_width.
+//
+// Every kernel here works on a table of lattices (MapArgs): workgroups
+// [first[k], first[k+1]) of a launch serve lattice k, with a share that
+// depends on the kernel's decomposition (MapShape).  A single lattice is a
+// table of one; a batch refreshes all its lattices with one launch per
+// kernel.  A refresh kernel does nothing for a lattice that is stopped or
+// whose step is not a refresh step (steps % k_own != 0), so a batch can
+// launch the refresh whenever any member is due.
 #pragma once
+#include <algorithm>
+
 #include "step.hpp"
 
 namespace flb {
@@ -99,28 +109,87 @@ __device__ __forceinline__ int wave_min_i32(int v) {
 }
 __device__ __forceinline__ int first_lane(unsigned long long m) { return __builtin_ctzll(m); }
 
-// parent[c] = c for gas cells (double-precision density of the stored state
-// below rho_th), -1 otherwise
-template <class L, class S>
-__global__ __launch_bounds__(MAP_NT) void k_gas_init(const void* b0, const void* b1, const Ctl* ctl, Geo geo,
-                                                     MapDims d, double rho_th, int* par) {
-  if (ctl->stopped) return;
-  const void* src = (ctl->steps & 1) ? b1 : b0;
-  for_cells<false>(d, [&](const SegCell& q) {
-    typename S::ct f[L::Q];
-    load_pulled<L, S>(src, geo, q.x, q.m, q.z, f);
-    double r = 0.0;
-#pragma unroll
-    for (int i = 0; i < L::Q; i++) r += (double)f[i];
-    par[q.c] = r < rho_th ? (int)q.c : -1;
-  });
+
+// ---- per-lattice arguments of the map kernels ----
+enum GasSrc { GAS_POP = 0, GAS_FIELD = 1, GAS_RHO = 2 };
+
+struct MapArgs {
+  Ctl* ctl;               // gate: run control of the lattice (or a zeroed query control)
+  const Ctl* sctl;        // run control whose step count selects the current population buffer
+  MapDims d;
+  Geo geo;                // population layout (gas from the stored state)
+  const void* b0;
+  const void* b1;
+  const void* src;        // a cell-linear density field: FP64 (GAS_FIELD) or compute type (GAS_RHO)
+  double rho_th;
+  int k_own;              // refresh steps: steps % k_own == 0 (0: every launch, queries)
+  int zone_width;
+  int refresh;            // 1: film refresh (owners, aliases, masks); 0: labels only
+  int nrb;                // rank blocks, ceil(N / RANK_BLOCK)
+  int* par;
+  int* rank;
+  int* counts;
+  int* label;             // labels out
+  int* n_out;             // label count out
+  int* label_old;
+  int* alias;
+  int* alias_old;
+  int* rep;
+  int2* own;
+  uint8_t* dist;
+  uint8_t* flag;
+  uint32_t* mask;
+  int* flist;
+  unsigned long long* fr0;  // BFS frontier bitsets (ping-pong) and visited set
+  unsigned long long* fr1;
+  unsigned long long* vis;
+};
+
+__device__ __forceinline__ bool map_due(const MapArgs& m) {
+  const Ctl* c = m.ctl;
+  return !c->stopped && (m.k_own == 0 || c->steps % m.k_own == 0);
 }
 
-// same from a host-provided density field
-static __global__ void k_gas_from_field(const double* rho, MapDims d, double rho_th, int* par) {
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < d.N;
-       c += (long long)gridDim.x * blockDim.x)
-    par[c] = rho[c] < rho_th ? (int)c : -1;
+// decompositions of a map launch (workgroups per lattice)
+enum MapShape { SH_CELLS = 0, SH_SEG, SH_WORDS, SH_CCT, SH_MT, SH_RANK, SH_ONE, SH_LIST, SH_COUNT };
+
+#define MAP_KERNEL_PARAMS const MapArgs *__restrict__ tab, const int *__restrict__ first, int nmem
+#define MAP_MEMBER                                                           \
+  const int k_ = batch_member(first, nmem, blockIdx.x);                      \
+  const MapArgs m = tab[k_];                                                 \
+  const unsigned bid = blockIdx.x - (unsigned)first[k_];                     \
+  const unsigned nbk = (unsigned)(first[k_ + 1] - first[k_]);                \
+  (void)bid;                                                                 \
+  (void)nbk;
+
+// grid-stride over [0, n) within a lattice's share
+#define FOR_SHARE(i, n) for (long long i = bid * (long long)blockDim.x + threadIdx.x; i < (n); i += (long long)nbk * blockDim.x)
+
+// ---- gas flags: par[c] = c for gas cells, -1 otherwise ----
+template <class L, class S, int SRC>
+__global__ __launch_bounds__(MAP_NT) void k_gas(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  if constexpr (SRC == GAS_POP) {
+    // density of the stored state, summed in FP64
+    const void* src = (m.sctl->steps & 1) ? m.b1 : m.b0;
+    for_cells<false>(
+        m.d,
+        [&](const SegCell& q) {
+          typename S::ct f[L::Q];
+          load_pulled<L, S>(src, m.geo, q.x, q.m, q.z, f);
+          double r = 0.0;
+#pragma unroll
+          for (int i = 0; i < L::Q; i++) r += (double)f[i];
+          m.par[q.c] = r < m.rho_th ? (int)q.c : -1;
+        },
+        bid, nbk);
+  } else {
+    FOR_SHARE(c, m.d.N) {
+      const double r = SRC == GAS_FIELD ? ((const double*)m.src)[c] : (double)((const typename S::ct*)m.src)[c];
+      m.par[c] = r < m.rho_th ? (int)c : -1;
+    }
+  }
 }
 
 // ---- connected components in two phases ----
@@ -171,27 +240,29 @@ __device__ __forceinline__ void lds_unite(int* lp, int a, int b) {
 }
 
 template <class L>
-__global__ __launch_bounds__(CC_NT) void k_cc_local(const Ctl* ctl, MapDims d, int* par) {
-  if (ctl->stopped) return;
+__global__ __launch_bounds__(CC_NT) void k_cc_local(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
   using TT = CCTile<L>;
   __shared__ int lp[CC_CELLS];
+  const MapDims d = m.d;
   const int ntx = (d.nx + 63) / 64, ntm = (d.nm + TT::TM - 1) / TT::TM;
-  const int b = blockIdx.x;
+  const int b = (int)bid;
   const int tx = b % ntx, tm = (b / ntx) % ntm, tz = b / (ntx * ntm);
   const int x0 = tx * 64, m0 = tm * TT::TM, z0 = tz * TT::TZ;
   constexpr int PER = CC_CELLS / CC_NT;
-  auto gcell = [&](int l, int& x, int& m, int& z) -> bool {
+  auto gcell = [&](int l, int& x, int& mm_, int& z) -> bool {
     x = x0 + (l & 63);
-    m = m0 + (l >> 6) % TT::TM;
+    mm_ = m0 + (l >> 6) % TT::TM;
     z = z0 + (l >> 6) / TT::TM;
-    return x < d.nx && m < d.nm && z < d.nz;
+    return x < d.nx && mm_ < d.nm && z < d.nz;
   };
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int l = threadIdx.x + k * CC_NT;
-    int x, m, z;
+    int x, mm_, z;
     bool gas = false;
-    if (gcell(l, x, m, z)) gas = par[x + (unsigned)d.nx * (m + (unsigned)d.nm * z)] >= 0;
+    if (gcell(l, x, mm_, z)) gas = m.par[x + (unsigned)d.nx * (mm_ + (unsigned)d.nm * z)] >= 0;
     lp[l] = gas ? l : -1;
   }
   __syncthreads();
@@ -215,44 +286,52 @@ __global__ __launch_bounds__(CC_NT) void k_cc_local(const Ctl* ctl, MapDims d, i
     const int l = threadIdx.x + k * CC_NT;
     if (lp[l] < 0) continue;
     const int r = lds_find(lp, l);
-    int x, m, z, rx, rm, rz;
-    gcell(l, x, m, z);
+    int x, mm_, z, rx, rm, rz;
+    gcell(l, x, mm_, z);
     gcell(r, rx, rm, rz);
-    par[x + (unsigned)d.nx * (m + (unsigned)d.nm * z)] = (int)(rx + (unsigned)d.nx * (rm + (unsigned)d.nm * rz));
+    m.par[x + (unsigned)d.nx * (mm_ + (unsigned)d.nm * z)] = (int)(rx + (unsigned)d.nx * (rm + (unsigned)d.nm * rz));
   }
 }
 
 template <class L>
-__global__ __launch_bounds__(MAP_NT) void k_cc_cross(const Ctl* ctl, MapDims d, int* par) {
-  if (ctl->stopped) return;
+__global__ __launch_bounds__(MAP_NT) void k_cc_cross(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
   using TT = CCTile<L>;
+  const MapDims d = m.d;
+  int* par = m.par;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nxs = (d.nx + 63) >> 6;
   const unsigned nseg = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
   // wave-uniform loop over segments: every lane takes part in the merging
-  for (unsigned s = blockIdx.x * MAP_WAVES + wv; s < nseg; s += gridDim.x * MAP_WAVES) {
+  for (unsigned s = bid * MAP_WAVES + wv; s < nseg; s += nbk * MAP_WAVES) {
     const unsigned row = s / (unsigned)nxs;
     const int x = (int)(s - row * (unsigned)nxs) * 64 + lane;
-    const int m = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
+    const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
     const bool in = x < d.nx;
     const unsigned c = (unsigned)min(x, d.nx - 1) + (unsigned)d.nx * row;
     const int pc = in ? par[c] : -1;
+    if (!__ballot(pc >= 0)) continue;  // no gas in this segment
+    // the neighbours across tile edges, all loaded before any union
+    constexpr int NP = (L::Q - 1) / 2;
+    int py[NP];
 #pragma unroll
-    for (int i = 1; i < L::Q; i += 2) {
-      const int xu = x + L::ex[i], mu = m + L::em[i], zu = z + L::ez[i];
+    for (int p = 0; p < NP; p++) {
+      const int i = 2 * p + 1;  // one direction of each opposite pair
+      const int xu = x + L::ex[i], mu = mm_ + L::em[i], zu = z + L::ez[i];
       const bool local = xu >= 0 && xu < d.nx && (xu >> 6) == (x >> 6) && mu >= 0 && mu < d.nm &&
-                         mu / TT::TM == m / TT::TM && zu >= 0 && zu < d.nz && zu / TT::TZ == z / TT::TZ;
-      int ra = -1, rb = -1;
+                         mu / TT::TM == mm_ / TT::TM && zu >= 0 && zu < d.nz && zu / TT::TZ == z / TT::TZ;
+      py[p] = -1;
       if (pc >= 0 && !local) {
         const unsigned y = (unsigned)wrap_any(xu, d.nx) +
                            (unsigned)d.nx * ((unsigned)wrap_any(mu, d.nm) + (unsigned)d.nm * wrap_any(zu, d.nz));
-        const int py = __atomic_load_n(&par[y], __ATOMIC_RELAXED);
-        if (py >= 0) {
-          ra = __atomic_load_n(&par[c], __ATOMIC_RELAXED);
-          rb = py;
-        }
+        py[p] = __atomic_load_n(&par[y], __ATOMIC_RELAXED);
       }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+      const int ra = py[p] >= 0 ? pc : -1, rb = py[p];
       bool pend = ra >= 0 && ra != rb;
       unsigned long long mk = __ballot(pend);
       while (mk) {
@@ -266,23 +345,23 @@ __global__ __launch_bounds__(MAP_NT) void k_cc_cross(const Ctl* ctl, MapDims d, 
   }
 }
 
-static __global__ void k_cc_compress(const Ctl* ctl, MapDims d, int* par) {
-  if (ctl->stopped) return;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < d.N;
-       c += (long long)gridDim.x * blockDim.x) {
-    if (par[c] < 0) continue;
-    par[c] = uf_find_live(par, (int)c);
+static __global__ __launch_bounds__(MAP_NT) void k_cc_compress(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  FOR_SHARE(c, m.d.N) {
+    if (m.par[c] < 0) continue;
+    m.par[c] = uf_find_live(m.par, (int)c);
   }
 }
 
 // ---- canonical ranks: count roots per block, scan, write labels ----
 constexpr int RANK_BLOCK = 1024;
 
-static __global__ __launch_bounds__(RANK_BLOCK) void k_count_roots(const Ctl* ctl, MapDims d, const int* par,
-                                                           int* counts) {
-  if (ctl->stopped) return;
-  const long long c = blockIdx.x * (long long)RANK_BLOCK + threadIdx.x;
-  const int is_root = (c < d.N && par[c] == (int)c) ? 1 : 0;
+static __global__ __launch_bounds__(RANK_BLOCK) void k_count_roots(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  const long long c = bid * (long long)RANK_BLOCK + threadIdx.x;
+  const int is_root = (c < m.d.N && m.par[c] == (int)c) ? 1 : 0;
   __shared__ int s[RANK_BLOCK / 64];
   const unsigned long long bal = __ballot(is_root);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = __popcll(bal);
@@ -290,22 +369,24 @@ static __global__ __launch_bounds__(RANK_BLOCK) void k_count_roots(const Ctl* ct
   if (threadIdx.x == 0) {
     int t = 0;
     for (int w = 0; w < RANK_BLOCK / 64; w++) t += s[w];
-    counts[blockIdx.x] = t;
+    m.counts[bid] = t;
   }
 }
 
-// single workgroup: exclusive scan of the per-block counts, total to *total
-static __global__ __launch_bounds__(1024) void k_scan_counts(const Ctl* ctl, int* counts, int nblocks, int* total) {
-  if (ctl->stopped) return;
+// one workgroup per lattice: exclusive scan of the per-block counts, total
+// to *n_out
+static __global__ __launch_bounds__(1024) void k_scan_counts(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
   __shared__ int s_carry;
   __shared__ int s_w[16];
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
+  const int nblocks = m.nrb;
   for (int base = 0; base < nblocks; base += 1024) {
     const int i = base + threadIdx.x;
-    const int v = i < nblocks ? counts[i] : 0;
-    // inclusive scan within the wave
-    int incl = v;
+    const int v = i < nblocks ? m.counts[i] : 0;
+    int incl = v;  // inclusive scan within the wave
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -317,81 +398,92 @@ static __global__ __launch_bounds__(1024) void k_scan_counts(const Ctl* ctl, int
     int wbase = 0;
     for (int k = 0; k < w; k++) wbase += s_w[k];
     const int carry = s_carry;
-    if (i < nblocks) counts[i] = carry + wbase + incl - v;
+    if (i < nblocks) m.counts[i] = carry + wbase + incl - v;
     __syncthreads();
     if (threadIdx.x == 1023) s_carry = carry + wbase + incl;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *total = s_carry;
+  if (threadIdx.x == 0) *m.n_out = s_carry;
 }
 
 // rank[root] = 1-based label of the component rooted there
-static __global__ __launch_bounds__(RANK_BLOCK) void k_write_rank(const Ctl* ctl, MapDims d, const int* par,
-                                                          const int* offs, int* rank) {
-  if (ctl->stopped) return;
-  const long long c = blockIdx.x * (long long)RANK_BLOCK + threadIdx.x;
-  const int is_root = (c < d.N && par[c] == (int)c) ? 1 : 0;
+static __global__ __launch_bounds__(RANK_BLOCK) void k_write_rank(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  const long long c = bid * (long long)RANK_BLOCK + threadIdx.x;
+  const int is_root = (c < m.d.N && m.par[c] == (int)c) ? 1 : 0;
   __shared__ int s[RANK_BLOCK / 64];
   const unsigned long long bal = __ballot(is_root);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) s[w] = __popcll(bal);
   __syncthreads();
   if (is_root) {
-    int before = offs[blockIdx.x];
+    int before = m.counts[bid];
     for (int k = 0; k < w; k++) before += s[k];
     before += __popcll(bal & ((1ull << lane) - 1ull));
-    rank[c] = before + 1;
+    m.rank[c] = before + 1;
   }
 }
 
-static __global__ void k_write_labels(const Ctl* ctl, MapDims d, const int* par, const int* rank, int* label) {
-  if (ctl->stopped) return;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < d.N;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int p = par[c];
-    label[c] = p < 0 ? 0 : rank[p];
+static __global__ __launch_bounds__(MAP_NT) void k_write_labels(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  FOR_SHARE(c, m.d.N) {
+    const int p = m.par[c];
+    m.label[c] = p < 0 ? 0 : m.rank[p];
+  }
+}
+
+// ---- previous labels and aliases, kept for the alias carry ----
+static __global__ __launch_bounds__(MAP_NT) void k_keep_old(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  const int nb = m.ctl->maps_seen ? m.ctl->n_bubbles : 0;  // labels of the maps in force
+  if (bid == 0 && threadIdx.x == 0) m.ctl->nb_old = nb;  // read by k_alias_reset, after the scan
+  if (!m.ctl->maps_seen) return;
+  FOR_SHARE(c, m.d.N) {
+    m.label_old[c] = m.label[c];
+    if (c <= nb) m.alias_old[c] = m.alias[c];
   }
 }
 
 // ---- owner / dist ----
 // The layered BFS keeps two bitsets with one 64-bit word per row segment
 // (word s covers x = 64 xs .. 64 xs + 63 of row (m, z), s = xs + nxs row):
-// the frontier of the previous layer and the visited set.  A wavefront handles
-// one segment; the neighbour words it needs are wave-uniform loads, so finding
-// the cells a layer reaches takes bit operations instead of neighbour gathers.
-// Only newly reached cells read the owners of their frontier neighbours.
-static __global__ __launch_bounds__(MAP_NT) void k_owner_init(const Ctl* ctl, MapDims d, const int* label, int2* own,
-                                                       uint8_t* dist, unsigned long long* front,
-                                                       unsigned long long* vis) {
-  if (ctl->stopped) return;
+// the frontier of the previous layer and the visited set.
+static __global__ __launch_bounds__(MAP_NT) void k_owner_init(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  const MapDims d = m.d;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nxs = (d.nx + 63) >> 6;
   const unsigned nseg = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
-  for (unsigned s = blockIdx.x * MAP_WAVES + wv; s < nseg; s += gridDim.x * MAP_WAVES) {
+  for (unsigned s = bid * MAP_WAVES + wv; s < nseg; s += nbk * MAP_WAVES) {
     const unsigned row = s / (unsigned)nxs;
     const int x = (int)(s - row * (unsigned)nxs) * 64 + lane;
     const bool in = x < d.nx;
     const unsigned c = (unsigned)x + (unsigned)d.nx * row;
-    const int l = in ? label[c] : 0;
+    const int l = in ? m.label[c] : 0;
     if (in) {
-      own[c] = make_int2(l, l);
-      dist[c] = l > 0 ? 0 : 255;
+      m.own[c] = make_int2(l, l);
+      m.dist[c] = l > 0 ? 0 : 255;
     }
     const unsigned long long g = __ballot(l > 0);
     if (lane == 0) {
-      front[s] = g;
-      vis[s] = g;
+      m.fr0[s] = g;
+      m.vis[s] = g;
     }
   }
 }
 
-// One BFS layer, one 64-bit word (64 x-cells of a row) per lane: the words
-// reached this layer are the unvisited bits of the frontier dilated by the
-// lattice links, formed with whole-word shifts of the neighbour rows' words
-// (x - 1 and x + 1 bring in one bit from the adjacent word, periodic across
-// the row end).  Only the newly reached cells then read the owners of their
-// frontier neighbours.  Word bits past the end of a row are always zero.
+// One BFS layer in two passes.  The reach pass works on one 64-bit word (64
+// x-cells of a row) per lane: the cells reached this layer are the unvisited
+// bits of the frontier dilated by the lattice links, formed with whole-word
+// shifts of the neighbour rows' words (x - 1 and x + 1 bring in one bit from
+// the adjacent word, periodic across the row end).  The owner pass then lets
+// only the newly reached cells read the owners of their neighbours of the
+// previous layer.  Word bits past the end of a row are always zero.
 struct WordRow {
   const unsigned long long* __restrict__ b;
   int nxs, last_valid;  // words per row; valid bits of a row's last word
@@ -410,18 +502,20 @@ struct WordRow {
   }
 };
 
+// Reach pass of BFS layer `layer`, one word per lane (no per-cell work).
 template <class L>
-__global__ __launch_bounds__(MAP_NT) void k_owner_layer(const Ctl* ctl, MapDims d, int layer,
-                                                        const unsigned long long* __restrict__ fin,
-                                                        unsigned long long* __restrict__ fout,
-                                                        unsigned long long* __restrict__ vis, int2* own,
-                                                        uint8_t* dist) {
-  if (ctl->stopped) return;
+__global__ __launch_bounds__(MAP_NT) void k_bfs_reach(MAP_KERNEL_PARAMS, int layer) {
+  MAP_MEMBER
+  if (!map_due(m) || layer > m.zone_width - 1) return;
+  const MapDims d = m.d;
+  const unsigned long long* fin = (layer & 1) ? m.fr0 : m.fr1;
+  unsigned long long* fout = (layer & 1) ? m.fr1 : m.fr0;
+  unsigned long long* vis = m.vis;
   const int nxs = (d.nx + 63) >> 6;
   const unsigned nw = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
   const int last_valid = d.nx - 64 * (nxs - 1);
   const WordRow fr{fin, nxs, last_valid};
-  for (unsigned s = blockIdx.x * MAP_NT + threadIdx.x; s < nw; s += gridDim.x * MAP_NT) {
+  for (unsigned s = bid * MAP_NT + threadIdx.x; s < nw; s += nbk * MAP_NT) {
     const unsigned row = s / (unsigned)nxs;
     const int xs = (int)(s - row * (unsigned)nxs);
     const unsigned long long valid = (xs == nxs - 1 && last_valid < 64) ? (1ull << last_valid) - 1ull : ~0ull;
@@ -430,176 +524,241 @@ __global__ __launch_bounds__(MAP_NT) void k_owner_layer(const Ctl* ctl, MapDims 
       fout[s] = 0ull;
       continue;
     }
-    const int m = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
-    const int mm[3] = {m == 0 ? d.nm - 1 : m - 1, m, m == d.nm - 1 ? 0 : m + 1};
+    const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
+    const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
     const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
-    unsigned long long sh[L::Q];  // sh[i] bit l: the cell x + e_i of x = 64 xs + l is on the frontier
     unsigned long long reach = 0ull;
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
       const unsigned rb = (unsigned)nxs * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
-      sh[i] = fr.shifted(rb, xs, L::ex[i]);
-      reach |= sh[i];
+      reach |= fr.shifted(rb, xs, L::ex[i]);
     }
-    unsigned long long nwb = reach & ~v & valid;
+    const unsigned long long nwb = reach & ~v & valid;
     fout[s] = nwb;
     vis[s] = v | nwb;
-    const unsigned cbase = (unsigned)xs * 64u + (unsigned)d.nx * row;
-    while (nwb) {
-      const int l = __builtin_ctzll(nwb);
-      nwb &= nwb - 1ull;
-      const int x = xs * 64 + l;
-      const int xw[3] = {x == 0 ? d.nx - 1 : x - 1, x, x == d.nx - 1 ? 0 : x + 1};
-      int lo = 0, hi = 0;
-#pragma unroll
-      for (int i = 1; i < L::Q; i++) {
-        if (!((sh[i] >> l) & 1ull)) continue;
-        const unsigned y = (unsigned)xw[1 + L::ex[i]] +
-                           (unsigned)d.nx * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
-        const int2 o = own[y];
-        lo = (lo == 0 || o.x < lo) ? o.x : lo;
-        hi = o.y > hi ? o.y : hi;
-      }
-      own[cbase + (unsigned)l] = make_int2(lo, hi);
-      dist[cbase + (unsigned)l] = (uint8_t)layer;
-    }
   }
 }
 
-// keep the previous labels and aliases for the carry (a device copy, so that
-// a refresh queued after a stop leaves everything untouched)
-static __global__ void k_copy_int(const Ctl* ctl, const int* src, int* dst, long long n) {
-  if (ctl->stopped) return;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x)
-    dst[c] = src[c];
+// Owner pass of BFS layer `layer`: a wavefront per row segment; segments
+// that reached nothing return after one word load; a newly reached cell takes
+// the smallest owner and the largest owner2 of its neighbours of the
+// previous layer.
+template <class L>
+__global__ __launch_bounds__(MAP_NT) void k_bfs_owner(MAP_KERNEL_PARAMS, int layer) {
+  MAP_MEMBER
+  if (!map_due(m) || layer > m.zone_width - 1) return;
+  const MapDims d = m.d;
+  const unsigned long long* fnew = (layer & 1) ? m.fr1 : m.fr0;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nxs = (d.nx + 63) >> 6;
+  const unsigned nseg = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
+  for (unsigned s = bid * MAP_WAVES + wv; s < nseg; s += nbk * MAP_WAVES) {
+    const unsigned long long w = fnew[s];
+    if (!((w >> lane) & 1ull)) continue;
+    const unsigned row = s / (unsigned)nxs;
+    const int x = (int)(s - row * (unsigned)nxs) * 64 + lane;
+    const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
+    const int xw[3] = {x == 0 ? d.nx - 1 : x - 1, x, x == d.nx - 1 ? 0 : x + 1};
+    const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
+    const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
+    // every neighbour's distance and owners are loaded before any is used,
+    // so the loads of a lane overlap instead of waiting one after another
+    uint8_t dn[L::Q];
+    int2 on[L::Q];
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {
+      const unsigned y = (unsigned)xw[1 + L::ex[i]] +
+                         (unsigned)d.nx * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
+      dn[i] = m.dist[y];
+      on[i] = m.own[y];
+    }
+    int lo = 0x7fffffff, hi = 0;
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {
+      const bool f = dn[i] == layer - 1;
+      lo = f ? min(lo, on[i].x) : lo;
+      hi = f ? max(hi, on[i].y) : hi;
+    }
+    const unsigned c = (unsigned)x + (unsigned)d.nx * row;
+    m.own[c] = make_int2(lo, hi);
+    m.dist[c] = (uint8_t)layer;
+  }
 }
 
 // ---- alias carry across a refresh ----
-static __global__ void k_alias_reset(const Ctl* ctl, int* alias, int* rep, int nb_cap) {
-  if (ctl->stopped) return;
-  const int nb = ctl->n_bubbles;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= nb_cap; b += gridDim.x * blockDim.x) {
-    if (b <= nb) alias[b] = b;
-    rep[b] = 0x7fffffff;
+static __global__ __launch_bounds__(MAP_NT) void k_alias_reset(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  const int nb = m.ctl->n_bubbles, nb_old = m.ctl->nb_old;
+  FOR_SHARE(b, (long long)max(nb, nb_old) + 1) {
+    if (b <= nb) m.alias[b] = (int)b;
+    if (b <= nb_old) m.rep[b] = 0x7fffffff;  // indexed by classes of the previous labels
   }
 }
 
 // Both carry passes run over whole wavefronts (the loop bound is uniform per
 // wavefront) and merge the many lanes that carry the same (old class, new
 // label) pair before touching global memory.
-static __global__ __launch_bounds__(MAP_NT) void k_alias_carry1(const Ctl* ctl, MapDims d, const int* label,
-                                                         const int* label_old, const int* alias_old, int* rep) {
-  if (ctl->stopped) return;
+static __global__ __launch_bounds__(MAP_NT) void k_alias_carry1(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m) || !m.ctl->maps_seen) return;
   const int lane = threadIdx.x & 63;
-  const long long stride = (long long)gridDim.x * MAP_NT;
-  for (long long base = blockIdx.x * (long long)MAP_NT + (threadIdx.x & ~63); base < d.N; base += stride) {
+  const long long stride = (long long)nbk * MAP_NT;
+  for (long long base = bid * (long long)MAP_NT + (threadIdx.x & ~63); base < m.d.N; base += stride) {
     const long long c = base + lane;
     int b = 0, a = 0;
-    if (c < d.N) {
-      b = label[c];
-      a = label_old[c];
+    if (c < m.d.N) {
+      b = m.label[c];
+      a = m.label_old[c];
     }
     bool pend = b > 0 && a > 0;
-    const int r = pend ? uf_root(alias_old, a) : 0;
+    const int r = pend ? uf_root(m.alias_old, a) : 0;
     unsigned long long mk = __ballot(pend);
     while (mk) {
       const int ld = first_lane(mk);
       const int r0 = __shfl(r, ld, 64);
       const bool mine = pend && r == r0;
       const int bmin = wave_min_i32(mine ? b : 0x7fffffff);
-      if (lane == ld && __atomic_load_n(&rep[r0], __ATOMIC_RELAXED) > bmin) atomicMin(&rep[r0], bmin);
+      if (lane == ld && __atomic_load_n(&m.rep[r0], __ATOMIC_RELAXED) > bmin) atomicMin(&m.rep[r0], bmin);
       if (mine) pend = false;
       mk = __ballot(pend);
     }
   }
 }
 
-static __global__ __launch_bounds__(MAP_NT) void k_alias_carry2(const Ctl* ctl, MapDims d, const int* label,
-                                                         const int* label_old, const int* alias_old,
-                                                         const int* rep, int* alias) {
-  if (ctl->stopped) return;
+static __global__ __launch_bounds__(MAP_NT) void k_alias_carry2(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m) || !m.ctl->maps_seen) return;
   const int lane = threadIdx.x & 63;
-  const long long stride = (long long)gridDim.x * MAP_NT;
-  for (long long base = blockIdx.x * (long long)MAP_NT + (threadIdx.x & ~63); base < d.N; base += stride) {
+  const long long stride = (long long)nbk * MAP_NT;
+  for (long long base = bid * (long long)MAP_NT + (threadIdx.x & ~63); base < m.d.N; base += stride) {
     const long long c = base + lane;
     int b = 0, a = 0;
-    if (c < d.N) {
-      b = label[c];
-      a = label_old[c];
+    if (c < m.d.N) {
+      b = m.label[c];
+      a = m.label_old[c];
     }
-    const int r = (b > 0 && a > 0) ? rep[uf_root(alias_old, a)] : 0;
+    const int r = (b > 0 && a > 0) ? m.rep[uf_root(m.alias_old, a)] : 0;
     bool pend = b > 0 && a > 0 && r != b;
     unsigned long long mk = __ballot(pend);
     while (mk) {
       const int ld = first_lane(mk);
       const int b0 = __shfl(b, ld, 64), r0 = __shfl(r, ld, 64);
-      if (lane == ld) uf_unite(alias, b0, r0);
+      if (lane == ld) uf_unite(m.alias, b0, r0);
       if (pend && b == b0 && r == r0) pend = false;
       mk = __ballot(pend);
     }
   }
 }
 
-static __global__ void k_alias_compress(const Ctl* ctl, int* alias) {
-  if (ctl->stopped) return;
-  const int nb = ctl->n_bubbles;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= nb; b += gridDim.x * blockDim.x)
-    alias[b] = uf_find_live(alias, b);
+static __global__ __launch_bounds__(MAP_NT) void k_alias_compress(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m) || !m.ctl->maps_seen) return;
+  const int nb = m.ctl->n_bubbles;
+  FOR_SHARE(b, (long long)nb + 1) m.alias[b] = uf_find_live(m.alias, (int)b);
 }
 
-// ---- barrier candidate masks ----
 // Barrier masks from the owner maps, and the list of cells that have barrier
 // links (appended a wavefront at a time; its order is irrelevant to the
-// results).  ctl->n_flagged must be zero before the launch.
+// results).  A workgroup stages the owners and distances of its tile and a
+// one-cell halo in LDS, so the 18 neighbour tests of a cell read LDS.
+// ctl->n_flagged must be zero before the launch.
 template <class L>
-__global__ __launch_bounds__(MAP_NT) void k_masks(Ctl* ctl, MapDims d, int zone_width, const int2* own,
-                                                  const uint8_t* dist, const int* alias, uint8_t* flag,
-                                                  uint32_t* mask, int* flist) {
-  if (ctl->stopped) return;
+struct MaskTile {
+  static constexpr int HM = L::HAS_M ? 1 : 0;
+  static constexpr int TM = L::HAS_M ? 4 : 1;
+  static constexpr int TZ = L::HAS_M ? 4 : 16;
+  static constexpr int LX = 66, LM = TM + 2 * HM, LZ = TZ + 2;
+  static constexpr int NL = LX * LM * LZ;
+  static constexpr int NC = 64 * TM * TZ;
+};
+
+template <class L>
+__host__ inline int mask_tiles(const MapDims& d) {
+  using MT = MaskTile<L>;
+  return ((d.nx + 63) / 64) * ((d.nm + MT::TM - 1) / MT::TM) * ((d.nz + MT::TZ - 1) / MT::TZ);
+}
+
+template <class L>
+__global__ __launch_bounds__(MAP_NT) void k_masks(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  using MT = MaskTile<L>;
+  __shared__ int2 s_rp[MT::NL];  // alias-root pair of the cell's owners
+  __shared__ uint8_t s_dist[MT::NL];
+  const MapDims d = m.d;
+  const int zone_width = m.zone_width;
+  const int ntx = (d.nx + 63) / 64, ntm = (d.nm + MT::TM - 1) / MT::TM;
+  const int b = (int)bid;
+  const int x0 = (b % ntx) * 64, m0 = ((b / ntx) % ntm) * MT::TM, z0 = (b / (ntx * ntm)) * MT::TZ;
+  // staging: every load of a thread is issued before any is used
+  constexpr int SPT = (MT::NL + MAP_NT - 1) / MAP_NT;
+  uint8_t dd[SPT];
+  int2 oo[SPT];
+#pragma unroll
+  for (int j = 0; j < SPT; j++) {
+    const int idx = threadIdx.x + j * MAP_NT;
+    const int lx = idx % MT::LX, r = idx / MT::LX;
+    const int lm = r % MT::LM, lz = r / MT::LM;
+    const int gx = wrap_any(x0 - 1 + lx, d.nx);
+    const int gm = L::HAS_M ? wrap_any(m0 - 1 + lm, d.nm) : 0;
+    const int gz = wrap_any(z0 - 1 + min(lz, MT::LZ - 1), d.nz);
+    const unsigned g = (unsigned)gx + (unsigned)d.nx * ((unsigned)gm + (unsigned)d.nm * (unsigned)gz);
+    dd[j] = m.dist[g];
+    oo[j] = m.own[g];
+  }
+  int2 ra[SPT];
+#pragma unroll
+  for (int j = 0; j < SPT; j++) ra[j] = dd[j] != 255 ? make_int2(m.alias[oo[j].x], m.alias[oo[j].y]) : make_int2(0, 0);
+#pragma unroll
+  for (int j = 0; j < SPT; j++) {
+    const int idx = threadIdx.x + j * MAP_NT;
+    if (idx < MT::NL) {
+      s_dist[idx] = dd[j];
+      // the aliases are compressed at every refresh: one look-up gives the root
+      s_rp[idx] = dd[j] != 255 ? make_int2(min(ra[j].x, ra[j].y), max(ra[j].x, ra[j].y)) : make_int2(0, 0);
+    }
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
-  for_cells<true>(d, [&](const SegCell& q) {
-    const int2 o = own[q.c];
+  for (int k = threadIdx.x; k < MT::NC; k += MAP_NT) {  // uniform trip count
+    const int lx = k & 63, lm = (k >> 6) % MT::TM, lz = (k >> 6) / MT::TM;
+    const int x = x0 + lx, mm_ = m0 + lm, z = z0 + lz;
+    const bool valid = x < d.nx && mm_ < d.nm && z < d.nz;
+    const int li = (lx + 1) + MT::LX * ((lm + MT::HM) + MT::LM * (lz + 1));
     unsigned mk = 0;
-    if (o.x > 0) {
-      int2 rp = make_int2(0, 0);
-      bool have_rp = false;
-      const int dc = dist[q.c];
+    const int dc = s_dist[li];
+    if (valid && dc != 255) {
+      const int2 rp = s_rp[li];
 #pragma unroll
       for (int i = 1; i < L::Q; i++) {
-        const unsigned y = q.nb(L::ex[i], L::em[i], L::ez[i]);
-        if (dc + (int)dist[y] + 1 > zone_width) continue;  // also rejects unowned ends (dist 255)
-        const int2 oy = own[y];
-        if (oy.x == o.x && oy.y == o.y) continue;  // same owner pair, same root pair
-        if (!have_rp) {
-          rp = root_pair(alias, o);
-          have_rp = true;
-        }
-        const int2 rq = root_pair(alias, oy);
-        if (rq.x != rp.x || rq.y != rp.y) mk |= 1u << i;
+        const int ln = li + L::ex[i] + MT::LX * (L::em[i] + MT::LM * L::ez[i]);
+        const int2 rq = s_rp[ln];
+        // both ends owned (dist 255 fails the sum), thin enough, different pairs
+        if (dc + (int)s_dist[ln] + 1 <= zone_width && (rq.x != rp.x || rq.y != rp.y)) mk |= 1u << i;
       }
     }
-    flag[q.c] = mk ? 1 : 0;
-    mask[q.c] = mk;
+    const unsigned c = (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z);
+    if (valid) {
+      m.flag[c] = mk ? 1 : 0;
+      m.mask[c] = mk;
+    }
     const unsigned long long bal = __ballot(mk != 0);
     if (bal) {
       const int ld = first_lane(bal);
       unsigned base = 0;
-      if (lane == ld) base = atomicAdd(&ctl->n_flagged, (unsigned)__popcll(bal));
+      if (lane == ld) base = atomicAdd(&m.ctl->n_flagged, (unsigned)__popcll(bal));
       base = __shfl(base, ld, 64);
-      if (mk) flist[base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull))] = (int)q.c;
+      if (mk) m.flist[base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull))] = (int)c;
     }
-  });
+  }
 }
 
 // an empty flagged-cell list before k_masks fills it
-static __global__ void k_flag_list_reset(Ctl* ctl) {
-  if (!ctl->stopped && threadIdx.x == 0) ctl->n_flagged = 0;
-}
-
-// the masks just built reflect the current aliases
-static __global__ void k_masks_done(Ctl* ctl) {
-  if (!ctl->stopped && threadIdx.x == 0) ctl->alias_dirty = 0;
+static __global__ void k_flag_list_reset(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (map_due(m) && threadIdx.x == 0) m.ctl->n_flagged = 0;
 }
 
 // Lattice coordinates of listed cell c (a division per cell; lists are sparse).
@@ -633,23 +792,52 @@ __device__ __forceinline__ void for_list(unsigned n, unsigned bid, unsigned nb, 
 // Marks every cell whose density the rupture test reads: both ends and the
 // outer neighbours of every barrier link.
 template <class L>
-__global__ __launch_bounds__(MAP_NT) void k_rho_marks(const Ctl* ctl, MapDims d, const int* flist,
-                                                      uint32_t* mask) {
-  if (ctl->stopped) return;
-  const unsigned n = ctl->n_flagged;
-  for_list(n, blockIdx.x, gridDim.x, [&](unsigned idx, bool act) {
+__global__ __launch_bounds__(MAP_NT) void k_rho_marks(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  const MapDims d = m.d;
+  for_list(m.ctl->n_flagged, bid, nbk, [&](unsigned idx, bool act) {
     if (!act) return;
-    const unsigned c = (unsigned)flist[idx];
+    const unsigned c = (unsigned)m.flist[idx];
     const ListCell q(d, c);
-    const unsigned mk = mask[c] & kLinkBits;
-    atomicOr(&mask[c], kRhoBit);
+    const unsigned mk = m.mask[c] & kLinkBits;
+    atomicOr(&m.mask[c], kRhoBit);
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
       if (!(mk & (1u << i))) continue;
-      atomicOr(&mask[q.nb(d, L::ex[i], L::em[i], L::ez[i])], kRhoBit);
-      atomicOr(&mask[q.nb(d, -L::ex[i], -L::em[i], -L::ez[i])], kRhoBit);
+      atomicOr(&m.mask[q.nb(d, L::ex[i], L::em[i], L::ez[i])], kRhoBit);
+      atomicOr(&m.mask[q.nb(d, -L::ex[i], -L::em[i], -L::ez[i])], kRhoBit);
     }
   });
+}
+
+// the maps just built reflect the current aliases, and the next refresh can
+// carry aliases from them
+static __global__ void k_masks_done(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (map_due(m) && threadIdx.x == 0) {
+    m.ctl->alias_dirty = 0;
+    m.ctl->maps_seen = 1;
+  }
+}
+
+// workgroups of lattice d for each decomposition
+template <class L>
+__host__ inline int map_share(int shape, const MapDims& d) {
+  const long long N = d.N;
+  const long long nseg = (long long)((d.nx + 63) / 64) * d.nm * d.nz;
+  long long g = 1;
+  switch (shape) {
+    case SH_CELLS: g = std::min<long long>((N + 1 + MAP_NT - 1) / MAP_NT, 16384); break;
+    case SH_SEG: g = std::min<long long>((nseg + MAP_WAVES - 1) / MAP_WAVES, 65536); break;
+    case SH_WORDS: g = std::min<long long>((nseg + MAP_NT - 1) / MAP_NT, 65536); break;
+    case SH_CCT: g = cc_tiles(d, CCTile<L>::TM, CCTile<L>::TZ); break;
+    case SH_MT: g = mask_tiles<L>(d); break;
+    case SH_RANK: g = (N + RANK_BLOCK - 1) / RANK_BLOCK; break;
+    case SH_ONE: g = 1; break;
+    case SH_LIST: g = list_grid(N); break;
+  }
+  return (int)std::max<long long>(g, 1);
 }
 
 // After a step whose ruptures united bubbles: drop the links whose two ends

@@ -126,6 +126,18 @@ inline size_t ctx_footprint(const flb_params* p) {
   return t;
 }
 
+// A MapSet is a device table of MapArgs plus, per decomposition, the
+// workgroup ranges of its lattices.  Tables of one lattice serve a context;
+// a batch builds one over its film members.
+struct MapSet {
+  MapArgs* tab = nullptr;  // device, n entries
+  int* first = nullptr;    // device, SH_COUNT arrays of n + 1 offsets
+  int n = 0;
+  int total[SH_COUNT] = {};
+  int max_zone = 0;
+  const int* first_of(int sh) const { return first + sh * (n + 1); }
+};
+
 }  // namespace flb_rt
 
 struct flb_ctx {
@@ -165,7 +177,10 @@ struct flb_ctx {
   long long nwords = 0;                // 64-bit words per bitset
   long long* events = nullptr;
   unsigned ev_cap = 1u << 16;
-  bool maps_seen = false;  // a refresh has run since the last set_nuclei
+  // map-kernel tables: film refresh from the state or the rho array, label
+  // queries from the state or a field
+  flb_rt::MapSet ms_pop, ms_rho, qs_pop, qs_field;
+  bool ms_ready = false;
   // query scratch
   double* qd = nullptr;    // (1 + 3) * N doubles
   int* qlabel = nullptr;
@@ -296,69 +311,149 @@ inline PruneArgs prune_args(flb_ctx* c) {
   return p;
 }
 
-// ---- labels of the current state (or of a density field) into `label` ----
-template <class L, class S>
-int label_pipeline(flb_ctx* c, const Ctl* gate, int* total, int* label, const double* field,
-                   bool from_rho = false) {
-  const int B = 256, g = grid_for(c->N, B);
-  if (field)
-    hipLaunchKernelGGL(k_gas_from_field, dim3(g), dim3(B), 0, c->st, field, c->md, c->p.rho_th, c->par);
-  else if (from_rho)
-    hipLaunchKernelGGL((k_gas_from_rho<typename S::ct>), dim3(g), dim3(B), 0, c->st, gate,
-                       (const typename S::ct*)c->rho, c->md, c->p.rho_th, c->par);
-  else
-    hipLaunchKernelGGL((k_gas_init<L, S>), dim3(map_grid(c->md)), dim3(MAP_NT), 0, c->st, c->f[0], c->f[1], gate, c->geo, c->md,
-                       c->p.rho_th, c->par);
-  hipLaunchKernelGGL((k_cc_local<L>), dim3(cc_tiles(c->md, CCTile<L>::TM, CCTile<L>::TZ)), dim3(CC_NT), 0, c->st,
-                     gate, c->md, c->par);
-  hipLaunchKernelGGL((k_cc_cross<L>), dim3(map_grid(c->md)), dim3(MAP_NT), 0, c->st, gate, c->md, c->par);
-  hipLaunchKernelGGL(k_cc_compress, dim3(g), dim3(B), 0, c->st, gate, c->md, c->par);
-  const int nrb = (int)((c->N + RANK_BLOCK - 1) / RANK_BLOCK);
-  hipLaunchKernelGGL(k_count_roots, dim3(nrb), dim3(RANK_BLOCK), 0, c->st, gate, c->md, c->par, c->counts);
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, c->st, gate, c->counts, nrb, total);
-  hipLaunchKernelGGL(k_write_rank, dim3(nrb), dim3(RANK_BLOCK), 0, c->st, gate, c->md, c->par, c->counts,
-                     c->rank);
-  hipLaunchKernelGGL(k_write_labels, dim3(g), dim3(B), 0, c->st, gate, c->md, c->par, c->rank, label);
-  HIPCHK(hipGetLastError());
+// ---- map pipelines over tables of lattices ----
+// Builds (or rebuilds, reusing storage of the same size) a map set.  `alloc`
+// allocates device memory that lives as long as the owner.
+template <class Alloc>
+int mapset_build(MapSet& ms, const std::vector<MapArgs>& args, int D, Alloc&& alloc, hipStream_t st) {
+  const int n = (int)args.size();
+  if (!ms.tab || ms.n != n) {
+    ms.tab = (MapArgs*)alloc(sizeof(MapArgs) * (size_t)n);
+    ms.first = (int*)alloc(sizeof(int) * (size_t)SH_COUNT * (n + 1));
+    if (!ms.tab || !ms.first) return fail(FLB_ENOMEM, "map table allocation failed");
+  }
+  ms.n = n;
+  std::vector<int> first((size_t)SH_COUNT * (n + 1), 0);
+  ms.max_zone = 0;
+  for (int sh = 0; sh < SH_COUNT; sh++) {
+    int* f = first.data() + sh * (n + 1);
+    for (int k = 0; k < n; k++)
+      f[k + 1] = f[k] + (D == 2 ? map_share<D2Q9K>(sh, args[k].d) : map_share<D3Q19K>(sh, args[k].d));
+    ms.total[sh] = f[n];
+  }
+  for (const MapArgs& a : args) ms.max_zone = std::max(ms.max_zone, a.zone_width);
+  HIPCHK(hipMemcpyAsync(ms.tab, args.data(), sizeof(MapArgs) * (size_t)n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ms.first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
   return FLB_OK;
 }
 
-// ---- film-map refresh before a step ----
+// The map arguments of a context: its film refresh (gated by its own run
+// control and k_own), or a labels-only query (gated by the zeroed query
+// control) from the stored state, a host field or the two-pass rho array.
+inline MapArgs map_args(flb_ctx* c, bool query, int src) {
+  MapArgs a;
+  memset(&a, 0, sizeof a);
+  a.ctl = query ? c->qctl : c->ctl;
+  a.sctl = c->ctl;
+  a.d = c->md;
+  a.geo = c->geo;
+  a.b0 = c->f[0];
+  a.b1 = c->f[1];
+  a.src = src == GAS_FIELD ? (const void*)c->qd : (src == GAS_RHO ? c->rho : nullptr);
+  a.rho_th = c->p.rho_th;
+  a.k_own = query ? 0 : c->p.k_own;
+  a.zone_width = c->p.zone_width;
+  a.refresh = query ? 0 : 1;
+  a.nrb = (int)((c->N + RANK_BLOCK - 1) / RANK_BLOCK);
+  a.par = c->par;
+  a.rank = c->rank;
+  a.counts = c->counts;
+  a.label = query ? c->qlabel : c->label;
+  a.n_out = query ? &c->qctl->n_bubbles : &c->ctl->n_bubbles;
+  if (!query) {
+    a.label_old = c->label_old;
+    a.alias = c->alias;
+    a.alias_old = c->alias_old;
+    a.rep = c->rep;
+    a.own = c->own;
+    a.dist = c->dist;
+    a.flag = c->flag;
+    a.mask = c->mask;
+    a.flist = c->flist;
+    a.fr0 = c->bits;
+    a.fr1 = c->bits + c->nwords;
+    a.vis = c->bits + 2 * c->nwords;
+  }
+  return a;
+}
+
+#define MAPL(K, SH, NT, ...) \
+  hipLaunchKernelGGL(K, dim3(s.total[SH]), dim3(NT), 0, st, s.tab, s.first_of(SH), s.n, ##__VA_ARGS__)
+
+// Labels (gas cells, connected components, canonical ranks), and for a film
+// refresh also owners and distances, alias carry, barrier masks, the list of
+// flagged cells and its density marks.  No synchronisation; capturable.
+template <class L, class S>
+int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh) {
+  if (refresh) MAPL(k_keep_old, SH_CELLS, MAP_NT);
+  if (src == GAS_POP) MAPL((k_gas<L, S, GAS_POP>), SH_SEG, MAP_NT);
+  else if (src == GAS_FIELD) MAPL((k_gas<L, S, GAS_FIELD>), SH_CELLS, MAP_NT);
+  else MAPL((k_gas<L, S, GAS_RHO>), SH_CELLS, MAP_NT);
+  MAPL((k_cc_local<L>), SH_CCT, CC_NT);
+  MAPL((k_cc_cross<L>), SH_SEG, MAP_NT);
+  MAPL(k_cc_compress, SH_CELLS, MAP_NT);
+  MAPL(k_count_roots, SH_RANK, RANK_BLOCK);
+  MAPL(k_scan_counts, SH_ONE, 1024);
+  MAPL(k_write_rank, SH_RANK, RANK_BLOCK);
+  MAPL(k_write_labels, SH_CELLS, MAP_NT);
+  if (refresh) {
+    MAPL(k_owner_init, SH_SEG, MAP_NT);
+    for (int layer = 1; layer <= s.max_zone - 1; layer++) {
+      MAPL((k_bfs_reach<L>), SH_WORDS, MAP_NT, layer);
+      MAPL((k_bfs_owner<L>), SH_SEG, MAP_NT, layer);
+    }
+    MAPL(k_alias_reset, SH_CELLS, MAP_NT);
+    MAPL(k_alias_carry1, SH_CELLS, MAP_NT);
+    MAPL(k_alias_carry2, SH_CELLS, MAP_NT);
+    MAPL(k_alias_compress, SH_CELLS, MAP_NT);
+    MAPL(k_flag_list_reset, SH_ONE, 64);
+    MAPL((k_masks<L>), SH_MT, MAP_NT);
+    MAPL((k_rho_marks<L>), SH_LIST, MAP_NT);
+    MAPL(k_masks_done, SH_ONE, 64);
+  }
+  HIPCHK(hipGetLastError());
+  return FLB_OK;
+}
+#undef MAPL
+
+// the context's own map sets, built on first use
+inline int ctx_mapsets(flb_ctx* c) {
+  if (c->ms_ready) return FLB_OK;
+  auto al = [c](size_t n) { return c->dalloc(n); };
+  std::vector<MapArgs> q{map_args(c, true, GAS_POP)};
+  int rc = mapset_build(c->qs_pop, q, c->D, al, c->st);
+  if (!rc) {
+    q[0] = map_args(c, true, GAS_FIELD);
+    rc = mapset_build(c->qs_field, q, c->D, al, c->st);
+  }
+  if (!rc && c->p.film_on) {
+    std::vector<MapArgs> r{map_args(c, false, GAS_POP)};
+    rc = mapset_build(c->ms_pop, r, c->D, al, c->st);
+    if (!rc) {
+      r[0] = map_args(c, false, GAS_RHO);
+      rc = mapset_build(c->ms_rho, r, c->D, al, c->st);
+    }
+  }
+  if (!rc) c->ms_ready = true;
+  return rc;
+}
+
+// ---- film-map refresh of one context before its step ----
 template <class L, class S>
 int refresh_maps(flb_ctx* c, bool from_rho) {
-  const int B = 256, g = grid_for(c->N, B);
-  const int gl = grid_for(c->N + 1, B);
-  const Ctl* gate = c->ctl;
-  if (c->maps_seen) {
-    hipLaunchKernelGGL(k_copy_int, dim3(g), dim3(B), 0, c->st, gate, c->label, c->label_old, c->N);
-    hipLaunchKernelGGL(k_copy_int, dim3(gl), dim3(B), 0, c->st, gate, c->alias, c->alias_old, c->N + 1);
-  }
-  int rc = label_pipeline<L, S>(c, gate, &c->ctl->n_bubbles, c->label, nullptr, from_rho);
+  int rc = ctx_mapsets(c);
   if (rc) return rc;
-  unsigned long long* fr[2] = {c->bits, c->bits + c->nwords};
-  unsigned long long* vis = c->bits + 2 * c->nwords;
-  hipLaunchKernelGGL(k_owner_init, dim3(map_grid(c->md)), dim3(MAP_NT), 0, c->st, gate, c->md, c->label, c->own,
-                     c->dist, fr[0], vis);
-  for (int layer = 1; layer <= c->p.zone_width - 1; layer++)
-    hipLaunchKernelGGL((k_owner_layer<L>), dim3(grid_for(c->nwords, MAP_NT)), dim3(MAP_NT), 0, c->st, gate, c->md, layer,
-                       fr[(layer - 1) & 1], fr[layer & 1], vis, c->own, c->dist);
-  hipLaunchKernelGGL(k_alias_reset, dim3(gl), dim3(B), 0, c->st, gate, c->alias, c->rep, (int)c->N);
-  if (c->maps_seen) {
-    hipLaunchKernelGGL(k_alias_carry1, dim3(g), dim3(MAP_NT), 0, c->st, gate, c->md, c->label, c->label_old,
-                       c->alias_old, c->rep);
-    hipLaunchKernelGGL(k_alias_carry2, dim3(g), dim3(MAP_NT), 0, c->st, gate, c->md, c->label, c->label_old,
-                       c->alias_old, c->rep, c->alias);
-    hipLaunchKernelGGL(k_alias_compress, dim3(gl), dim3(B), 0, c->st, gate, c->alias);
-  }
-  hipLaunchKernelGGL(k_flag_list_reset, dim3(1), dim3(64), 0, c->st, c->ctl);
-  hipLaunchKernelGGL((k_masks<L>), dim3(map_grid(c->md)), dim3(MAP_NT), 0, c->st, c->ctl, c->md, c->p.zone_width,
-                     c->own, c->dist, c->alias, c->flag, c->mask, c->flist);
-  hipLaunchKernelGGL((k_rho_marks<L>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, gate, c->md, c->flist,
-                     c->mask);
-  hipLaunchKernelGGL(k_masks_done, dim3(1), dim3(64), 0, c->st, c->ctl);
-  HIPCHK(hipGetLastError());
-  c->maps_seen = true;
-  return FLB_OK;
+  return map_pipeline<L, S>(from_rho ? c->ms_rho : c->ms_pop, c->st, from_rho ? GAS_RHO : GAS_POP, true);
+}
+
+// ---- labels of the current state, or of the field in c->qd ----
+template <class L, class S>
+int label_query(flb_ctx* c, bool from_field) {
+  int rc = ctx_mapsets(c);
+  if (rc) return rc;
+  HIPCHK(hipMemsetAsync(c->qctl, 0, sizeof(Ctl), c->st));
+  return map_pipeline<L, S>(from_field ? c->qs_field : c->qs_pop, c->st, from_field ? GAS_FIELD : GAS_POP, false);
 }
 
 // `ev`, if given, holds 4 events per step that bracket the step-kernel launches

@@ -3,7 +3,9 @@
 //
 // Jobs queue in arrival order.  Each scheduling round admits queued jobs, in
 // order, while the device bytes of the admitted jobs stay within the pool
-// budget (and below the job limit), then advances every running job by the
+// budget, below the job limit and the running cells below max_cells (enough
+// to fill the GPU: beyond that, running more jobs at once lengthens every job
+// without adding throughput), then advances every running job by the
 // same number of steps -- the chunk, shortened so that no job passes its last
 // step -- with batched launches, one batch per lattice type and storage, so
 // jobs that arrived at different times share every launch.  A job whose
@@ -42,6 +44,7 @@ struct flb_server {
   hipStream_t st = nullptr;
   int64_t next_id = 1;
   size_t used = 0;
+  int64_t cells = 0;  // lattice cells of the running jobs
   int64_t n_done = 0;
   std::deque<Job*> queue;
   std::vector<Job*> running;
@@ -55,7 +58,9 @@ namespace {
 int admit(flb_server* s) {
   while (!s->queue.empty() && (int)s->running.size() < s->cfg.max_jobs) {
     Job* j = s->queue.front();
+    const int64_t jc = (int64_t)j->p.nx * j->p.ny * j->p.nz;
     if (s->used + ctx_footprint(&j->p) > (size_t)s->cfg.pool_bytes) break;  // in order: wait for room
+    if (!s->running.empty() && s->cells + jc > s->cfg.max_cells) break;
     s->queue.pop_front();
     int rc = flb_create(&j->p, s->have_al ? &s->al : nullptr, s->st, &j->c);
     if (!rc) rc = flb_set_nuclei(j->c, j->nuc.data(), (int32_t)j->nuc.size());
@@ -68,6 +73,7 @@ int admit(flb_server* s) {
     }
     j->bytes = j->c->bytes;
     s->used += j->bytes;
+    s->cells += jc;
     j->state = FLB_JOB_RUNNING;
     s->running.push_back(j);
   }
@@ -103,6 +109,7 @@ void retire(flb_server* s, Job* j) {
     j->state = FLB_JOB_DONE;
   }
   s->used -= j->bytes;
+  s->cells -= j->c->N;
   flb_destroy(j->c);
   j->c = nullptr;
   s->n_done++;
@@ -118,6 +125,7 @@ void flb_server_default_config(flb_server_config* cfg) {
   cfg->max_jobs = 256;
   cfg->chunk_steps = 100;
   cfg->graph_steps = 20;
+  cfg->max_cells = (int64_t)1 << 24;
 }
 
 int flb_server_create(const flb_server_config* cfg, const flb_allocator* alloc, void* hip_stream,
@@ -129,6 +137,7 @@ int flb_server_create(const flb_server_config* cfg, const flb_allocator* alloc, 
   if (cfg->max_jobs < 1 || cfg->max_jobs > (1 << 16)) return fail(FLB_EINVAL, "max_jobs must be in 1..65536");
   if (cfg->chunk_steps < 1) return fail(FLB_EINVAL, "chunk_steps must be >= 1");
   if (cfg->graph_steps < 0 || cfg->graph_steps > 4096) return fail(FLB_EINVAL, "graph_steps must be in 0..4096");
+  if (cfg->max_cells < 1) return fail(FLB_EINVAL, "max_cells must be >= 1");
   if (alloc && (!alloc->alloc || !alloc->free)) return fail(FLB_EINVAL, "allocator needs alloc and free");
   flb_server* s = new (std::nothrow) flb_server();
   if (!s) return fail(FLB_ENOMEM, "host allocation failed");

@@ -186,6 +186,18 @@ __device__ __forceinline__ bool d2_may_be_nonneg(float rp, float rc, float rm, f
 // run offsets are small, so the offset sum cannot wrap into the buffer.
 constexpr unsigned kDropOffset = 0x80000000u;
 constexpr unsigned long long kBufPathLimit = 1ull << 31;
+// Cache-policy bits of the population loads and stores on the buffer path
+// (gfx950: bit 1 marks an access non-temporal).  A step reads and writes
+// twice the last-level cache many times over, so nothing it stores is read
+// back from the caches before the next step overwrites the working set.
+#ifndef FLB_LD_CPOL
+#define FLB_LD_CPOL 0
+#endif
+#ifndef FLB_ST_CPOL
+#define FLB_ST_CPOL 0
+#endif
+constexpr int kLdCpol = FLB_LD_CPOL;
+constexpr int kStCpol = FLB_ST_CPOL;
 constexpr unsigned long long kDrop = ~0ull;  // "discard" lane offset before lowering
 // s_waitcnt encoding (gfx9): vmcnt(0), expcnt and lgkmcnt left at their maxima
 constexpr int kWaitVmcnt0 = 0x0F70;
@@ -218,17 +230,17 @@ struct PopIO {
     if constexpr (sizeof(T) == 8) {
       if (BUF) {
         typedef unsigned u2 __attribute__((ext_vector_type(2)));
-        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, vo, po, 0);
+        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, vo, po, kLdCpol);
         return __builtin_bit_cast(double, v);
       }
       return *(const double*)(gs + off + po);
     } else if (S::HALF && i > 0) {
       _Float16 h;
-      if (BUF) h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, vo, po, 0));
+      if (BUF) h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, vo, po, kLdCpol));
       else h = *(const _Float16*)(gs + off + po);
       return (float)h + (float)L::w[i];
     } else {
-      if (BUF) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, po, 0));
+      if (BUF) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, po, kLdCpol));
       return *(const float*)(gs + off + po);
     }
   }
@@ -240,16 +252,16 @@ struct PopIO {
     if constexpr (sizeof(T) == 8) {
       if (BUF) {
         typedef unsigned u2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rd, vo, po, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rd, vo, po, kStCpol);
       } else {
         *(double*)(gd + off + po) = v;
       }
     } else if (S::HALF && i > 0) {
       const _Float16 h = (_Float16)(v - (float)L::w[i]);
-      if (BUF) __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), rd, vo, po, 0);
+      if (BUF) __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), rd, vo, po, kStCpol);
       else *(_Float16*)(gd + off + po) = h;
     } else {
-      if (BUF) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rd, vo, po, 0);
+      if (BUF) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rd, vo, po, kStCpol);
       else *(float*)(gd + off + po) = v;
     }
   }

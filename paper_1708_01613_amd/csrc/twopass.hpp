@@ -170,13 +170,4 @@ __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
                        keep * (double)(L::HAS_M ? jz : T(0)));
 }
 
-// gas flags of the film-map refresh from the rho array of k_psi
-template <class T>
-__global__ void k_gas_from_rho(const Ctl* ctl, const T* rho, MapDims d, double rho_th, int* par) {
-  if (ctl->stopped) return;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < d.N;
-       c += (long long)gridDim.x * blockDim.x)
-    par[c] = (double)rho[c] < rho_th ? (int)c : -1;
-}
-
 }  // namespace flb

@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(_HERE, "libfoamlbm.so")
+# FOAMLBM_LIB selects another build of the library (e.g. built with other
+# compile-time options); the default is the in-tree build
+LIBPATH = os.environ.get("FOAMLBM_LIB") or os.path.join(_HERE, "libfoamlbm.so")
 
 FLB_OK, FLB_EINVAL, FLB_ENOMEM, FLB_ENUMERIC, FLB_EBUSY, FLB_EHIP, FLB_STOPPED = 0, -1, -2, -3, -4, -5, 1
 FLB_D2Q9, FLB_D3Q19 = 0, 1
@@ -55,7 +57,7 @@ class flb_stats(C.Structure):
 
 class flb_server_config(C.Structure):
     _fields_ = [("pool_bytes", C.c_int64), ("max_jobs", C.c_int32), ("chunk_steps", C.c_int32),
-                ("graph_steps", C.c_int32)]
+                ("graph_steps", C.c_int32), ("max_cells", C.c_int64)]
 
 
 FLB_JOB_QUEUED, FLB_JOB_RUNNING, FLB_JOB_DONE, FLB_JOB_FAILED = 0, 1, 2, 3
@@ -96,6 +98,7 @@ _SIGS = {
     "flb_get_rupture_events": (C.c_int, [_CTX, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
     "flb_set_tuning": (C.c_int, [_CTX, C.c_int32, C.c_int32, C.c_int32]),
     "flb_get_tuning": (C.c_int, [_CTX] + [C.POINTER(C.c_int32)] * 6),
+    "flb_autotune": (C.c_int, [_CTX, C.c_int32, C.POINTER(C.c_double)]),
     "flb_time_steps": (C.c_int, [_CTX, C.c_int64, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "flb_destroy": (None, [_CTX]),
     "flb_last_error": (C.c_char_p, []),
@@ -304,6 +307,12 @@ class Sim:
         check(flb_get_tuning(self.h, *[C.byref(x) for x in v]), "flb_get_tuning")
         return dict(zip(("tile", "lz", "xcd", "n_tiles", "tile_x", "tile_m"), (x.value for x in v)))
 
+    def autotune(self, reps=5):
+        """Pick the fastest step-kernel variant for this lattice (state unchanged)."""
+        ms = C.c_double(0.0)
+        check(flb_autotune(self.h, int(reps), C.byref(ms)), "flb_autotune")
+        return ms.value
+
     def time_steps(self, n, refresh=True, kernel=False):
         """Milliseconds for n steps; with kernel=True, (total, step-kernel sum)."""
         ms = C.c_double(0.0)
@@ -409,14 +418,14 @@ class Server:
     queues a job, pump() runs one scheduling round, result() returns the final
     density and statistics of a finished job."""
 
-    def __init__(self, pool_bytes=None, max_jobs=None, chunk_steps=None, graph_steps=None, stream=None,
-                 use_torch_memory=True):
+    def __init__(self, pool_bytes=None, max_jobs=None, chunk_steps=None, graph_steps=None, max_cells=None,
+                 stream=None, use_torch_memory=True):
         import torch
 
         cfg = flb_server_config()
         flb_server_default_config(C.byref(cfg))
         for k, v in (("pool_bytes", pool_bytes), ("max_jobs", max_jobs), ("chunk_steps", chunk_steps),
-                     ("graph_steps", graph_steps)):
+                     ("graph_steps", graph_steps), ("max_cells", max_cells)):
             if v is not None:
                 setattr(cfg, k, int(v))
         self.cfg = cfg

@@ -313,3 +313,41 @@ def test_film_maps_bit_exact_ragged_many_bubbles(flb, kind, dims):
     gm = _compare_maps(flb, kind, g, o)
     assert g.stats()["n_bubbles"] > 1 and np.count_nonzero(gm["mask"]) > 0
     assert max_rel(g.density(), o.density()) <= 1e-12
+
+
+def test_labels_follow_the_current_buffer(flb):
+    # after an odd number of steps the current state sits in the second
+    # population buffer; labels of the state equal labels of its density
+    p = _case(flb, lattice=0, storage="f32", nx=90, ny=70, G=-5.5, rho_liquid=2.3, rho_gas=0.11, seed=8)
+    nuc = [[20.0, 20.0, 0, 8.0], [60.0, 45.0, 0, 10.0], [85.0, 10.0, 0, 6.0]]
+    g = flb.Sim(**p)
+    g.set_nuclei(nuc)
+    for steps in (7, 1):
+        g.step(steps)
+        lab, nb = g.labels()
+        lab2, nb2 = g.label_field(g.density())
+        assert nb == nb2 and nb >= 3 and np.array_equal(lab, lab2)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_autotune_keeps_state_and_results(flb, kind):
+    if kind == 0:
+        p = _case(flb, lattice=0, storage="f32", nx=150, ny=90, G=-5.5, rho_liquid=2.3, rho_gas=0.11, film_on=1,
+                  k_own=4, rupture_warmup=10, seed=12)
+        nuc = [[40.0, 45.0, 0, 14.0], [72.0, 45.0, 0, 14.0], [120.0, 20.0, 0, 9.0]]
+    else:
+        p = _case(flb, lattice=1, storage="f32", nx=70, ny=40, nz=36, G=-5.5, rho_liquid=2.3, rho_gas=0.11,
+                  film_on=1, k_own=4, rupture_warmup=10, seed=12)
+        nuc = [[20.0, 20.0, 18.0, 9.0], [40.0, 20.0, 18.0, 9.0]]
+    g = flb.Sim(**p)
+    g.set_nuclei(nuc)
+    g.step(11)
+    f = g.populations()
+    ms = g.autotune(reps=2)
+    assert ms > 0 and np.array_equal(g.populations(), f) and g.stats()["step"] == 11
+    g.step(30)
+    r = flb.Sim(**p)
+    r.set_nuclei(nuc)
+    r.step(41)
+    assert np.array_equal(g.populations(), r.populations())
+    assert g.stats()["n_ruptures"] == r.stats()["n_ruptures"]
