@@ -254,23 +254,51 @@ void or_lattice(int lattice, int32_t* e_out, double* w_out) {
 /* ------------------------------------------------------------------ */
 static double min_image(double d, long n) { return d - (double)n * floor(d / (double)n + 0.5); }
 
+static int in_nucleus(const or_params* p, long x, long y, long z, const double* nk) {
+  double dx = min_image((double)x - nk[0], p->nx);
+  double dy = min_image((double)y - nk[1], p->ny);
+  double dz = min_image((double)z - nk[2], p->nz);
+  return dx * dx + dy * dy + dz * dz <= nk[3] * nk[3];
+}
+
+/* integer coordinates k with |k - c| <= r, as a range [*k0, *k1] of at most n */
+static void box_range(double c, double r, long n, long* k0, long* k1) {
+  *k0 = (long)ceil(c - r);
+  *k1 = (long)floor(c + r);
+  if (*k1 - *k0 + 1 > n) {
+    *k0 = 0;
+    *k1 = n - 1;
+  }
+}
+
 int or_set_nuclei(or_sim* s, const double* nuc, int32_t n) {
   const or_params* p = &s->p;
   long N = s->N;
+  /* a cell inside a nucleus has minimum-image offsets of at most r on every
+     axis, so it lies in the nucleus' bounding box taken modulo the lattice:
+     testing the cells of each box finds every inside cell */
+  unsigned char* inside = (unsigned char*)calloc((size_t)N, 1);
+  if (!inside) return -1;
+  for (int k = 0; k < n; k++) {
+    const double* nk = nuc + 4 * k;
+    long x0, x1, y0, y1, z0, z1;
+    box_range(nk[0], nk[3], p->nx, &x0, &x1);
+    box_range(nk[1], nk[3], p->ny, &y0, &y1);
+    box_range(nk[2], nk[3], p->nz, &z0, &z1);
+    for (long zz = z0; zz <= z1; zz++)
+      for (long yy = y0; yy <= y1; yy++)
+        for (long xx = x0; xx <= x1; xx++) {
+          long x = wrap(xx, p->nx), y = wrap(yy, p->ny), z = wrap(zz, p->nz);
+          if (in_nucleus(p, x, y, z, nk)) inside[(z * p->ny + y) * p->nx + x] = 1;
+        }
+  }
+#pragma omp parallel for schedule(static)
   for (long c = 0; c < N; c++) {
-    long x = c % p->nx, y = (c / p->nx) % p->ny, z = c / ((long)p->nx * p->ny);
-    int inside = 0;
-    for (int k = 0; k < n && !inside; k++) {
-      double dx = min_image((double)x - nuc[4 * k + 0], p->nx);
-      double dy = min_image((double)y - nuc[4 * k + 1], p->ny);
-      double dz = min_image((double)z - nuc[4 * k + 2], p->nz);
-      double r = nuc[4 * k + 3];
-      if (dx * dx + dy * dy + dz * dz <= r * r) inside = 1;
-    }
-    double rho = inside ? p->rho_gas : p->rho_liquid;
+    double rho = inside[c] ? p->rho_gas : p->rho_liquid;
     rho += p->noise_amp * (2.0 * or_uniform(p->seed, (uint64_t)c) - 1.0);
     for (int i = 0; i < s->Q; i++) s->f[(long)i * N + c] = s->w[i] * rho;
   }
+  free(inside);
   s->step = 0;
   s->stopped = 0;
   s->nev = 0;

@@ -140,7 +140,8 @@ class OracleSim:
             n = 0
         else:
             n = arr.shape[0]
-        self._lib.or_set_nuclei(self._h, arr.reshape(-1), n)
+        if self._lib.or_set_nuclei(self._h, arr.reshape(-1), n) != 0:
+            raise MemoryError("oracle: out of host memory")
         return self
 
     def set_populations(self, f):

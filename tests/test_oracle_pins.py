@@ -367,6 +367,29 @@ def test_nuclei_minimum_image_gauss_counts():
     assert int(np.sum(s3.density() < 1.0)) == 33
 
 
+@pytest.mark.parametrize("kind,dims", [(0, (23, 17, 1)), (1, (11, 13, 9))])
+def test_nuclei_gas_cells_vs_exhaustive_search(kind, dims):
+    # every cell against every nucleus with the periodic minimum image, on
+    # nuclei at fractional centres, across the wrap, and wider than the lattice
+    nx, ny, nz = dims
+    rng = np.random.default_rng(5 + kind)
+    nuc = [[rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz) if kind else 0.0, rng.uniform(0.5, 4.5)]
+           for _ in range(6)]
+    nuc += [[0.3, ny - 0.2, 0.0, 2.7], [nx / 2, ny / 2, nz / 2 if kind else 0.0, 0.45 * max(dims)]]
+    s = OracleSim(lattice=kind, nx=nx, ny=ny, nz=nz, noise_amp=0.0, rho_liquid=2.0, rho_gas=0.1)
+    s.set_nuclei(nuc)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    gas = np.zeros((nz, ny, nx), bool)
+    for cx, cy, cz, r in nuc:
+        d2 = 0.0
+        for coord, c, n in ((x, cx, nx), (y, cy, ny), (z, cz, nz)):
+            d = np.abs(coord - c) % n
+            d2 = d2 + np.minimum(d, n - d) ** 2
+        gas |= d2 <= r * r
+    assert 0 < gas.sum() < gas.size
+    assert np.array_equal(s.density().reshape(nz, ny, nx) < 1.0, gas)
+
+
 def test_initial_noise_uses_counter_generator():
     s = OracleSim(lattice=0, nx=9, ny=5, noise_amp=0.01, rho_liquid=2.0, seed=123)
     s.set_nuclei([])
