@@ -215,6 +215,24 @@ int flb_autotune(flb_ctx* ctx, int32_t reps, double* best_ms);
  * those durations, i.e. the time of the step kernel alone. */
 int flb_time_steps(flb_ctx* ctx, int64_t nsteps, int32_t refresh, double* ms, double* kernel_ms);
 
+/* Checkpoint and resume: flb_save writes the current state (populations,
+ * run control, film maps, aliases, rupture log) to a file; flb_load restores
+ * it into a context created with identical parameters, after which stepping
+ * continues exactly as it would have from the saved point. */
+int flb_save(flb_ctx* ctx, const char* path);
+int flb_load(flb_ctx* ctx, const char* path);
+
+/* Replaces the film maps in force (film_on only) by given ones, as if a
+ * refresh had built them: labels, owner / owner2 (0 = none), dist (-1 =
+ * beyond zone_width - 1), each of n == nx*ny*nz cells, the alias root of
+ * every label 0..n_bubbles (NULL: every label its own root), and n_bubbles;
+ * masks and the flagged-cell list are rebuilt from them.  The next regular
+ * refresh replaces them again.  Lets two implementations run step-locked on
+ * identical maps (parity tests beyond the horizon where independently
+ * computed maps may differ).  FLB_EINVAL on inconsistent maps. */
+int flb_import_maps(flb_ctx* ctx, const int32_t* label, const int32_t* owner, const int32_t* owner2,
+                    const int32_t* dist, size_t n, const int32_t* alias_root, int32_t n_bubbles);
+
 /* Destroys the context and frees its device state.  NULL, and a context
  * owned by a batch (see flb_batch_member), are ignored. */
 void flb_destroy(flb_ctx* ctx);

@@ -99,6 +99,7 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     ok = ok && (c->dist = (uint8_t*)c->dalloc((size_t)c->N));
     ok = ok && (c->mask = (uint32_t*)c->dalloc(sizeof(uint32_t) * (size_t)c->N));
     ok = ok && (c->flist = (int*)c->dalloc(sizeof(int) * (size_t)c->N));
+    ok = ok && (c->rpair = (int2*)c->dalloc(sizeof(int2) * (size_t)c->N));
     ok = ok && (c->own = (int2*)c->dalloc(sizeof(int2) * (size_t)c->N));
     ok = ok && (c->label = (int*)c->dalloc(sizeof(int) * (size_t)c->N));
     ok = ok && (c->label_old = (int*)c->dalloc(sizeof(int) * (size_t)c->N));
@@ -107,7 +108,7 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     ok = ok && (c->rep = (int*)c->dalloc(sizeof(int) * (size_t)(c->N + 1)));
     ok = ok && (c->events = (long long*)c->dalloc(sizeof(long long) * 4 * (size_t)c->ev_cap));
     c->nwords = (long long)((c->md.nx + 63) / 64) * c->md.nm * c->md.nz;
-    ok = ok && (c->bits = (unsigned long long*)c->dalloc(sizeof(unsigned long long) * 3 * (size_t)c->nwords));
+    ok = ok && (c->bits = (unsigned long long*)c->dalloc(sizeof(unsigned long long) * 4 * (size_t)c->nwords));
   }
   if (!ok) {
     c->dfree_all();
@@ -505,3 +506,141 @@ int flb_get_stats(flb_ctx* c, flb_stats* out) {
 
 }  // extern "C"
 
+// ---- checkpoints ----
+namespace {
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t version, params_size;
+  flb_params p;
+  Ctl ctl;
+  uint64_t fbytes, N, n_events, n_flagged;
+};
+constexpr char kCkptMagic[8] = {'F', 'L', 'B', 'C', 'K', 'P', 'T', '1'};
+
+int dev_to_file(FILE* fp, const void* dev, size_t bytes, hipStream_t st) {
+  std::vector<char> h(bytes);
+  if (bytes) {
+    HIPCHK(hipMemcpyAsync(h.data(), dev, bytes, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  if (bytes && fwrite(h.data(), 1, bytes, fp) != bytes) return fail(FLB_EINVAL, "checkpoint write failed");
+  return FLB_OK;
+}
+
+int file_to_dev(FILE* fp, void* dev, size_t bytes, hipStream_t st) {
+  std::vector<char> h(bytes);
+  if (bytes && fread(h.data(), 1, bytes, fp) != bytes) return fail(FLB_EINVAL, "checkpoint truncated");
+  if (bytes) {
+    HIPCHK(hipMemcpyAsync(dev, h.data(), bytes, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return FLB_OK;
+}
+
+// the device arrays a checkpoint carries besides the populations
+struct CkptArrays {
+  std::vector<std::pair<void*, size_t>> v;
+  CkptArrays(flb_ctx* c, size_t n_events, size_t n_flagged) {
+    if (!c->p.film_on) return;
+    const size_t N = (size_t)c->N;
+    v = {{c->label, 4 * N},       {c->alias, 4 * (N + 1)}, {c->own, 8 * N},
+         {c->dist, N},            {c->flag, N},            {c->mask, 4 * N},
+         {c->flist, 4 * n_flagged}, {c->events, 32 * n_events}};
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int flb_save(flb_ctx* c, const char* path) {
+  if (!c || !path) return fail(FLB_EINVAL, "NULL argument");
+  Ctl h;
+  int rc = read_ctl(c, &h);
+  if (rc) return rc;
+  CkptHeader hd;
+  memset(&hd, 0, sizeof hd);
+  memcpy(hd.magic, kCkptMagic, 8);
+  hd.version = 1;
+  hd.params_size = sizeof(flb_params);
+  hd.p = c->p;
+  hd.ctl = h;
+  hd.fbytes = c->fbytes;
+  hd.N = (uint64_t)c->N;
+  hd.n_events = c->p.film_on ? std::min<unsigned>(h.ev_count, c->ev_cap) : 0;
+  hd.n_flagged = c->p.film_on ? h.n_flagged : 0;
+  FILE* fp = fopen(path, "wb");
+  if (!fp) return fail(FLB_EINVAL, "cannot open %s for writing", path);
+  rc = fwrite(&hd, sizeof hd, 1, fp) == 1 ? FLB_OK : fail(FLB_EINVAL, "checkpoint write failed");
+  if (!rc) rc = dev_to_file(fp, c->f[h.steps & 1], c->fbytes, c->st);
+  CkptArrays arr(c, hd.n_events, hd.n_flagged);
+  for (auto& a : arr.v)
+    if (!rc) rc = dev_to_file(fp, a.first, a.second, c->st);
+  if (fclose(fp) != 0 && !rc) rc = fail(FLB_EINVAL, "checkpoint close failed");
+  return rc;
+}
+
+int flb_load(flb_ctx* c, const char* path) {
+  if (!c || !path) return fail(FLB_EINVAL, "NULL argument");
+  FILE* fp = fopen(path, "rb");
+  if (!fp) return fail(FLB_EINVAL, "cannot open %s", path);
+  CkptHeader hd;
+  int rc = fread(&hd, sizeof hd, 1, fp) == 1 ? FLB_OK : fail(FLB_EINVAL, "not a checkpoint");
+  if (!rc && (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1 || hd.params_size != sizeof(flb_params)))
+    rc = fail(FLB_EINVAL, "not a checkpoint of this library version");
+  if (!rc && (memcmp(&hd.p, &c->p, sizeof(flb_params)) != 0 || hd.fbytes != c->fbytes || hd.N != (uint64_t)c->N))
+    rc = fail(FLB_EINVAL, "checkpoint parameters differ from the context's");
+  if (!rc && (hd.n_events > c->ev_cap || hd.n_flagged > (uint64_t)c->N))
+    rc = fail(FLB_EINVAL, "corrupt checkpoint");
+  if (!rc) rc = file_to_dev(fp, c->f[hd.ctl.steps & 1], c->fbytes, c->st);
+  CkptArrays arr(c, hd.n_events, hd.n_flagged);
+  for (auto& a : arr.v)
+    if (!rc) rc = file_to_dev(fp, a.first, a.second, c->st);
+  fclose(fp);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(c->ctl, &hd.ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  c->launched = hd.ctl.steps;
+  return FLB_OK;
+}
+
+int flb_import_maps(flb_ctx* c, const int32_t* label, const int32_t* owner, const int32_t* owner2,
+                    const int32_t* dist, size_t n, const int32_t* alias_root, int32_t n_bubbles) {
+  if (!c || !label || !owner || !owner2 || !dist) return fail(FLB_EINVAL, "NULL argument");
+  if (!c->p.film_on) return fail(FLB_EINVAL, "film maps exist only with film_on");
+  if (n != (size_t)c->N) return fail(FLB_EINVAL, "n must be nx*ny*nz = %lld", c->N);
+  if (n_bubbles < 0 || (long long)n_bubbles > c->N) return fail(FLB_EINVAL, "bad n_bubbles");
+  std::vector<int2> own(n);
+  std::vector<uint8_t> d8(n);
+  for (size_t k = 0; k < n; k++) {
+    if (label[k] < 0 || label[k] > n_bubbles || owner[k] < 0 || owner[k] > n_bubbles || owner2[k] < 0 ||
+        owner2[k] > n_bubbles || dist[k] < -1 || dist[k] >= c->p.zone_width || (dist[k] < 0) != (owner[k] == 0))
+      return fail(FLB_EINVAL, "inconsistent maps at cell %zu", k);
+    own[k] = make_int2(owner[k], owner2[k]);
+    d8[k] = dist[k] < 0 ? 255 : (uint8_t)dist[k];
+  }
+  std::vector<int> alias(n_bubbles + 1);
+  for (int b = 0; b <= n_bubbles; b++) {
+    alias[b] = alias_root ? alias_root[b] : b;
+    if (alias[b] < 0 || alias[b] > n_bubbles || (alias_root && alias_root[alias[b]] != alias[b]))
+      return fail(FLB_EINVAL, "alias_root[%d] is not a root label", b);
+  }
+  Ctl h;
+  int rc = read_ctl(c, &h);
+  if (rc) return rc;
+  if (h.stopped) return fail(FLB_EINVAL, "context is stopped");
+  rc = ctx_mapsets(c);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(c->label, label, 4 * n, hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(c->own, own.data(), 8 * n, hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(c->dist, d8.data(), n, hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(c->alias, alias.data(), 4 * alias.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(&c->ctl->n_bubbles, &n_bubbles, sizeof(int), hipMemcpyHostToDevice, c->st));
+  rc = c->D == 2 ? map_masks<D2Q9K>(c->ms_import, c->st) : map_masks<D3Q19K>(c->ms_import, c->st);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->st));
+  return FLB_OK;
+}
+
+}  // extern "C"

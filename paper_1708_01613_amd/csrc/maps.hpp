@@ -140,6 +140,8 @@ struct MapArgs {
   uint8_t* flag;
   uint32_t* mask;
   int* flist;
+  int2* rpair;            // alias-root pairs of the owners (mask construction)
+  unsigned long long* fwords;  // flag words: bit l of word s = cell 64 xs + l of its row has links
   unsigned long long* fr0;  // BFS frontier bitsets (ping-pong) and visited set
   unsigned long long* fr1;
   unsigned long long* vis;
@@ -151,7 +153,7 @@ __device__ __forceinline__ bool map_due(const MapArgs& m) {
 }
 
 // decompositions of a map launch (workgroups per lattice)
-enum MapShape { SH_CELLS = 0, SH_SEG, SH_WORDS, SH_CCT, SH_MT, SH_RANK, SH_ONE, SH_LIST, SH_COUNT };
+enum MapShape { SH_CELLS = 0, SH_SEG, SH_WORDS, SH_CCT, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_COUNT };
 
 #define MAP_KERNEL_PARAMS const MapArgs *__restrict__ tab, const int *__restrict__ first, int nmem
 #define MAP_MEMBER                                                           \
@@ -356,6 +358,7 @@ static __global__ __launch_bounds__(MAP_NT) void k_cc_compress(MAP_KERNEL_PARAMS
 
 // ---- canonical ranks: count roots per block, scan, write labels ----
 constexpr int RANK_BLOCK = 1024;
+constexpr int FW_BLOCK = 1024;  // flag words per workgroup (flagged-list build)
 
 static __global__ __launch_bounds__(RANK_BLOCK) void k_count_roots(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
@@ -373,16 +376,18 @@ static __global__ __launch_bounds__(RANK_BLOCK) void k_count_roots(MAP_KERNEL_PA
   }
 }
 
-// one workgroup per lattice: exclusive scan of the per-block counts, total
-// to *n_out
-static __global__ __launch_bounds__(1024) void k_scan_counts(MAP_KERNEL_PARAMS) {
+// one workgroup per lattice: exclusive scan of the per-block counts; the
+// total goes to *n_out (which 0: roots per rank block, the label count) or
+// to ctl->n_flagged (which 1: flagged cells per flag-word block)
+static __global__ __launch_bounds__(1024) void k_scan_counts(MAP_KERNEL_PARAMS, int which) {
   MAP_MEMBER
   if (!map_due(m)) return;
   __shared__ int s_carry;
   __shared__ int s_w[16];
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
-  const int nblocks = m.nrb;
+  const long long nwords = (long long)((m.d.nx + 63) >> 6) * m.d.nm * m.d.nz;
+  const int nblocks = which == 0 ? m.nrb : (int)((nwords + FW_BLOCK - 1) / FW_BLOCK);
   for (int base = 0; base < nblocks; base += 1024) {
     const int i = base + threadIdx.x;
     const int v = i < nblocks ? m.counts[i] : 0;
@@ -403,7 +408,10 @@ static __global__ __launch_bounds__(1024) void k_scan_counts(MAP_KERNEL_PARAMS) 
     if (threadIdx.x == 1023) s_carry = carry + wbase + incl;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *m.n_out = s_carry;
+  if (threadIdx.x == 0) {
+    if (which == 0) *m.n_out = s_carry;
+    else m.ctl->n_flagged = (unsigned)s_carry;
+  }
 }
 
 // rank[root] = 1-based label of the component rooted there
@@ -477,13 +485,11 @@ static __global__ __launch_bounds__(MAP_NT) void k_owner_init(MAP_KERNEL_PARAMS)
   }
 }
 
-// One BFS layer in two passes.  The reach pass works on one 64-bit word (64
-// x-cells of a row) per lane: the cells reached this layer are the unvisited
+// Bitset words of a row: the cells reached by a BFS layer are the unvisited
 // bits of the frontier dilated by the lattice links, formed with whole-word
 // shifts of the neighbour rows' words (x - 1 and x + 1 bring in one bit from
-// the adjacent word, periodic across the row end).  The owner pass then lets
-// only the newly reached cells read the owners of their neighbours of the
-// previous layer.  Word bits past the end of a row are always zero.
+// the adjacent word, periodic across the row end).  Word bits past the end of
+// a row are always zero.
 struct WordRow {
   const unsigned long long* __restrict__ b;
   int nxs, last_valid;  // words per row; valid bits of a row's last word
@@ -502,87 +508,91 @@ struct WordRow {
   }
 };
 
-// Reach pass of BFS layer `layer`, one word per lane (no per-cell work).
+// One BFS layer.  A wavefront takes BFS_WPW words: lane k < BFS_WPW forms
+// the frontier words of its word's 18 neighbourhoods (whole-word shifts) and
+// the word of cells this layer reaches; then the wavefront takes the words
+// with new cells one at a time, its 64 lanes standing for the 64 cells of the
+// word, and every new cell reads only the owners of its frontier neighbours
+// (the smallest owner and the largest owner2 win).  Few words per wavefront
+// keep that serial part short and give many wavefronts to hide latency.
+constexpr int BFS_WPW = 16;
 template <class L>
-__global__ __launch_bounds__(MAP_NT) void k_bfs_reach(MAP_KERNEL_PARAMS, int layer) {
+__global__ __launch_bounds__(MAP_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int layer) {
   MAP_MEMBER
   if (!map_due(m) || layer > m.zone_width - 1) return;
   const MapDims d = m.d;
   const unsigned long long* fin = (layer & 1) ? m.fr0 : m.fr1;
   unsigned long long* fout = (layer & 1) ? m.fr1 : m.fr0;
   unsigned long long* vis = m.vis;
+  const int lane = threadIdx.x & 63;
   const int nxs = (d.nx + 63) >> 6;
   const unsigned nw = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
   const int last_valid = d.nx - 64 * (nxs - 1);
   const WordRow fr{fin, nxs, last_valid};
-  for (unsigned s = bid * MAP_NT + threadIdx.x; s < nw; s += nbk * MAP_NT) {
-    const unsigned row = s / (unsigned)nxs;
-    const int xs = (int)(s - row * (unsigned)nxs);
-    const unsigned long long valid = (xs == nxs - 1 && last_valid < 64) ? (1ull << last_valid) - 1ull : ~0ull;
-    const unsigned long long v = vis[s];
-    if ((v & valid) == valid) {
-      fout[s] = 0ull;
-      continue;
-    }
-    const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
-    const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
-    const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
-    unsigned long long reach = 0ull;
+  // wave-uniform loop: every lane takes part in the expansion below
+  const unsigned wave = bid * MAP_WAVES + (threadIdx.x >> 6), nwaves = nbk * MAP_WAVES;
+  for (unsigned base = wave * BFS_WPW; base < nw; base += nwaves * BFS_WPW) {
+    const unsigned s = base + lane;
+    const bool in = lane < BFS_WPW && s < nw;
+    unsigned long long sh[L::Q];
 #pragma unroll
-    for (int i = 1; i < L::Q; i++) {
-      const unsigned rb = (unsigned)nxs * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
-      reach |= fr.shifted(rb, xs, L::ex[i]);
-    }
-    const unsigned long long nwb = reach & ~v & valid;
-    fout[s] = nwb;
-    vis[s] = v | nwb;
-  }
-}
-
-// Owner pass of BFS layer `layer`: a wavefront per row segment; segments
-// that reached nothing return after one word load; a newly reached cell takes
-// the smallest owner and the largest owner2 of its neighbours of the
-// previous layer.
-template <class L>
-__global__ __launch_bounds__(MAP_NT) void k_bfs_owner(MAP_KERNEL_PARAMS, int layer) {
-  MAP_MEMBER
-  if (!map_due(m) || layer > m.zone_width - 1) return;
-  const MapDims d = m.d;
-  const unsigned long long* fnew = (layer & 1) ? m.fr1 : m.fr0;
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nxs = (d.nx + 63) >> 6;
-  const unsigned nseg = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
-  for (unsigned s = bid * MAP_WAVES + wv; s < nseg; s += nbk * MAP_WAVES) {
-    const unsigned long long w = fnew[s];
-    if (!((w >> lane) & 1ull)) continue;
-    const unsigned row = s / (unsigned)nxs;
-    const int x = (int)(s - row * (unsigned)nxs) * 64 + lane;
-    const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
-    const int xw[3] = {x == 0 ? d.nx - 1 : x - 1, x, x == d.nx - 1 ? 0 : x + 1};
-    const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
-    const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
-    // every neighbour's distance and owners are loaded before any is used,
-    // so the loads of a lane overlap instead of waiting one after another
-    uint8_t dn[L::Q];
-    int2 on[L::Q];
+    for (int i = 0; i < L::Q; i++) sh[i] = 0ull;
+    unsigned long long nwb = 0ull;
+    unsigned row = 0;
+    int xs = 0;
+    if (in) {
+      row = s / (unsigned)nxs;
+      xs = (int)(s - row * (unsigned)nxs);
+      const unsigned long long valid = (xs == nxs - 1 && last_valid < 64) ? (1ull << last_valid) - 1ull : ~0ull;
+      const unsigned long long v = vis[s];
+      if ((v & valid) != valid) {
+        const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
+        const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
+        const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
+        unsigned long long reach = 0ull;
 #pragma unroll
-    for (int i = 1; i < L::Q; i++) {
-      const unsigned y = (unsigned)xw[1 + L::ex[i]] +
-                         (unsigned)d.nx * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
-      dn[i] = m.dist[y];
-      on[i] = m.own[y];
+        for (int i = 1; i < L::Q; i++) {
+          const unsigned rb =
+              (unsigned)nxs * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
+          sh[i] = fr.shifted(rb, xs, L::ex[i]);
+          reach |= sh[i];
+        }
+        nwb = reach & ~v & valid;
+        vis[s] = v | nwb;
+      }
+      fout[s] = nwb;
     }
-    int lo = 0x7fffffff, hi = 0;
+    unsigned long long todo = __ballot(nwb != 0ull);
+    while (todo) {
+      const int ld = first_lane(todo);
+      todo &= todo - 1ull;
+      const unsigned long long w = __shfl(nwb, ld, 64);
+      const unsigned wrow = __shfl(row, ld, 64);
+      const int wxs = __shfl(xs, ld, 64);
+      unsigned long long mine[L::Q];  // the leader's frontier words, on every lane
 #pragma unroll
-    for (int i = 1; i < L::Q; i++) {
-      const bool f = dn[i] == layer - 1;
-      lo = f ? min(lo, on[i].x) : lo;
-      hi = f ? max(hi, on[i].y) : hi;
+      for (int i = 1; i < L::Q; i++) mine[i] = __shfl(sh[i], ld, 64);
+      if ((w >> lane) & 1ull) {
+        const int x = wxs * 64 + lane;
+        const int mm_ = (int)(wrow % (unsigned)d.nm), z = (int)(wrow / (unsigned)d.nm);
+        const int xw[3] = {x == 0 ? d.nx - 1 : x - 1, x, x == d.nx - 1 ? 0 : x + 1};
+        const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
+        const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
+        int lo = 0x7fffffff, hi = 0;
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) {
+          if (!((mine[i] >> lane) & 1ull)) continue;
+          const unsigned y = (unsigned)xw[1 + L::ex[i]] +
+                             (unsigned)d.nx * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
+          const int2 o = m.own[y];
+          lo = min(lo, o.x);
+          hi = max(hi, o.y);
+        }
+        const unsigned c = (unsigned)x + (unsigned)d.nx * wrow;
+        m.own[c] = make_int2(lo, hi);
+        m.dist[c] = (uint8_t)layer;
+      }
     }
-    const unsigned c = (unsigned)x + (unsigned)d.nx * row;
-    m.own[c] = make_int2(lo, hi);
-    m.dist[c] = (uint8_t)layer;
   }
 }
 
@@ -659,107 +669,127 @@ static __global__ __launch_bounds__(MAP_NT) void k_alias_compress(MAP_KERNEL_PAR
   FOR_SHARE(b, (long long)nb + 1) m.alias[b] = uf_find_live(m.alias, (int)b);
 }
 
-// Barrier masks from the owner maps, and the list of cells that have barrier
-// links (appended a wavefront at a time; its order is irrelevant to the
-// results).  A workgroup stages the owners and distances of its tile and a
-// one-cell halo in LDS, so the 18 neighbour tests of a cell read LDS.
-// ctl->n_flagged must be zero before the launch.
-template <class L>
-struct MaskTile {
-  static constexpr int HM = L::HAS_M ? 1 : 0;
-  static constexpr int TM = L::HAS_M ? 4 : 1;
-  static constexpr int TZ = L::HAS_M ? 4 : 16;
-  static constexpr int LX = 66, LM = TM + 2 * HM, LZ = TZ + 2;
-  static constexpr int NL = LX * LM * LZ;
-  static constexpr int NC = 64 * TM * TZ;
-};
-
-template <class L>
-__host__ inline int mask_tiles(const MapDims& d) {
-  using MT = MaskTile<L>;
-  return ((d.nx + 63) / 64) * ((d.nm + MT::TM - 1) / MT::TM) * ((d.nz + MT::TZ - 1) / MT::TZ);
+// alias-root pair of every owned cell's owners, (0, 0) for unowned cells;
+// the aliases are compressed at every refresh, so one look-up gives a root
+static __global__ __launch_bounds__(MAP_NT) void k_root_pairs(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  FOR_SHARE(c, m.d.N) {
+    int2 r = make_int2(0, 0);
+    if (m.dist[c] != 255) {
+      const int2 o = m.own[c];
+      const int a = m.alias[o.x], b = m.alias[o.y];
+      r = make_int2(min(a, b), max(a, b));
+    }
+    m.rpair[c] = r;
+  }
 }
 
+// Barrier masks from the distances and root pairs, one wavefront per row
+// segment; a cell's 18 neighbours are loaded before any is tested.  The
+// segment's cells with links form one word of the flag bitset, from which
+// k_flag_count / k_scan_counts / k_flag_write build the flagged-cell list in
+// cell order (no atomics).
 template <class L>
 __global__ __launch_bounds__(MAP_NT) void k_masks(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m)) return;
-  using MT = MaskTile<L>;
-  __shared__ int2 s_rp[MT::NL];  // alias-root pair of the cell's owners
-  __shared__ uint8_t s_dist[MT::NL];
-  const MapDims d = m.d;
   const int zone_width = m.zone_width;
-  const int ntx = (d.nx + 63) / 64, ntm = (d.nm + MT::TM - 1) / MT::TM;
-  const int b = (int)bid;
-  const int x0 = (b % ntx) * 64, m0 = ((b / ntx) % ntm) * MT::TM, z0 = (b / (ntx * ntm)) * MT::TZ;
-  // staging: every load of a thread is issued before any is used
-  constexpr int SPT = (MT::NL + MAP_NT - 1) / MAP_NT;
-  uint8_t dd[SPT];
-  int2 oo[SPT];
-#pragma unroll
-  for (int j = 0; j < SPT; j++) {
-    const int idx = threadIdx.x + j * MAP_NT;
-    const int lx = idx % MT::LX, r = idx / MT::LX;
-    const int lm = r % MT::LM, lz = r / MT::LM;
-    const int gx = wrap_any(x0 - 1 + lx, d.nx);
-    const int gm = L::HAS_M ? wrap_any(m0 - 1 + lm, d.nm) : 0;
-    const int gz = wrap_any(z0 - 1 + min(lz, MT::LZ - 1), d.nz);
-    const unsigned g = (unsigned)gx + (unsigned)d.nx * ((unsigned)gm + (unsigned)d.nm * (unsigned)gz);
-    dd[j] = m.dist[g];
-    oo[j] = m.own[g];
-  }
-  int2 ra[SPT];
-#pragma unroll
-  for (int j = 0; j < SPT; j++) ra[j] = dd[j] != 255 ? make_int2(m.alias[oo[j].x], m.alias[oo[j].y]) : make_int2(0, 0);
-#pragma unroll
-  for (int j = 0; j < SPT; j++) {
-    const int idx = threadIdx.x + j * MAP_NT;
-    if (idx < MT::NL) {
-      s_dist[idx] = dd[j];
-      // the aliases are compressed at every refresh: one look-up gives the root
-      s_rp[idx] = dd[j] != 255 ? make_int2(min(ra[j].x, ra[j].y), max(ra[j].x, ra[j].y)) : make_int2(0, 0);
-    }
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63;
-  for (int k = threadIdx.x; k < MT::NC; k += MAP_NT) {  // uniform trip count
-    const int lx = k & 63, lm = (k >> 6) % MT::TM, lz = (k >> 6) / MT::TM;
-    const int x = x0 + lx, mm_ = m0 + lm, z = z0 + lz;
-    const bool valid = x < d.nx && mm_ < d.nm && z < d.nz;
-    const int li = (lx + 1) + MT::LX * ((lm + MT::HM) + MT::LM * (lz + 1));
+  const MapDims d = m.d;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nxs = (d.nx + 63) >> 6;
+  const unsigned nseg = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
+  for (unsigned s = bid * MAP_WAVES + wv; s < nseg; s += nbk * MAP_WAVES) {  // wave-uniform
+    const unsigned row = s / (unsigned)nxs;
+    const int x = (int)(s - row * (unsigned)nxs) * 64 + lane;
+    const bool in = x < d.nx;
+    const int xc = min(x, d.nx - 1);
+    const unsigned c = (unsigned)xc + (unsigned)d.nx * row;
+    const int dc = in ? m.dist[c] : 255;
     unsigned mk = 0;
-    const int dc = s_dist[li];
-    if (valid && dc != 255) {
-      const int2 rp = s_rp[li];
+    if (__ballot(dc != 255)) {  // any owned cell in the segment
+      const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
+      const int xw[3] = {xc == 0 ? d.nx - 1 : xc - 1, xc, xc == d.nx - 1 ? 0 : xc + 1};
+      const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
+      const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
+      const int2 rp = m.rpair[c];
+      uint8_t dn[L::Q];
+      int2 rn[L::Q];
 #pragma unroll
       for (int i = 1; i < L::Q; i++) {
-        const int ln = li + L::ex[i] + MT::LX * (L::em[i] + MT::LM * L::ez[i]);
-        const int2 rq = s_rp[ln];
-        // both ends owned (dist 255 fails the sum), thin enough, different pairs
-        if (dc + (int)s_dist[ln] + 1 <= zone_width && (rq.x != rp.x || rq.y != rp.y)) mk |= 1u << i;
+        const unsigned y = (unsigned)xw[1 + L::ex[i]] +
+                           (unsigned)d.nx * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
+        dn[i] = m.dist[y];
+        rn[i] = m.rpair[y];
+      }
+      if (dc != 255) {
+#pragma unroll
+        for (int i = 1; i < L::Q; i++)
+          // both ends owned (dist 255 fails the sum), thin enough, different pairs
+          if (dc + (int)dn[i] + 1 <= zone_width && (rn[i].x != rp.x || rn[i].y != rp.y)) mk |= 1u << i;
       }
     }
-    const unsigned c = (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z);
-    if (valid) {
+    if (in) {
       m.flag[c] = mk ? 1 : 0;
       m.mask[c] = mk;
     }
     const unsigned long long bal = __ballot(mk != 0);
-    if (bal) {
-      const int ld = first_lane(bal);
-      unsigned base = 0;
-      if (lane == ld) base = atomicAdd(&m.ctl->n_flagged, (unsigned)__popcll(bal));
-      base = __shfl(base, ld, 64);
-      if (mk) m.flist[base + (unsigned)__popcll(bal & ((1ull << lane) - 1ull))] = (int)c;
+    if (lane == 0) m.fwords[s] = bal;
+  }
+}
+
+// ---- the flagged-cell list from the flag words, in cell order ----
+static __global__ __launch_bounds__(FW_BLOCK) void k_flag_count(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  const long long nw = (long long)((m.d.nx + 63) >> 6) * m.d.nm * m.d.nz;
+  const long long w = bid * (long long)FW_BLOCK + threadIdx.x;
+  int v = w < nw ? __popcll(m.fwords[w]) : 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __shared__ int s[FW_BLOCK / 64];
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < FW_BLOCK / 64; k++) t += s[k];
+    m.counts[bid] = t;
+  }
+}
+
+static __global__ __launch_bounds__(FW_BLOCK) void k_flag_write(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  const int nxs = (m.d.nx + 63) >> 6;
+  const long long nw = (long long)nxs * m.d.nm * m.d.nz;
+  const long long w = bid * (long long)FW_BLOCK + threadIdx.x;
+  const unsigned long long word = w < nw ? m.fwords[w] : 0ull;
+  const int v = __popcll(word);
+  int incl = v;  // inclusive scan within the wave
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  __shared__ int s[FW_BLOCK / 64];
+  if (lane == 63) s[wv] = incl;
+  __syncthreads();
+  int base = m.counts[bid] + incl - v;
+  for (int k = 0; k < wv; k++) base += s[k];
+  if (word) {
+    const unsigned row = (unsigned)(w / nxs);
+    const unsigned c0 = (unsigned)(w - (long long)row * nxs) * 64u + (unsigned)m.d.nx * row;
+    unsigned long long b = word;
+    while (b) {
+      const int l = __builtin_ctzll(b);
+      b &= b - 1ull;
+      m.flist[base++] = (int)(c0 + (unsigned)l);
     }
   }
 }
 
-// an empty flagged-cell list before k_masks fills it
-static __global__ void k_flag_list_reset(MAP_KERNEL_PARAMS) {
-  MAP_MEMBER
-  if (map_due(m) && threadIdx.x == 0) m.ctl->n_flagged = 0;
-}
 
 // Lattice coordinates of listed cell c (a division per cell; lists are sparse).
 struct ListCell {
@@ -830,12 +860,12 @@ __host__ inline int map_share(int shape, const MapDims& d) {
   switch (shape) {
     case SH_CELLS: g = std::min<long long>((N + 1 + MAP_NT - 1) / MAP_NT, 16384); break;
     case SH_SEG: g = std::min<long long>((nseg + MAP_WAVES - 1) / MAP_WAVES, 65536); break;
-    case SH_WORDS: g = std::min<long long>((nseg + MAP_NT - 1) / MAP_NT, 65536); break;
+    case SH_WORDS: g = std::min<long long>((nseg + BFS_WPW * MAP_WAVES - 1) / (BFS_WPW * MAP_WAVES), 65536); break;
     case SH_CCT: g = cc_tiles(d, CCTile<L>::TM, CCTile<L>::TZ); break;
-    case SH_MT: g = mask_tiles<L>(d); break;
     case SH_RANK: g = (N + RANK_BLOCK - 1) / RANK_BLOCK; break;
     case SH_ONE: g = 1; break;
     case SH_LIST: g = list_grid(N); break;
+    case SH_FW: g = (nseg + FW_BLOCK - 1) / FW_BLOCK; break;
   }
   return (int)std::max<long long>(g, 1);
 }

@@ -121,7 +121,8 @@ inline size_t ctx_footprint(const flb_params* p) {
              2 * r(4 * N) + r(4 * (N / 1024 + 2)) + r(4 * N) + r(8 * (N + 1));
   if (p->film_on) {
     const size_t nwords = nxb * nm * nz;
-    t += 2 * r(N) + r(4 * N) + r(8 * N) + 2 * r(4 * N) + 3 * r(4 * (N + 1)) + r(32 * 65536) + r(24 * nwords);
+    t += 2 * r(N) + r(4 * N) + r(8 * N) + 2 * r(4 * N) + 3 * r(4 * (N + 1)) + r(32 * 65536) + r(24 * nwords) +
+         r(4 * N) + r(8 * N) + r(8 * nwords);
   }
   return t;
 }
@@ -164,6 +165,7 @@ struct flb_ctx {
   uint8_t* dist = nullptr;
   uint32_t* mask = nullptr;
   int* flist = nullptr;    // cells with barrier links at the last refresh
+  int2* rpair = nullptr;   // alias-root pairs of the owners, at refresh
   int2* own = nullptr;
   int* label = nullptr;
   int* label_old = nullptr;
@@ -173,13 +175,13 @@ struct flb_ctx {
   int* par = nullptr;
   int* rank = nullptr;
   int* counts = nullptr;
-  unsigned long long* bits = nullptr;  // BFS bitsets: 2 frontiers + visited
+  unsigned long long* bits = nullptr;  // bitsets: 2 BFS frontiers, visited, flag words
   long long nwords = 0;                // 64-bit words per bitset
   long long* events = nullptr;
   unsigned ev_cap = 1u << 16;
   // map-kernel tables: film refresh from the state or the rho array, label
   // queries from the state or a field
-  flb_rt::MapSet ms_pop, ms_rho, qs_pop, qs_field;
+  flb_rt::MapSet ms_pop, ms_rho, qs_pop, qs_field, ms_import;
   bool ms_ready = false;
   // query scratch
   double* qd = nullptr;    // (1 + 3) * N doubles
@@ -371,15 +373,32 @@ inline MapArgs map_args(flb_ctx* c, bool query, int src) {
     a.flag = c->flag;
     a.mask = c->mask;
     a.flist = c->flist;
+    a.rpair = c->rpair;
     a.fr0 = c->bits;
     a.fr1 = c->bits + c->nwords;
     a.vis = c->bits + 2 * c->nwords;
+    a.fwords = c->bits + 3 * c->nwords;
   }
   return a;
 }
 
 #define MAPL(K, SH, NT, ...) \
   hipLaunchKernelGGL(K, dim3(s.total[SH]), dim3(NT), 0, st, s.tab, s.first_of(SH), s.n, ##__VA_ARGS__)
+
+// Barrier masks, the flagged-cell list and its density marks from the
+// owners, distances and aliases in place.
+template <class L>
+int map_masks(const MapSet& s, hipStream_t st) {
+  MAPL(k_root_pairs, SH_CELLS, MAP_NT);
+  MAPL((k_masks<L>), SH_SEG, MAP_NT);
+  MAPL(k_flag_count, SH_FW, FW_BLOCK);
+  MAPL(k_scan_counts, SH_ONE, 1024, 1);
+  MAPL(k_flag_write, SH_FW, FW_BLOCK);
+  MAPL((k_rho_marks<L>), SH_LIST, MAP_NT);
+  MAPL(k_masks_done, SH_ONE, 64);
+  HIPCHK(hipGetLastError());
+  return FLB_OK;
+}
 
 // Labels (gas cells, connected components, canonical ranks), and for a film
 // refresh also owners and distances, alias carry, barrier masks, the list of
@@ -394,24 +413,18 @@ int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh) {
   MAPL((k_cc_cross<L>), SH_SEG, MAP_NT);
   MAPL(k_cc_compress, SH_CELLS, MAP_NT);
   MAPL(k_count_roots, SH_RANK, RANK_BLOCK);
-  MAPL(k_scan_counts, SH_ONE, 1024);
+  MAPL(k_scan_counts, SH_ONE, 1024, 0);
   MAPL(k_write_rank, SH_RANK, RANK_BLOCK);
   MAPL(k_write_labels, SH_CELLS, MAP_NT);
   if (refresh) {
     MAPL(k_owner_init, SH_SEG, MAP_NT);
-    for (int layer = 1; layer <= s.max_zone - 1; layer++) {
-      MAPL((k_bfs_reach<L>), SH_WORDS, MAP_NT, layer);
-      MAPL((k_bfs_owner<L>), SH_SEG, MAP_NT, layer);
-    }
+    for (int layer = 1; layer <= s.max_zone - 1; layer++) MAPL((k_bfs_layer<L>), SH_WORDS, MAP_NT, layer);
     MAPL(k_alias_reset, SH_CELLS, MAP_NT);
     MAPL(k_alias_carry1, SH_CELLS, MAP_NT);
     MAPL(k_alias_carry2, SH_CELLS, MAP_NT);
     MAPL(k_alias_compress, SH_CELLS, MAP_NT);
-    MAPL(k_flag_list_reset, SH_ONE, 64);
-    MAPL((k_masks<L>), SH_MT, MAP_NT);
-    MAPL((k_rho_marks<L>), SH_LIST, MAP_NT);
-    MAPL(k_masks_done, SH_ONE, 64);
   }
+  if (refresh) return map_masks<L>(s, st);
   HIPCHK(hipGetLastError());
   return FLB_OK;
 }
@@ -433,6 +446,11 @@ inline int ctx_mapsets(flb_ctx* c) {
     if (!rc) {
       r[0] = map_args(c, false, GAS_RHO);
       rc = mapset_build(c->ms_rho, r, c->D, al, c->st);
+    }
+    if (!rc) {  // imported maps: masks at any step
+      r[0] = map_args(c, false, GAS_POP);
+      r[0].k_own = 0;
+      rc = mapset_build(c->ms_import, r, c->D, al, c->st);
     }
   }
   if (!rc) c->ms_ready = true;

@@ -99,6 +99,9 @@ _SIGS = {
     "flb_set_tuning": (C.c_int, [_CTX, C.c_int32, C.c_int32, C.c_int32]),
     "flb_get_tuning": (C.c_int, [_CTX] + [C.POINTER(C.c_int32)] * 6),
     "flb_autotune": (C.c_int, [_CTX, C.c_int32, C.POINTER(C.c_double)]),
+    "flb_save": (C.c_int, [_CTX, C.c_char_p]),
+    "flb_load": (C.c_int, [_CTX, C.c_char_p]),
+    "flb_import_maps": (C.c_int, [_CTX, _I, _I, _I, _I, C.c_size_t, C.c_void_p, C.c_int32]),
     "flb_time_steps": (C.c_int, [_CTX, C.c_int64, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "flb_destroy": (None, [_CTX]),
     "flb_last_error": (C.c_char_p, []),
@@ -306,6 +309,18 @@ class Sim:
         v = [C.c_int32(0) for _ in range(6)]
         check(flb_get_tuning(self.h, *[C.byref(x) for x in v]), "flb_get_tuning")
         return dict(zip(("tile", "lz", "xcd", "n_tiles", "tile_x", "tile_m"), (x.value for x in v)))
+
+    def save(self, path):
+        check(flb_save(self.h, os.fsencode(path)), "flb_save")
+
+    def load(self, path):
+        check(flb_load(self.h, os.fsencode(path)), "flb_load")
+
+    def import_maps(self, label, owner, owner2, dist, n_bubbles, alias_root=None):
+        arrs = [np.ascontiguousarray(np.asarray(a, np.int32).reshape(-1)) for a in (label, owner, owner2, dist)]
+        ar = None if alias_root is None else np.ascontiguousarray(np.asarray(alias_root, np.int32).reshape(-1))
+        check(flb_import_maps(self.h, *arrs, arrs[0].size, None if ar is None else ar.ctypes.data_as(C.c_void_p),
+                              int(n_bubbles)), "flb_import_maps")
 
     def autotune(self, reps=5):
         """Pick the fastest step-kernel variant for this lattice (state unchanged)."""
