@@ -343,6 +343,10 @@ int flb_get_maps(flb_ctx* c, int32_t* label, int32_t* owner, int32_t* owner2, in
   if (!c) return fail(FLB_EINVAL, "ctx is NULL");
   if (!c->p.film_on) return fail(FLB_EINVAL, "film maps exist only with film_on");
   if (n != (size_t)c->N) return fail(FLB_EINVAL, "n must be nx*ny*nz = %lld", c->N);
+  if (owner || owner2 || dist) {
+    const int rc = c->D == 2 ? complete_maps<D2Q9K>(c) : complete_maps<D3Q19K>(c);
+    if (rc) return rc;
+  }
   if (label) HIPCHK(hipMemcpyAsync(label, c->label, sizeof(int) * n, hipMemcpyDeviceToHost, c->st));
   if (mask) HIPCHK(hipMemcpyAsync(mask, c->mask, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, c->st));
   std::vector<int2> own;
@@ -556,8 +560,11 @@ extern "C" {
 
 int flb_save(flb_ctx* c, const char* path) {
   if (!c || !path) return fail(FLB_EINVAL, "NULL argument");
+  int rc = FLB_OK;
+  if (c->p.film_on) rc = c->D == 2 ? complete_maps<D2Q9K>(c) : complete_maps<D3Q19K>(c);
+  if (rc) return rc;
   Ctl h;
-  int rc = read_ctl(c, &h);
+  rc = read_ctl(c, &h);
   if (rc) return rc;
   CkptHeader hd;
   memset(&hd, 0, sizeof hd);
@@ -638,6 +645,9 @@ int flb_import_maps(flb_ctx* c, const int32_t* label, const int32_t* owner, cons
   HIPCHK(hipMemcpyAsync(c->alias, alias.data(), 4 * alias.size(), hipMemcpyHostToDevice, c->st));
   HIPCHK(hipMemcpyAsync(&c->ctl->n_bubbles, &n_bubbles, sizeof(int), hipMemcpyHostToDevice, c->st));
   rc = c->D == 2 ? map_masks<D2Q9K>(c->ms_import, c->st) : map_masks<D3Q19K>(c->ms_import, c->st);
+  if (rc) return rc;
+  // the given maps are whole: no deferred layers to run
+  rc = c->D == 2 ? map_deferred<D2Q9K>(c->ms_import, c->st, false) : map_deferred<D3Q19K>(c->ms_import, c->st, false);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->st));
   return FLB_OK;

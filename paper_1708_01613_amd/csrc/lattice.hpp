@@ -132,6 +132,7 @@ struct Ctl {
   unsigned n_flagged;   // cells with barrier links at the last refresh (list length)
   int maps_seen;        // 1 once a refresh has built maps (the next one carries aliases)
   int nb_old;           // labels of the previous refresh, during a refresh
+  int maps_partial;     // 1 while owner/dist stop at the layers the masks need
   double mass, mom[3];  // FP64 totals of the state entering the last step
 };
 

@@ -508,6 +508,14 @@ struct WordRow {
   }
 };
 
+// Layers a barrier can depend on.  A barrier link joins two owned cells with
+// dist(x) + dist(y) + 1 <= zone_width, and BFS distances of neighbours differ
+// by at most one, so both ends lie within zone_width / 2 hops of a bubble.
+// A refresh runs only these layers; the deeper ones (up to zone_width - 1)
+// fill in the exported maps when they are read, from the frontier the
+// refresh left behind.
+__host__ __device__ constexpr int bfs_hot_layers(int zone_width) { return zone_width / 2; }
+
 // One BFS layer.  A wavefront takes BFS_WPW words: lane k < BFS_WPW forms
 // the frontier words of its word's 18 neighbourhoods (whole-word shifts) and
 // the word of cells this layer reaches; then the wavefront takes the words
@@ -517,9 +525,12 @@ struct WordRow {
 // keep that serial part short and give many wavefronts to hide latency.
 constexpr int BFS_WPW = 16;
 template <class L>
-__global__ __launch_bounds__(MAP_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int layer) {
+__global__ __launch_bounds__(MAP_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int layer, int deferred) {
   MAP_MEMBER
-  if (!map_due(m) || layer > m.zone_width - 1) return;
+  if (layer > m.zone_width - 1) return;
+  if (deferred ? (!m.ctl->maps_partial || layer <= bfs_hot_layers(m.zone_width))
+               : (!map_due(m) || layer > bfs_hot_layers(m.zone_width)))
+    return;
   const MapDims d = m.d;
   const unsigned long long* fin = (layer & 1) ? m.fr0 : m.fr1;
   unsigned long long* fout = (layer & 1) ? m.fr1 : m.fr0;
@@ -848,7 +859,14 @@ static __global__ void k_masks_done(MAP_KERNEL_PARAMS) {
   if (map_due(m) && threadIdx.x == 0) {
     m.ctl->alias_dirty = 0;
     m.ctl->maps_seen = 1;
+    m.ctl->maps_partial = m.zone_width - 1 > bfs_hot_layers(m.zone_width);
   }
+}
+
+// the deferred layers are done (or the maps came whole from the caller)
+static __global__ void k_maps_whole(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (threadIdx.x == 0) m.ctl->maps_partial = 0;
 }
 
 // workgroups of lattice d for each decomposition

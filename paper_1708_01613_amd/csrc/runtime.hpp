@@ -418,7 +418,8 @@ int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh) {
   MAPL(k_write_labels, SH_CELLS, MAP_NT);
   if (refresh) {
     MAPL(k_owner_init, SH_SEG, MAP_NT);
-    for (int layer = 1; layer <= s.max_zone - 1; layer++) MAPL((k_bfs_layer<L>), SH_WORDS, MAP_NT, layer);
+    for (int layer = 1; layer <= std::min(s.max_zone - 1, bfs_hot_layers(s.max_zone)); layer++)
+      MAPL((k_bfs_layer<L>), SH_WORDS, MAP_NT, layer, 0);
     MAPL(k_alias_reset, SH_CELLS, MAP_NT);
     MAPL(k_alias_carry1, SH_CELLS, MAP_NT);
     MAPL(k_alias_carry2, SH_CELLS, MAP_NT);
@@ -428,6 +429,18 @@ int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh) {
   HIPCHK(hipGetLastError());
   return FLB_OK;
 }
+// the BFS layers a refresh defers (run), then the maps are whole; or (run
+// false) the maps given are whole already
+template <class L>
+int map_deferred(const MapSet& s, hipStream_t st, bool run) {
+  if (run)
+    for (int layer = bfs_hot_layers(s.max_zone) + 1; layer <= s.max_zone - 1; layer++)
+      MAPL((k_bfs_layer<L>), SH_WORDS, MAP_NT, layer, 1);
+  MAPL(k_maps_whole, SH_ONE, 64);
+  HIPCHK(hipGetLastError());
+  return FLB_OK;
+}
+
 #undef MAPL
 
 // the context's own map sets, built on first use
@@ -463,6 +476,15 @@ int refresh_maps(flb_ctx* c, bool from_rho) {
   int rc = ctx_mapsets(c);
   if (rc) return rc;
   return map_pipeline<L, S>(from_rho ? c->ms_rho : c->ms_pop, c->st, from_rho ? GAS_RHO : GAS_POP, true);
+}
+
+// ---- the BFS layers a refresh defers, before owner / dist are read ----
+// (a no-op unless the last refresh left them out; film_on only)
+template <class L>
+int complete_maps(flb_ctx* c) {
+  int rc = ctx_mapsets(c);
+  if (rc) return rc;
+  return map_deferred<L>(c->ms_import, c->st, true);
 }
 
 // ---- labels of the current state, or of the field in c->qd ----

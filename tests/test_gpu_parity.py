@@ -351,3 +351,25 @@ def test_autotune_keeps_state_and_results(flb, kind):
     r.step(41)
     assert np.array_equal(g.populations(), r.populations())
     assert g.stats()["n_ruptures"] == r.stats()["n_ruptures"]
+
+
+@pytest.mark.parametrize("zw", [2, 3, 7, 9])
+def test_film_zone_widths_and_deferred_layers(flb, zw):
+    # a refresh builds owner / dist only as deep as a barrier can reach
+    # (zone_width / 2 hops); the deeper layers are filled in when the maps
+    # are read.  Masks, dynamics and the maps read back equal the oracle's,
+    # which always runs the BFS to zone_width - 1 hops
+    rng = np.random.default_rng(40 + zw)
+    nuc = [[float(rng.uniform(0, 120)), float(rng.uniform(0, 70)), 0.0, float(rng.uniform(4, 8))]
+           for _ in range(12)]
+    p = _case(flb, lattice=0, storage="f64", nx=120, ny=70, G=-5.5, rho_liquid=2.3, rho_gas=0.11, film_on=1,
+              k_own=5, zone_width=zw, rupture_warmup=20, seed=9)
+    g, o = _run_pair(flb, p, nuc, 33)
+    gm = _compare_maps(flb, 0, g, o)
+    assert np.array_equal(g.maps()["dist"], gm["dist"])  # reading twice changes nothing
+    assert gm["dist"].max() > zw // 2 or zw - 1 == zw // 2  # deferred layers were exercised
+    g.step(4)
+    o.step(4)
+    _compare_maps(flb, 0, g, o)
+    assert max_rel(g.density(), o.density()) <= 1e-12
+    assert g.stats()["n_ruptures"] == o.n_ruptures
