@@ -108,7 +108,7 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     ok = ok && (c->rep = (int*)c->dalloc(sizeof(int) * (size_t)(c->N + 1)));
     ok = ok && (c->events = (long long*)c->dalloc(sizeof(long long) * 4 * (size_t)c->ev_cap));
     c->nwords = (long long)((c->md.nx + 63) / 64) * c->md.nm * c->md.nz;
-    ok = ok && (c->bits = (unsigned long long*)c->dalloc(sizeof(unsigned long long) * 4 * (size_t)c->nwords));
+    ok = ok && (c->bits = (unsigned long long*)c->dalloc(sizeof(unsigned long long) * (size_t)c->nwords));
   }
   if (!ok) {
     c->dfree_all();

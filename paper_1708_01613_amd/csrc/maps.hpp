@@ -142,9 +142,6 @@ struct MapArgs {
   int* flist;
   int2* rpair;            // alias-root pairs of the owners (mask construction)
   unsigned long long* fwords;  // flag words: bit l of word s = cell 64 xs + l of its row has links
-  unsigned long long* fr0;  // BFS frontier bitsets (ping-pong) and visited set
-  unsigned long long* fr1;
-  unsigned long long* vis;
 };
 
 __device__ __forceinline__ bool map_due(const MapArgs& m) {
@@ -153,7 +150,7 @@ __device__ __forceinline__ bool map_due(const MapArgs& m) {
 }
 
 // decompositions of a map launch (workgroups per lattice)
-enum MapShape { SH_CELLS = 0, SH_SEG, SH_WORDS, SH_CCT, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_COUNT };
+enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_COUNT };
 
 #define MAP_KERNEL_PARAMS const MapArgs *__restrict__ tab, const int *__restrict__ first, int nmem
 #define MAP_MEMBER                                                           \
@@ -456,74 +453,31 @@ static __global__ __launch_bounds__(MAP_NT) void k_keep_old(MAP_KERNEL_PARAMS) {
 }
 
 // ---- owner / dist ----
-// The layered BFS keeps two bitsets with one 64-bit word per row segment
-// (word s covers x = 64 xs .. 64 xs + 63 of row (m, z), s = xs + nxs row):
-// the frontier of the previous layer and the visited set.
+// Gas cells are their own owners at distance 0; every other cell starts
+// unreached (dist 255).
 static __global__ __launch_bounds__(MAP_NT) void k_owner_init(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m)) return;
-  const MapDims d = m.d;
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nxs = (d.nx + 63) >> 6;
-  const unsigned nseg = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
-  for (unsigned s = bid * MAP_WAVES + wv; s < nseg; s += nbk * MAP_WAVES) {
-    const unsigned row = s / (unsigned)nxs;
-    const int x = (int)(s - row * (unsigned)nxs) * 64 + lane;
-    const bool in = x < d.nx;
-    const unsigned c = (unsigned)x + (unsigned)d.nx * row;
-    const int l = in ? m.label[c] : 0;
-    if (in) {
-      m.own[c] = make_int2(l, l);
-      m.dist[c] = l > 0 ? 0 : 255;
-    }
-    const unsigned long long g = __ballot(l > 0);
-    if (lane == 0) {
-      m.fr0[s] = g;
-      m.vis[s] = g;
-    }
+  FOR_SHARE(c, m.d.N) {
+    const int l = m.label[c];
+    m.own[c] = make_int2(l, l);
+    m.dist[c] = l > 0 ? 0 : 255;
   }
 }
-
-// Bitset words of a row: the cells reached by a BFS layer are the unvisited
-// bits of the frontier dilated by the lattice links, formed with whole-word
-// shifts of the neighbour rows' words (x - 1 and x + 1 bring in one bit from
-// the adjacent word, periodic across the row end).  Word bits past the end of
-// a row are always zero.
-struct WordRow {
-  const unsigned long long* __restrict__ b;
-  int nxs, last_valid;  // words per row; valid bits of a row's last word
-  // bits of the cells x + ex for every x of word xs of the row at rowbase
-  __device__ __forceinline__ unsigned long long shifted(unsigned rowbase, int xs, int ex) const {
-    const unsigned long long wc = b[rowbase + xs];
-    if (ex == 0) return wc;
-    if (ex > 0) {
-      const unsigned long long wr = b[rowbase + (xs + 1 < nxs ? xs + 1 : 0)];
-      const int top = xs == nxs - 1 ? last_valid - 1 : 63;
-      return (wc >> 1) | ((wr & 1ull) << top);
-    }
-    const unsigned long long in = xs > 0 ? b[rowbase + xs - 1] >> 63
-                                         : (b[rowbase + nxs - 1] >> (last_valid - 1)) & 1ull;
-    return (wc << 1) | in;
-  }
-};
 
 // Layers a barrier can depend on.  A barrier link joins two owned cells with
 // dist(x) + dist(y) + 1 <= zone_width, and BFS distances of neighbours differ
 // by at most one, so both ends lie within zone_width / 2 hops of a bubble.
 // A refresh runs only these layers; the deeper ones (up to zone_width - 1)
-// fill in the exported maps when they are read, from the frontier the
-// refresh left behind.
+// fill in the exported maps when they are read.
 __host__ __device__ constexpr int bfs_hot_layers(int zone_width) { return zone_width / 2; }
 
-// One BFS layer.  A wavefront takes BFS_WPW words: lane k < BFS_WPW forms
-// the frontier words of its word's 18 neighbourhoods (whole-word shifts) and
-// the word of cells this layer reaches; then the wavefront takes the words
-// with new cells one at a time, its 64 lanes standing for the 64 cells of the
-// word, and every new cell reads only the owners of its frontier neighbours
-// (the smallest owner and the largest owner2 win).  Few words per wavefront
-// keep that serial part short and give many wavefronts to hide latency.
-constexpr int BFS_WPW = 16;
+// One BFS layer, one wavefront per row segment: an unreached cell with a
+// neighbour at distance layer - 1 is reached now and takes the smallest owner
+// and the largest owner2 over those neighbours.  Cells reached in this layer
+// get dist = layer, which no cell of this layer compares with, so the update
+// in place is free of races.  A segment whose cells are all reached costs one
+// load.
 template <class L>
 __global__ __launch_bounds__(MAP_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int layer, int deferred) {
   MAP_MEMBER
@@ -532,74 +486,41 @@ __global__ __launch_bounds__(MAP_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int lay
                : (!map_due(m) || layer > bfs_hot_layers(m.zone_width)))
     return;
   const MapDims d = m.d;
-  const unsigned long long* fin = (layer & 1) ? m.fr0 : m.fr1;
-  unsigned long long* fout = (layer & 1) ? m.fr1 : m.fr0;
-  unsigned long long* vis = m.vis;
   const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nxs = (d.nx + 63) >> 6;
-  const unsigned nw = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
-  const int last_valid = d.nx - 64 * (nxs - 1);
-  const WordRow fr{fin, nxs, last_valid};
-  // wave-uniform loop: every lane takes part in the expansion below
-  const unsigned wave = bid * MAP_WAVES + (threadIdx.x >> 6), nwaves = nbk * MAP_WAVES;
-  for (unsigned base = wave * BFS_WPW; base < nw; base += nwaves * BFS_WPW) {
-    const unsigned s = base + lane;
-    const bool in = lane < BFS_WPW && s < nw;
-    unsigned long long sh[L::Q];
+  const unsigned nseg = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
+  const int prev = layer - 1;
+  for (unsigned s = bid * MAP_WAVES + wv; s < nseg; s += nbk * MAP_WAVES) {  // wave-uniform
+    const unsigned row = s / (unsigned)nxs;
+    const int x = (int)(s - row * (unsigned)nxs) * 64 + lane;
+    const bool in = x < d.nx;
+    const int xc = min(x, d.nx - 1);
+    const unsigned c = (unsigned)xc + (unsigned)d.nx * row;
+    const bool open = in && m.dist[c] == 255;
+    if (!__ballot(open)) continue;
+    const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
+    const int xw[3] = {xc == 0 ? d.nx - 1 : xc - 1, xc, xc == d.nx - 1 ? 0 : xc + 1};
+    const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
+    const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
+    unsigned y[L::Q];
+    uint8_t dn[L::Q];
 #pragma unroll
-    for (int i = 0; i < L::Q; i++) sh[i] = 0ull;
-    unsigned long long nwb = 0ull;
-    unsigned row = 0;
-    int xs = 0;
-    if (in) {
-      row = s / (unsigned)nxs;
-      xs = (int)(s - row * (unsigned)nxs);
-      const unsigned long long valid = (xs == nxs - 1 && last_valid < 64) ? (1ull << last_valid) - 1ull : ~0ull;
-      const unsigned long long v = vis[s];
-      if ((v & valid) != valid) {
-        const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
-        const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
-        const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
-        unsigned long long reach = 0ull;
-#pragma unroll
-        for (int i = 1; i < L::Q; i++) {
-          const unsigned rb =
-              (unsigned)nxs * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
-          sh[i] = fr.shifted(rb, xs, L::ex[i]);
-          reach |= sh[i];
-        }
-        nwb = reach & ~v & valid;
-        vis[s] = v | nwb;
-      }
-      fout[s] = nwb;
+    for (int i = 1; i < L::Q; i++) {
+      y[i] = (unsigned)xw[1 + L::ex[i]] +
+             (unsigned)d.nx * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
+      dn[i] = m.dist[y[i]];
     }
-    unsigned long long todo = __ballot(nwb != 0ull);
-    while (todo) {
-      const int ld = first_lane(todo);
-      todo &= todo - 1ull;
-      const unsigned long long w = __shfl(nwb, ld, 64);
-      const unsigned wrow = __shfl(row, ld, 64);
-      const int wxs = __shfl(xs, ld, 64);
-      unsigned long long mine[L::Q];  // the leader's frontier words, on every lane
+    if (open) {
+      int lo = 0x7fffffff, hi = 0;
 #pragma unroll
-      for (int i = 1; i < L::Q; i++) mine[i] = __shfl(sh[i], ld, 64);
-      if ((w >> lane) & 1ull) {
-        const int x = wxs * 64 + lane;
-        const int mm_ = (int)(wrow % (unsigned)d.nm), z = (int)(wrow / (unsigned)d.nm);
-        const int xw[3] = {x == 0 ? d.nx - 1 : x - 1, x, x == d.nx - 1 ? 0 : x + 1};
-        const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
-        const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
-        int lo = 0x7fffffff, hi = 0;
-#pragma unroll
-        for (int i = 1; i < L::Q; i++) {
-          if (!((mine[i] >> lane) & 1ull)) continue;
-          const unsigned y = (unsigned)xw[1 + L::ex[i]] +
-                             (unsigned)d.nx * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
-          const int2 o = m.own[y];
-          lo = min(lo, o.x);
-          hi = max(hi, o.y);
-        }
-        const unsigned c = (unsigned)x + (unsigned)d.nx * wrow;
+      for (int i = 1; i < L::Q; i++) {
+        if (dn[i] != prev) continue;
+        const int2 o = m.own[y[i]];
+        lo = min(lo, o.x);
+        hi = max(hi, o.y);
+      }
+      if (hi > 0) {
         m.own[c] = make_int2(lo, hi);
         m.dist[c] = (uint8_t)layer;
       }
@@ -878,7 +799,6 @@ __host__ inline int map_share(int shape, const MapDims& d) {
   switch (shape) {
     case SH_CELLS: g = std::min<long long>((N + 1 + MAP_NT - 1) / MAP_NT, 16384); break;
     case SH_SEG: g = std::min<long long>((nseg + MAP_WAVES - 1) / MAP_WAVES, 65536); break;
-    case SH_WORDS: g = std::min<long long>((nseg + BFS_WPW * MAP_WAVES - 1) / (BFS_WPW * MAP_WAVES), 65536); break;
     case SH_CCT: g = cc_tiles(d, CCTile<L>::TM, CCTile<L>::TZ); break;
     case SH_RANK: g = (N + RANK_BLOCK - 1) / RANK_BLOCK; break;
     case SH_ONE: g = 1; break;

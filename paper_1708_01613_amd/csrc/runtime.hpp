@@ -121,7 +121,7 @@ inline size_t ctx_footprint(const flb_params* p) {
              2 * r(4 * N) + r(4 * (N / 1024 + 2)) + r(4 * N) + r(8 * (N + 1));
   if (p->film_on) {
     const size_t nwords = nxb * nm * nz;
-    t += 2 * r(N) + r(4 * N) + r(8 * N) + 2 * r(4 * N) + 3 * r(4 * (N + 1)) + r(32 * 65536) + r(24 * nwords) +
+    t += 2 * r(N) + r(4 * N) + r(8 * N) + 2 * r(4 * N) + 3 * r(4 * (N + 1)) + r(32 * 65536) +
          r(4 * N) + r(8 * N) + r(8 * nwords);
   }
   return t;
@@ -175,7 +175,7 @@ struct flb_ctx {
   int* par = nullptr;
   int* rank = nullptr;
   int* counts = nullptr;
-  unsigned long long* bits = nullptr;  // bitsets: 2 BFS frontiers, visited, flag words
+  unsigned long long* bits = nullptr;  // flag words: one bit per cell, set where the cell has barrier links
   long long nwords = 0;                // 64-bit words per bitset
   long long* events = nullptr;
   unsigned ev_cap = 1u << 16;
@@ -374,10 +374,7 @@ inline MapArgs map_args(flb_ctx* c, bool query, int src) {
     a.mask = c->mask;
     a.flist = c->flist;
     a.rpair = c->rpair;
-    a.fr0 = c->bits;
-    a.fr1 = c->bits + c->nwords;
-    a.vis = c->bits + 2 * c->nwords;
-    a.fwords = c->bits + 3 * c->nwords;
+    a.fwords = c->bits;
   }
   return a;
 }
@@ -417,9 +414,9 @@ int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh) {
   MAPL(k_write_rank, SH_RANK, RANK_BLOCK);
   MAPL(k_write_labels, SH_CELLS, MAP_NT);
   if (refresh) {
-    MAPL(k_owner_init, SH_SEG, MAP_NT);
+    MAPL(k_owner_init, SH_CELLS, MAP_NT);
     for (int layer = 1; layer <= std::min(s.max_zone - 1, bfs_hot_layers(s.max_zone)); layer++)
-      MAPL((k_bfs_layer<L>), SH_WORDS, MAP_NT, layer, 0);
+      MAPL((k_bfs_layer<L>), SH_SEG, MAP_NT, layer, 0);
     MAPL(k_alias_reset, SH_CELLS, MAP_NT);
     MAPL(k_alias_carry1, SH_CELLS, MAP_NT);
     MAPL(k_alias_carry2, SH_CELLS, MAP_NT);
@@ -435,7 +432,7 @@ template <class L>
 int map_deferred(const MapSet& s, hipStream_t st, bool run) {
   if (run)
     for (int layer = bfs_hot_layers(s.max_zone) + 1; layer <= s.max_zone - 1; layer++)
-      MAPL((k_bfs_layer<L>), SH_WORDS, MAP_NT, layer, 1);
+      MAPL((k_bfs_layer<L>), SH_SEG, MAP_NT, layer, 1);
   MAPL(k_maps_whole, SH_ONE, 64);
   HIPCHK(hipGetLastError());
   return FLB_OK;
