@@ -89,33 +89,46 @@ def measured_traffic():
         return None
 
 
+def _rounded(r):
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+
+
 def batched_and_served(args):
-    """Reduced forms of the batched-ensemble and served-stream workloads:
-    64 uneven D2Q9 lattices (batched vs one-by-one), and a Poisson stream of
-    mixed D2Q9/D3Q19 jobs (server vs first-come first-served)."""
+    """The batched-ensemble and served-stream workloads: 64 uneven D2Q9
+    lattices (one batch vs one lattice at a time), and Poisson streams of
+    mixed D2Q9/D3Q19 jobs in two mixes (the job server with FIFO and with
+    shortest-remaining-work scheduling vs first-come first-served one job at
+    a time)."""
     import torch
 
-    from paper_1708_01613_amd import inputs, serve
+    from paper_1708_01613_amd import foamlbm, inputs, serve
 
     out = {}
     members, _ = inputs.config_ensemble()
     cells = sum(p["nx"] * p["ny"] for p, _ in members)
-    for mode in ("batched", "sequential"):
-        r = serve.ensemble(members, args.ensemble_steps, mode=mode)
-        log(f"ensemble {mode}: {r['MLUPS']:.0f} MLUPS")
-        out[f"ensemble_{mode}"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+    seq_steps = min(args.ensemble_steps, 2000)
+    for mode, steps in (("batched", args.ensemble_steps), ("sequential", seq_steps)):
+        r = serve.ensemble(members, steps, mode=mode)
+        log(f"ensemble {mode}: {r['MLUPS']:.0f} MLUPS over {steps} steps")
+        out[f"ensemble_{mode}"] = dict(_rounded(r), steps=steps)
         torch.cuda.empty_cache()
     out["ensemble"] = {"lattices": len(members), "cells": cells, "steps": args.ensemble_steps,
                        "speedup": round(out["ensemble_batched"]["MLUPS"] / out["ensemble_sequential"]["MLUPS"], 2)}
-    trace = inputs.arrival_trace(n_requests=args.serve_jobs)
-    for j in trace:
-        j["steps"] = args.serve_steps
-    for mode in ("server", "sequential"):
-        r = serve.served(trace, mode=mode)
-        log(f"served {mode}: {r['MLUPS']:.0f} MLUPS p50 {r['p50_s']:.2f}s p99 {r['p99_s']:.2f}s")
-        out[f"served_{mode}"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
-        torch.cuda.empty_cache()
-    out["served"] = {"jobs": len(trace), "rate_per_s": 20.0, "steps_per_job": args.serve_steps}
+    rate = 20.0
+    for tag, d3 in (("mix50", 0.5), ("mix10", 0.1)):
+        trace = inputs.arrival_trace(n_requests=args.serve_jobs, rate=rate, d3_fraction=d3)
+        for j in trace:
+            j["steps"] = args.serve_steps
+        res = {"jobs": len(trace), "d3_fraction": d3, "rate_per_s": rate, "steps_per_job": args.serve_steps,
+               "offered_MLUPS": round(serve.offered_mlups(trace, rate), 1)}
+        for name, mode, policy in (("fifo", "server", foamlbm.FLB_SERVE_FIFO),
+                                   ("shortest", "server", foamlbm.FLB_SERVE_SHORTEST),
+                                   ("sequential", "sequential", None)):
+            r = serve.served(trace, mode=mode, policy=policy)
+            log(f"served {tag} {name}: {r['MLUPS']:.0f} MLUPS p50 {r['p50_s']:.3f}s p99 {r['p99_s']:.3f}s")
+            res[name] = _rounded(r)
+            torch.cuda.empty_cache()
+        out[f"served_{tag}"] = res
     return out
 
 
@@ -149,7 +162,7 @@ def main():
     ap.add_argument("--lz", type=int, default=0)
     ap.add_argument("--xcd", type=int, default=-1)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and served measurements")
-    ap.add_argument("--ensemble-steps", type=int, default=1000)
+    ap.add_argument("--ensemble-steps", type=int, default=10000)
     ap.add_argument("--serve-jobs", type=int, default=48)
     ap.add_argument("--serve-steps", type=int, default=1000)
     args = ap.parse_args()

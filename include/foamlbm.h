@@ -282,11 +282,15 @@ void flb_batch_destroy(flb_batch* batch);
  * Jobs (a parameter set, nuclei and a step count) queue in submission order.
  * Each flb_server_pump is one scheduling round: it admits queued jobs, in
  * order, while the device bytes of all admitted jobs stay within
- * pool_bytes, fewer than max_jobs are resident and the running jobs hold at
- * most max_cells lattice cells (a job larger than max_cells runs once nothing
- * else does; a job that does not fit waits, and so do the jobs behind it); it advances every running job by the
- * same number of steps, chunk_steps or fewer so that no job passes its last
- * step, with batched launches (one batch per lattice type and storage, runs
+ * pool_bytes and fewer than max_jobs are resident (a job that does not fit
+ * waits, and so do the jobs behind it); it picks the resident jobs to
+ * advance -- FLB_SERVE_FIFO: all of them, and admission also stops once the
+ * resident jobs would hold more than max_cells lattice cells (a larger job
+ * runs once nothing else does); FLB_SERVE_SHORTEST: those with the least
+ * remaining work (cells x steps left) while their cells stay within
+ * max_cells (at least one; a job passed over 8 rounds in a row goes first)
+ * -- and advances them by the same number of steps, chunk_steps or fewer so
+ * that no job passes its last step, with batched launches (one batch per lattice type and storage, runs
  * of graph_steps steps replayed from captured HIP graphs); and it retires the
  * jobs that are done: their final density and statistics are copied to host
  * memory and their device memory is released.  The round synchronises the
@@ -300,10 +304,13 @@ typedef struct {
   int32_t graph_steps; /* steps per captured graph (0: no graphs) */
   int64_t max_cells;   /* lattice cells of the running jobs at most: enough
                           to fill the GPU; more only lengthens every job */
+  int32_t policy;      /* FLB_SERVE_FIFO or FLB_SERVE_SHORTEST */
 } flb_server_config;
+enum { FLB_SERVE_FIFO = 0, FLB_SERVE_SHORTEST = 1 };
 enum { FLB_JOB_QUEUED = 0, FLB_JOB_RUNNING = 1, FLB_JOB_DONE = 2, FLB_JOB_FAILED = 3 };
 
-/* pool 64 GiB, 256 jobs, chunks of 100 steps, graphs of 20 steps, 2^24 cells */
+/* pool 64 GiB, 256 jobs, chunks of 100 steps, graphs of 20 steps, 2^24 cells,
+ * FLB_SERVE_FIFO */
 void flb_server_default_config(flb_server_config* cfg);
 int flb_server_create(const flb_server_config* cfg, const flb_allocator* alloc, void* hip_stream,
                       flb_server** out);

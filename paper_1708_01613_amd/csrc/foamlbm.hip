@@ -99,7 +99,6 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     ok = ok && (c->dist = (uint8_t*)c->dalloc((size_t)c->N));
     ok = ok && (c->mask = (uint32_t*)c->dalloc(sizeof(uint32_t) * (size_t)c->N));
     ok = ok && (c->flist = (int*)c->dalloc(sizeof(int) * (size_t)c->N));
-    ok = ok && (c->rpair = (int2*)c->dalloc(sizeof(int2) * (size_t)c->N));
     ok = ok && (c->own = (int2*)c->dalloc(sizeof(int2) * (size_t)c->N));
     ok = ok && (c->label = (int*)c->dalloc(sizeof(int) * (size_t)c->N));
     ok = ok && (c->label_old = (int*)c->dalloc(sizeof(int) * (size_t)c->N));

@@ -140,7 +140,6 @@ struct MapArgs {
   uint8_t* flag;
   uint32_t* mask;
   int* flist;
-  int2* rpair;            // alias-root pairs of the owners (mask construction)
   unsigned long long* fwords;  // flag words: bit l of word s = cell 64 xs + l of its row has links
 };
 
@@ -150,7 +149,7 @@ __device__ __forceinline__ bool map_due(const MapArgs& m) {
 }
 
 // decompositions of a map launch (workgroups per lattice)
-enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_COUNT };
+enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_BFST, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_COUNT };
 
 #define MAP_KERNEL_PARAMS const MapArgs *__restrict__ tab, const int *__restrict__ first, int nmem
 #define MAP_MEMBER                                                           \
@@ -472,59 +471,142 @@ static __global__ __launch_bounds__(MAP_NT) void k_owner_init(MAP_KERNEL_PARAMS)
 // fill in the exported maps when they are read.
 __host__ __device__ constexpr int bfs_hot_layers(int zone_width) { return zone_width / 2; }
 
-// One BFS layer, one wavefront per row segment: an unreached cell with a
+// One BFS layer over tiles of 64 x TM x TZ cells: the workgroup stages the
+// distances of its tile and a one-cell halo in LDS (a tile whose cells are
+// all reached stops after reading its own), then every unreached cell with a
 // neighbour at distance layer - 1 is reached now and takes the smallest owner
 // and the largest owner2 over those neighbours.  Cells reached in this layer
 // get dist = layer, which no cell of this layer compares with, so the update
-// in place is free of races.  A segment whose cells are all reached costs one
-// load.
+// in place is free of races.
+__device__ __forceinline__ int wrap_mod(int a, int n) {
+  if (a >= 0 && a < n) return a;
+  const int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
 template <class L>
-__global__ __launch_bounds__(MAP_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int layer, int deferred) {
+struct BfsTile {
+  static constexpr int TM = L::HAS_M ? 4 : 1;
+  static constexpr int TZ = L::HAS_M ? 4 : 16;
+  static constexpr int HM = L::HAS_M ? 1 : 0;  // halo along m (none on 2-D lattices)
+  static constexpr int LX = 64 + 2, LM = TM + 2 * HM, LZ = TZ + 2;
+  static constexpr int CELLS = 64 * TM * TZ;
+  static constexpr int HALO = LX * LM * LZ;
+};
+constexpr int BFS_NT = 256;
+
+// The halo of a tile, row by row: halo row hr (LM x LZ of them) holds the
+// cells x0 - 1 .. x0 + 64 of lattice row (m0 - HM + hr % LM, z0 - 1 + hr / LM),
+// wrapped periodically.  Wavefront w takes rows w, w + 4, ...: its lanes load
+// the 64 cells x0 + lane (x0 + lane past the lattice end wraps to the cell
+// that is the periodic neighbour of the last one), lanes 0 and 1 also the
+// two end cells.  The row arithmetic is wave-uniform.
+template <class T>
+struct HaloRows {
+  static constexpr int NR = T::LM * T::LZ;
+  static constexpr int RPW = (NR + BFS_NT / 64 - 1) / (BFS_NT / 64);  // rows per wavefront
+  int wv, lane, xa, xe;
+  __device__ HaloRows(const MapDims& d, int x0) {
+    wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    lane = (int)threadIdx.x & 63;
+    xa = wrap_mod(x0 + lane, d.nx);
+    xe = wrap_mod(lane == 0 ? x0 - 1 : x0 + 64, d.nx);
+  }
+  __device__ __forceinline__ int row(int j) const { return wv + j * (BFS_NT / 64); }
+  // first cell index of halo row hr
+  __device__ __forceinline__ unsigned base(const MapDims& d, int m0, int z0, int hr) const {
+    const int gm = T::HM ? wrap_mod(m0 - 1 + hr % T::LM, d.nm) : 0;
+    const int gz = wrap_mod(z0 - 1 + hr / T::LM, d.nz);
+    return (unsigned)d.nx * ((unsigned)gm + (unsigned)d.nm * (unsigned)gz);
+  }
+};
+
+// offsets from a cell to its neighbours along one axis, periodic
+struct AxisStep {
+  int dn, up;
+  __device__ AxisStep(int i, int n, int stride)
+      : dn((i == 0 ? n - 1 : -1) * stride), up((i == n - 1 ? 1 - n : 1) * stride) {}
+  __device__ __forceinline__ int of(int e) const { return e < 0 ? dn : (e > 0 ? up : 0); }
+};
+
+template <class L>
+__global__ __launch_bounds__(BFS_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int layer, int deferred) {
   MAP_MEMBER
   if (layer > m.zone_width - 1) return;
   if (deferred ? (!m.ctl->maps_partial || layer <= bfs_hot_layers(m.zone_width))
                : (!map_due(m) || layer > bfs_hot_layers(m.zone_width)))
     return;
+  using T = BfsTile<L>;
+  using H = HaloRows<T>;
+  constexpr int PER = T::CELLS / BFS_NT;
+  __shared__ uint8_t ld[T::HALO];
   const MapDims d = m.d;
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nxs = (d.nx + 63) >> 6;
-  const unsigned nseg = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
-  const int prev = layer - 1;
-  for (unsigned s = bid * MAP_WAVES + wv; s < nseg; s += nbk * MAP_WAVES) {  // wave-uniform
-    const unsigned row = s / (unsigned)nxs;
-    const int x = (int)(s - row * (unsigned)nxs) * 64 + lane;
-    const bool in = x < d.nx;
-    const int xc = min(x, d.nx - 1);
-    const unsigned c = (unsigned)xc + (unsigned)d.nx * row;
-    const bool open = in && m.dist[c] == 255;
-    if (!__ballot(open)) continue;
-    const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
-    const int xw[3] = {xc == 0 ? d.nx - 1 : xc - 1, xc, xc == d.nx - 1 ? 0 : xc + 1};
-    const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
-    const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
-    unsigned y[L::Q];
-    uint8_t dn[L::Q];
+  const int ntx = (d.nx + 63) / 64, ntm = (d.nm + T::TM - 1) / T::TM;
+  const int b = (int)bid;
+  const int x0 = (b % ntx) * 64, m0 = ((b / ntx) % ntm) * T::TM, z0 = (b / (ntx * ntm)) * T::TZ;
+  const int lx = threadIdx.x & 63;
+  const int x = x0 + lx;
+  unsigned cidx[PER];
+  bool open[PER];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int r = (int)(threadIdx.x >> 6) + k * (BFS_NT / 64);
+    const int mm_ = m0 + r % T::TM, z = z0 + r / T::TM;
+    const bool in = x < d.nx && mm_ < d.nm && z < d.nz;
+    cidx[k] = in ? (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z) : 0u;
+    open[k] = in && m.dist[cidx[k]] == 255;
+    any |= open[k];
+  }
+  if (!__syncthreads_or(any)) return;  // block-uniform
+  const H hr(d, x0);
+  uint8_t va[H::RPW], ve[H::RPW];
+#pragma unroll
+  for (int j = 0; j < H::RPW; j++) {
+    va[j] = ve[j] = 0;
+    if (hr.row(j) < H::NR) {
+      const unsigned base = hr.base(d, m0, z0, hr.row(j));
+      va[j] = m.dist[base + (unsigned)hr.xa];
+      if (hr.lane < 2) ve[j] = m.dist[base + (unsigned)hr.xe];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < H::RPW; j++) {
+    if (hr.row(j) < H::NR) {
+      uint8_t* rowp = ld + hr.row(j) * T::LX;
+      rowp[1 + hr.lane] = va[j];
+      if (hr.lane < 2) rowp[hr.lane == 0 ? 0 : T::LX - 1] = ve[j];
+    }
+  }
+  __syncthreads();
+  const uint8_t prev = (uint8_t)(layer - 1);
+  const AxisStep sx(x < d.nx ? x : 0, d.nx, 1);
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    if (!open[k]) continue;
+    const int r = (int)(threadIdx.x >> 6) + k * (BFS_NT / 64);
+    const int lm = r % T::TM, lz = r / T::TM;
+    const int lc = (lx + 1) + T::LX * ((lm + T::HM) + T::LM * (lz + 1));
+    unsigned hit = 0;
+#pragma unroll
+    for (int i = 1; i < L::Q; i++)
+      if (ld[lc + L::ex[i] + T::LX * (L::em[i] + T::LM * L::ez[i])] == prev) hit |= 1u << i;
+    if (!hit) continue;
+    const AxisStep sm(m0 + lm, d.nm, d.nx), sz(z0 + lz, d.nz, d.nx * d.nm);
+    int2 o[L::Q];
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {  // the owners of all frontier neighbours in flight at once
+      o[i] = make_int2(0x7fffffff, 0);
+      if (hit & (1u << i)) o[i] = m.own[(int)cidx[k] + sx.of(L::ex[i]) + sm.of(L::em[i]) + sz.of(L::ez[i])];
+    }
+    int lo = 0x7fffffff, hi = 0;
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
-      y[i] = (unsigned)xw[1 + L::ex[i]] +
-             (unsigned)d.nx * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
-      dn[i] = m.dist[y[i]];
+      lo = min(lo, o[i].x);
+      hi = max(hi, o[i].y);
     }
-    if (open) {
-      int lo = 0x7fffffff, hi = 0;
-#pragma unroll
-      for (int i = 1; i < L::Q; i++) {
-        if (dn[i] != prev) continue;
-        const int2 o = m.own[y[i]];
-        lo = min(lo, o.x);
-        hi = max(hi, o.y);
-      }
-      if (hi > 0) {
-        m.own[c] = make_int2(lo, hi);
-        m.dist[c] = (uint8_t)layer;
-      }
-    }
+    m.own[cidx[k]] = make_int2(lo, hi);
+    m.dist[cidx[k]] = (uint8_t)layer;
   }
 }
 
@@ -601,73 +683,128 @@ static __global__ __launch_bounds__(MAP_NT) void k_alias_compress(MAP_KERNEL_PAR
   FOR_SHARE(b, (long long)nb + 1) m.alias[b] = uf_find_live(m.alias, (int)b);
 }
 
-// alias-root pair of every owned cell's owners, (0, 0) for unowned cells;
-// the aliases are compressed at every refresh, so one look-up gives a root
-static __global__ __launch_bounds__(MAP_NT) void k_root_pairs(MAP_KERNEL_PARAMS) {
-  MAP_MEMBER
-  if (!map_due(m)) return;
-  FOR_SHARE(c, m.d.N) {
-    int2 r = make_int2(0, 0);
-    if (m.dist[c] != 255) {
-      const int2 o = m.own[c];
-      const int a = m.alias[o.x], b = m.alias[o.y];
-      r = make_int2(min(a, b), max(a, b));
-    }
-    m.rpair[c] = r;
-  }
-}
-
-// Barrier masks from the distances and root pairs, one wavefront per row
-// segment; a cell's 18 neighbours are loaded before any is tested.  The
-// segment's cells with links form one word of the flag bitset, from which
-// k_flag_count / k_scan_counts / k_flag_write build the flagged-cell list in
-// cell order (no atomics).
+// Barrier masks over the BFS tiles: the workgroup stages, for its tile and a
+// one-cell halo, every cell's distance and, for owned cells, its owner pair.
+// A link is a barrier iff both ends are owned, the film is thin enough
+// (dist + dist + 1 <= zone_width) and the alias-root pairs of the two owner
+// pairs differ; equal owner pairs have equal root pairs, so the aliases are
+// looked up only where the owner pairs differ (near the walls between zones;
+// the aliases are compressed at every refresh, so one look-up gives a root).
+// Each wavefront handles whole 64-cell row segments, whose cells with links
+// form one word of the flag bitset, from which k_flag_count / k_scan_counts /
+// k_flag_write build the flagged-cell list in cell order (no atomics).  A tile
+// without owned cells only clears its masks.
 template <class L>
-__global__ __launch_bounds__(MAP_NT) void k_masks(MAP_KERNEL_PARAMS) {
+__global__ __launch_bounds__(BFS_NT) void k_masks(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m)) return;
-  const int zone_width = m.zone_width;
-  const int lane = threadIdx.x & 63;
+  using T = BfsTile<L>;
+  using H = HaloRows<T>;
+  constexpr int PER = T::CELLS / BFS_NT;
+  __shared__ uint8_t ld[T::HALO];
+  __shared__ int2 lo[T::HALO];
   const MapDims d = m.d;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nxs = (d.nx + 63) >> 6;
-  const unsigned nseg = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
-  for (unsigned s = bid * MAP_WAVES + wv; s < nseg; s += nbk * MAP_WAVES) {  // wave-uniform
-    const unsigned row = s / (unsigned)nxs;
-    const int x = (int)(s - row * (unsigned)nxs) * 64 + lane;
-    const bool in = x < d.nx;
-    const int xc = min(x, d.nx - 1);
-    const unsigned c = (unsigned)xc + (unsigned)d.nx * row;
-    const int dc = in ? m.dist[c] : 255;
-    unsigned mk = 0;
-    if (__ballot(dc != 255)) {  // any owned cell in the segment
-      const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
-      const int xw[3] = {xc == 0 ? d.nx - 1 : xc - 1, xc, xc == d.nx - 1 ? 0 : xc + 1};
-      const int mm[3] = {mm_ == 0 ? d.nm - 1 : mm_ - 1, mm_, mm_ == d.nm - 1 ? 0 : mm_ + 1};
-      const int zz[3] = {z == 0 ? d.nz - 1 : z - 1, z, z == d.nz - 1 ? 0 : z + 1};
-      const int2 rp = m.rpair[c];
-      uint8_t dn[L::Q];
-      int2 rn[L::Q];
+  const int zone_width = m.zone_width;
+  const int ntx = (d.nx + 63) / 64, ntm = (d.nm + T::TM - 1) / T::TM;
+  const int b = (int)bid;
+  const int x0 = (b % ntx) * 64, m0 = ((b / ntx) % ntm) * T::TM, z0 = (b / (ntx * ntm)) * T::TZ;
+  const int lane = threadIdx.x & 63;
+  const int x = x0 + lane;
+  unsigned cidx[PER];
+  bool in[PER], rowin[PER];
+  bool any = false;
 #pragma unroll
-      for (int i = 1; i < L::Q; i++) {
-        const unsigned y = (unsigned)xw[1 + L::ex[i]] +
-                           (unsigned)d.nx * ((unsigned)mm[1 + L::em[i]] + (unsigned)d.nm * (unsigned)zz[1 + L::ez[i]]);
-        dn[i] = m.dist[y];
-        rn[i] = m.rpair[y];
-      }
-      if (dc != 255) {
+  for (int k = 0; k < PER; k++) {
+    const int r = (int)(threadIdx.x >> 6) + k * (BFS_NT / 64);
+    const int mm_ = m0 + r % T::TM, z = z0 + r / T::TM;
+    rowin[k] = mm_ < d.nm && z < d.nz;
+    in[k] = rowin[k] && x < d.nx;
+    cidx[k] = in[k] ? (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z) : 0u;
+    any |= in[k] && m.dist[cidx[k]] != 255;
+  }
+  const bool owned = __syncthreads_or(any);  // block-uniform
+  if (owned) {
+    const H hr(d, x0);
+    unsigned ga[H::RPW], ge[H::RPW];
+    uint8_t da[H::RPW], de[H::RPW];
 #pragma unroll
-        for (int i = 1; i < L::Q; i++)
-          // both ends owned (dist 255 fails the sum), thin enough, different pairs
-          if (dc + (int)dn[i] + 1 <= zone_width && (rn[i].x != rp.x || rn[i].y != rp.y)) mk |= 1u << i;
+    for (int j = 0; j < H::RPW; j++) {  // distances, then the owners of owned cells
+      da[j] = de[j] = 255;
+      ga[j] = ge[j] = 0;
+      if (hr.row(j) < H::NR) {
+        const unsigned base = hr.base(d, m0, z0, hr.row(j));
+        ga[j] = base + (unsigned)hr.xa;
+        ge[j] = base + (unsigned)hr.xe;
+        da[j] = m.dist[ga[j]];
+        if (hr.lane < 2) de[j] = m.dist[ge[j]];
       }
     }
-    if (in) {
-      m.flag[c] = mk ? 1 : 0;
-      m.mask[c] = mk;
+    int2 oa[H::RPW], oe[H::RPW];
+#pragma unroll
+    for (int j = 0; j < H::RPW; j++) {
+      oa[j] = da[j] != 255 ? m.own[ga[j]] : make_int2(0, 0);
+      oe[j] = de[j] != 255 ? m.own[ge[j]] : make_int2(0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < H::RPW; j++) {
+      if (hr.row(j) >= H::NR) continue;
+      const int at = hr.row(j) * T::LX;
+      ld[at + 1 + hr.lane] = da[j];
+      lo[at + 1 + hr.lane] = oa[j];
+      if (hr.lane < 2) {
+        const int e = at + (hr.lane == 0 ? 0 : T::LX - 1);
+        ld[e] = de[j];
+        lo[e] = oe[j];
+      }
+    }
+    __syncthreads();
+  }
+  const int nxs = (d.nx + 63) >> 6;
+  const int* __restrict__ alias = m.alias;
+  auto root_pair = [&](int2 o) {
+    const int ra = alias[o.x], rb = alias[o.y];
+    return make_int2(min(ra, rb), max(ra, rb));
+  };
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int r = (int)(threadIdx.x >> 6) + k * (BFS_NT / 64);
+    const int lm = r % T::TM, lz = r / T::TM;
+    unsigned mk = 0;
+    if (owned && in[k]) {
+      const int lc = (lane + 1) + T::LX * ((lm + T::HM) + T::LM * (lz + 1));
+      const int dc = ld[lc];
+      if (dc != 255) {
+        const int2 oc = lo[lc];
+        unsigned cand = 0;  // thin links to cells with another owner pair
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) {
+          const int li = lc + L::ex[i] + T::LX * (L::em[i] + T::LM * L::ez[i]);
+          // both ends owned (dist 255 fails the sum), thin enough, different owners
+          if (dc + (int)ld[li] + 1 <= zone_width) {
+            const int2 on = lo[li];
+            if (on.x != oc.x || on.y != oc.y) cand |= 1u << i;
+          }
+        }
+        if (cand) {
+          const int2 rc = root_pair(oc);
+#pragma unroll
+          for (int i = 1; i < L::Q; i++) {
+            if (!(cand & (1u << i))) continue;
+            const int2 rn = root_pair(lo[lc + L::ex[i] + T::LX * (L::em[i] + T::LM * L::ez[i])]);
+            if (rn.x != rc.x || rn.y != rc.y) mk |= 1u << i;
+          }
+        }
+      }
+    }
+    if (in[k]) {
+      m.flag[cidx[k]] = mk ? 1 : 0;
+      m.mask[cidx[k]] = mk;
     }
     const unsigned long long bal = __ballot(mk != 0);
-    if (lane == 0) m.fwords[s] = bal;
+    if (rowin[k] && lane == 0) {
+      const unsigned row = (unsigned)(m0 + lm) + (unsigned)d.nm * (unsigned)(z0 + lz);
+      m.fwords[(unsigned)(x0 >> 6) + (unsigned)nxs * row] = bal;
+    }
   }
 }
 
@@ -800,6 +937,7 @@ __host__ inline int map_share(int shape, const MapDims& d) {
     case SH_CELLS: g = std::min<long long>((N + 1 + MAP_NT - 1) / MAP_NT, 16384); break;
     case SH_SEG: g = std::min<long long>((nseg + MAP_WAVES - 1) / MAP_WAVES, 65536); break;
     case SH_CCT: g = cc_tiles(d, CCTile<L>::TM, CCTile<L>::TZ); break;
+    case SH_BFST: g = cc_tiles(d, BfsTile<L>::TM, BfsTile<L>::TZ); break;
     case SH_RANK: g = (N + RANK_BLOCK - 1) / RANK_BLOCK; break;
     case SH_ONE: g = 1; break;
     case SH_LIST: g = list_grid(N); break;

@@ -122,7 +122,7 @@ inline size_t ctx_footprint(const flb_params* p) {
   if (p->film_on) {
     const size_t nwords = nxb * nm * nz;
     t += 2 * r(N) + r(4 * N) + r(8 * N) + 2 * r(4 * N) + 3 * r(4 * (N + 1)) + r(32 * 65536) +
-         r(4 * N) + r(8 * N) + r(8 * nwords);
+         r(4 * N) + r(8 * nwords);
   }
   return t;
 }
@@ -165,7 +165,6 @@ struct flb_ctx {
   uint8_t* dist = nullptr;
   uint32_t* mask = nullptr;
   int* flist = nullptr;    // cells with barrier links at the last refresh
-  int2* rpair = nullptr;   // alias-root pairs of the owners, at refresh
   int2* own = nullptr;
   int* label = nullptr;
   int* label_old = nullptr;
@@ -373,7 +372,6 @@ inline MapArgs map_args(flb_ctx* c, bool query, int src) {
     a.flag = c->flag;
     a.mask = c->mask;
     a.flist = c->flist;
-    a.rpair = c->rpair;
     a.fwords = c->bits;
   }
   return a;
@@ -386,8 +384,7 @@ inline MapArgs map_args(flb_ctx* c, bool query, int src) {
 // owners, distances and aliases in place.
 template <class L>
 int map_masks(const MapSet& s, hipStream_t st) {
-  MAPL(k_root_pairs, SH_CELLS, MAP_NT);
-  MAPL((k_masks<L>), SH_SEG, MAP_NT);
+  MAPL((k_masks<L>), SH_BFST, BFS_NT);
   MAPL(k_flag_count, SH_FW, FW_BLOCK);
   MAPL(k_scan_counts, SH_ONE, 1024, 1);
   MAPL(k_flag_write, SH_FW, FW_BLOCK);
@@ -416,7 +413,7 @@ int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh) {
   if (refresh) {
     MAPL(k_owner_init, SH_CELLS, MAP_NT);
     for (int layer = 1; layer <= std::min(s.max_zone - 1, bfs_hot_layers(s.max_zone)); layer++)
-      MAPL((k_bfs_layer<L>), SH_SEG, MAP_NT, layer, 0);
+      MAPL((k_bfs_layer<L>), SH_BFST, BFS_NT, layer, 0);
     MAPL(k_alias_reset, SH_CELLS, MAP_NT);
     MAPL(k_alias_carry1, SH_CELLS, MAP_NT);
     MAPL(k_alias_carry2, SH_CELLS, MAP_NT);
@@ -432,7 +429,7 @@ template <class L>
 int map_deferred(const MapSet& s, hipStream_t st, bool run) {
   if (run)
     for (int layer = bfs_hot_layers(s.max_zone) + 1; layer <= s.max_zone - 1; layer++)
-      MAPL((k_bfs_layer<L>), SH_SEG, MAP_NT, layer, 1);
+      MAPL((k_bfs_layer<L>), SH_BFST, BFS_NT, layer, 1);
   MAPL(k_maps_whole, SH_ONE, 64);
   HIPCHK(hipGetLastError());
   return FLB_OK;

@@ -2,19 +2,27 @@
 // device and advances them together (flb_server_* in include/foamlbm.h).
 //
 // Jobs queue in arrival order.  Each scheduling round admits queued jobs, in
-// order, while the device bytes of the admitted jobs stay within the pool
-// budget, below the job limit and the running cells below max_cells (enough
-// to fill the GPU: beyond that, running more jobs at once lengthens every job
-// without adding throughput), then advances every running job by the
-// same number of steps -- the chunk, shortened so that no job passes its last
-// step -- with batched launches, one batch per lattice type and storage, so
-// jobs that arrived at different times share every launch.  A job whose
-// steps are done is retired at the end of the round: its final density and
-// statistics are copied to host memory and its device memory is released, so
-// the next round can admit more.  A job's fields are exactly those of the
-// same job run alone.
+// order, while the device bytes of the admitted (resident) jobs stay within
+// the pool budget and below the job limit, then picks the jobs it advances:
+//   FIFO     every resident job; admission also stops once the resident
+//            cells would pass max_cells (enough to fill the GPU: beyond that,
+//            running more jobs at once lengthens every job without adding
+//            throughput);
+//   SHORTEST resident jobs by least remaining work (cells x steps left) while
+//            their cells stay within max_cells, so short jobs are not held
+//            behind long ones; a job passed over kStarveRounds rounds in a row
+//            goes first.
+// The picked jobs advance by the same number of steps -- the chunk, shortened
+// so that no job passes its last step -- with batched launches, one batch per
+// lattice type and storage, so jobs that arrived at different times share
+// every launch.  A job whose steps are done is retired at the end of the
+// round: its final density and statistics are copied to host memory and its
+// device memory is released, so the next round can admit more.  A job's
+// fields are exactly those of the same job run alone.
+#include <algorithm>
 #include <deque>
 #include <map>
+#include <tuple>
 
 #include "batch.hpp"
 
@@ -28,6 +36,7 @@ struct Job {
   std::vector<flb_nucleus> nuc;
   int64_t steps = 0, done = 0;
   int32_t state = FLB_JOB_QUEUED;
+  int idle = 0;  // consecutive rounds this resident job was not advanced
   flb_ctx* c = nullptr;
   size_t bytes = 0;
   std::vector<double> density;
@@ -55,12 +64,16 @@ struct flb_server {
 
 namespace {
 
+constexpr int kStarveRounds = 8;
+
+int64_t job_cells(const Job* j) { return (int64_t)j->p.nx * j->p.ny * j->p.nz; }
+
 int admit(flb_server* s) {
   while (!s->queue.empty() && (int)s->running.size() < s->cfg.max_jobs) {
     Job* j = s->queue.front();
-    const int64_t jc = (int64_t)j->p.nx * j->p.ny * j->p.nz;
+    const int64_t jc = job_cells(j);
     if (s->used + ctx_footprint(&j->p) > (size_t)s->cfg.pool_bytes) break;  // in order: wait for room
-    if (!s->running.empty() && s->cells + jc > s->cfg.max_cells) break;
+    if (s->cfg.policy == FLB_SERVE_FIFO && !s->running.empty() && s->cells + jc > s->cfg.max_cells) break;
     s->queue.pop_front();
     int rc = flb_create(&j->p, s->have_al ? &s->al : nullptr, s->st, &j->c);
     if (!rc) rc = flb_set_nuclei(j->c, j->nuc.data(), (int32_t)j->nuc.size());
@@ -80,10 +93,30 @@ int admit(flb_server* s) {
   return FLB_OK;
 }
 
-// batch views over the running jobs, rebuilt where membership changed
-int sync_views(flb_server* s) {
+// the resident jobs this round advances
+std::vector<Job*> pick(flb_server* s) {
+  if (s->cfg.policy == FLB_SERVE_FIFO) return s->running;
+  std::vector<Job*> order = s->running;
+  auto key = [](const Job* j) {
+    return std::make_tuple(j->idle >= kStarveRounds ? 0 : 1, (double)job_cells(j) * (double)(j->steps - j->done),
+                           j->id);
+  };
+  std::sort(order.begin(), order.end(), [&](const Job* a, const Job* b) { return key(a) < key(b); });
+  std::vector<Job*> act;
+  int64_t cells = 0;
+  for (Job* j : order)
+    if (act.empty() || cells + job_cells(j) <= s->cfg.max_cells) {
+      act.push_back(j);
+      cells += job_cells(j);
+    }
+  std::sort(act.begin(), act.end(), [](const Job* a, const Job* b) { return a->id < b->id; });
+  return act;
+}
+
+// batch views over the jobs of this round, rebuilt where membership changed
+int sync_views(flb_server* s, const std::vector<Job*>& act) {
   std::vector<flb_ctx*> want[2][3];
-  for (Job* j : s->running) want[j->c->D == 2 ? 0 : 1][j->c->p.storage].push_back(j->c);
+  for (Job* j : act) want[j->c->D == 2 ? 0 : 1][j->c->p.storage].push_back(j->c);
   for (int d = 0; d < 2; d++)
     for (int t = 0; t < 3; t++) {
       if (want[d][t] == s->vm[d][t] && (s->view[d][t] || want[d][t].empty())) continue;
@@ -126,6 +159,7 @@ void flb_server_default_config(flb_server_config* cfg) {
   cfg->chunk_steps = 100;
   cfg->graph_steps = 20;
   cfg->max_cells = (int64_t)1 << 24;
+  cfg->policy = FLB_SERVE_FIFO;
 }
 
 int flb_server_create(const flb_server_config* cfg, const flb_allocator* alloc, void* hip_stream,
@@ -138,6 +172,8 @@ int flb_server_create(const flb_server_config* cfg, const flb_allocator* alloc, 
   if (cfg->chunk_steps < 1) return fail(FLB_EINVAL, "chunk_steps must be >= 1");
   if (cfg->graph_steps < 0 || cfg->graph_steps > 4096) return fail(FLB_EINVAL, "graph_steps must be in 0..4096");
   if (cfg->max_cells < 1) return fail(FLB_EINVAL, "max_cells must be >= 1");
+  if (cfg->policy != FLB_SERVE_FIFO && cfg->policy != FLB_SERVE_SHORTEST)
+    return fail(FLB_EINVAL, "policy must be FLB_SERVE_FIFO or FLB_SERVE_SHORTEST");
   if (alloc && (!alloc->alloc || !alloc->free)) return fail(FLB_EINVAL, "allocator needs alloc and free");
   flb_server* s = new (std::nothrow) flb_server();
   if (!s) return fail(FLB_ENOMEM, "host allocation failed");
@@ -189,9 +225,10 @@ int flb_server_pump(flb_server* s, int32_t* n_running, int32_t* n_queued, int64_
     }
   }
   if (!s->running.empty()) {
+    const std::vector<Job*> act = pick(s);
     int64_t r = s->cfg.chunk_steps;
-    for (Job* j : s->running) r = std::min<int64_t>(r, j->steps - j->done);
-    rc = sync_views(s);
+    for (Job* j : act) r = std::min<int64_t>(r, j->steps - j->done);
+    rc = sync_views(s, act);
     if (rc) return rc;
     for (int d = 0; d < 2 && !rc; d++)
       for (int t = 0; t < 3 && !rc; t++)
@@ -200,7 +237,12 @@ int flb_server_pump(flb_server* s, int32_t* n_running, int32_t* n_queued, int64_
     HIPCHK(hipStreamSynchronize(s->st));
     std::vector<Job*> still;
     for (Job* j : s->running) {
-      j->done += r;
+      if (std::find(act.begin(), act.end(), j) != act.end()) {
+        j->done += r;
+        j->idle = 0;
+      } else {
+        j->idle++;
+      }
       if (j->done >= j->steps) retire(s, j);
       else still.push_back(j);
     }

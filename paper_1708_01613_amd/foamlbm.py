@@ -57,10 +57,11 @@ class flb_stats(C.Structure):
 
 class flb_server_config(C.Structure):
     _fields_ = [("pool_bytes", C.c_int64), ("max_jobs", C.c_int32), ("chunk_steps", C.c_int32),
-                ("graph_steps", C.c_int32), ("max_cells", C.c_int64)]
+                ("graph_steps", C.c_int32), ("max_cells", C.c_int64), ("policy", C.c_int32)]
 
 
 FLB_JOB_QUEUED, FLB_JOB_RUNNING, FLB_JOB_DONE, FLB_JOB_FAILED = 0, 1, 2, 3
+FLB_SERVE_FIFO, FLB_SERVE_SHORTEST = 0, 1
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -434,13 +435,13 @@ class Server:
     density and statistics of a finished job."""
 
     def __init__(self, pool_bytes=None, max_jobs=None, chunk_steps=None, graph_steps=None, max_cells=None,
-                 stream=None, use_torch_memory=True):
+                 policy=None, stream=None, use_torch_memory=True):
         import torch
 
         cfg = flb_server_config()
         flb_server_default_config(C.byref(cfg))
         for k, v in (("pool_bytes", pool_bytes), ("max_jobs", max_jobs), ("chunk_steps", chunk_steps),
-                     ("graph_steps", graph_steps), ("max_cells", max_cells)):
+                     ("graph_steps", graph_steps), ("max_cells", max_cells), ("policy", policy)):
             if v is not None:
                 setattr(cfg, k, int(v))
         self.cfg = cfg

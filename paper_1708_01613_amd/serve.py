@@ -8,8 +8,9 @@ single-lattice kernels (flb_step):
   one flb_batch (autotuned tiles, steps replayed from captured HIP graphs).
 * served(trace): jobs arrive at the trace's Poisson times.  Server mode
   submits each job at its arrival time and pumps the job server (admission
-  by device footprint, continuous batching); sequential mode runs the jobs
-  first-come first-served, one at a time.  Completion latency is measured
+  by device footprint, continuous batching, FIFO or shortest-remaining-work
+  scheduling); sequential mode runs the jobs first-come first-served, one at
+  a time.  Completion latency is measured
   from arrival to the round that finished the job.
 
 Aggregate MLUPS = sum over jobs of cells x steps / makespan.
@@ -63,7 +64,12 @@ def ensemble(members, steps, mode="batched", autotune=True, log=None):
     return dict(mode=mode, seconds=dt, MLUPS=total / dt / 1e6)
 
 
-def served(trace, mode="server", pool_bytes=64 << 30, chunk_steps=100, graph_steps=20, log=None):
+def offered_mlups(trace, rate):
+    """Lattice updates per second the trace asks for, in millions."""
+    return rate * float(np.mean([_cells(j["params"]) * j["steps"] for j in trace])) / 1e6
+
+
+def served(trace, mode="server", pool_bytes=64 << 30, chunk_steps=100, graph_steps=20, policy=None, log=None):
     """Run a job trace (list of dicts with arrival, params, nuclei, steps)."""
     import torch
 
@@ -72,7 +78,7 @@ def served(trace, mode="server", pool_bytes=64 << 30, chunk_steps=100, graph_ste
     latency = np.zeros(n)
     work = sum(_cells(j["params"]) * j["steps"] for j in trace)
     if mode == "server":
-        srv = foamlbm.Server(pool_bytes=pool_bytes, chunk_steps=chunk_steps, graph_steps=graph_steps)
+        srv = foamlbm.Server(pool_bytes=pool_bytes, chunk_steps=chunk_steps, graph_steps=graph_steps, policy=policy)
         ids = {}
         nxt = 0
         pending = set()

@@ -28,3 +28,24 @@ def max_rel(a, b):
 
 def vel_err(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def active_links(kind, om):
+    """The oracle's barrier mask (its direction order) without the links whose
+    two ends now have equal alias-root pairs: the links a rupture has removed
+    since the refresh, which the library clears from its mask."""
+    e, _ = lattice(kind)
+    ar = om["alias_root"]
+    a, b = ar[om["owner"]], ar[om["owner2"]]
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    mask = om["mask"]
+    out = np.zeros_like(mask)
+    axes = (0, 1, 2) if kind == 1 else (0, 1)
+    for j in range(1, len(e)):
+        bit = ((mask >> np.uint32(j)) & np.uint32(1)).astype(bool)
+        if not bit.any():
+            continue
+        sh = (-int(e[j][2]), -int(e[j][1]), -int(e[j][0])) if kind == 1 else (-int(e[j][1]), -int(e[j][0]))
+        keep = bit & ((np.roll(lo, sh, axes) != lo) | (np.roll(hi, sh, axes) != hi))
+        out |= keep.astype(np.uint32) << np.uint32(j)
+    return out

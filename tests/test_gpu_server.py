@@ -46,11 +46,16 @@ def _jobs():
     return jobs
 
 
-def test_jobs_in_the_mix_equal_jobs_alone(flb):
+@pytest.mark.parametrize("policy", ["fifo", "shortest"])
+def test_jobs_in_the_mix_equal_jobs_alone(flb, policy):
     jobs = _jobs()
-    _say(f"server with {len(jobs)} mixed jobs, staggered arrivals, small pool")
-    # a pool that holds about three of these jobs at once, so later jobs wait
-    srv = flb.Server(pool_bytes=3 * 40 * 1024 * 1024, chunk_steps=16, graph_steps=8)
+    _say(f"server ({policy}) with {len(jobs)} mixed jobs, staggered arrivals, small pool")
+    # a pool that holds about three of these jobs at once, so later jobs wait;
+    # with shortest-first, a cell budget below the resident cells leaves some
+    # resident jobs out of some rounds
+    pol = flb.FLB_SERVE_FIFO if policy == "fifo" else flb.FLB_SERVE_SHORTEST
+    srv = flb.Server(pool_bytes=3 * 40 * 1024 * 1024, chunk_steps=16, graph_steps=8, policy=pol,
+                     max_cells=None if policy == "fifo" else 20000)
     ids = []
     for k, (p, nuc, steps) in enumerate(jobs):
         ids.append(srv.submit(steps, nuc, **p))
@@ -76,6 +81,31 @@ def test_jobs_in_the_mix_equal_jobs_alone(flb):
         assert np.array_equal(rho, solo.density()), k
         assert stats["step"] == steps
         srv.release(ids[k])
+
+
+def test_shortest_first_finishes_short_jobs_first(flb):
+    # a long job resident first, then short ones: with shortest-first the
+    # short jobs finish while the long one waits, and the long one still ends
+    _say("shortest-first ordering: one long job, four short ones")
+    srv = flb.Server(chunk_steps=10, graph_steps=0, policy=flb.FLB_SERVE_SHORTEST, max_cells=9000)
+    long_id = srv.submit(400, [[40, 40, 0, 8]], lattice=0, storage="f32", nx=90, ny=90, G=-5.5)
+    srv.pump()
+    short = [srv.submit(30, [[20, 20, 0, 6]], lattice=0, storage="f32", nx=60, ny=60, G=-5.5, seed=k)
+             for k in range(4)]
+    finished = []
+    for _ in range(200):
+        running, queued, _ = srv.pump()
+        for jid in [long_id] + short:
+            if jid not in finished and srv.state(jid)[0] == flb.FLB_JOB_DONE:
+                finished.append(jid)
+        if running == 0 and queued == 0:
+            break
+    assert finished[-1] == long_id and sorted(finished[:-1]) == sorted(short)
+    rho, st = srv.result(long_id)
+    solo = flb.Sim(lattice=0, storage="f32", nx=90, ny=90, G=-5.5)
+    solo.set_nuclei([[40, 40, 0, 8]])
+    solo.step(400)
+    assert st["step"] == 400 and np.array_equal(rho, solo.density())
 
 
 def test_job_larger_than_pool_is_refused(flb):
