@@ -160,6 +160,15 @@ enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_BFST, SH_RANK, SH_ONE, SH_LIST,
   (void)bid;                                                                 \
   (void)nbk;
 
+// true unless the previous lane of the wavefront holds the same pair: keeps
+// one lane per run of equal pairs (runs along x are the common case), so the
+// remaining lanes can each do their own union or atomic at once
+__device__ __forceinline__ bool run_head(int a, int b) {
+  const int lane = threadIdx.x & 63;
+  const int pa = __shfl_up(a, 1, 64), pb = __shfl_up(b, 1, 64);
+  return lane == 0 || pa != a || pb != b;
+}
+
 // grid-stride over [0, n) within a lattice's share
 #define FOR_SHARE(i, n) for (long long i = bid * (long long)blockDim.x + threadIdx.x; i < (n); i += (long long)nbk * blockDim.x)
 
@@ -327,18 +336,12 @@ __global__ __launch_bounds__(MAP_NT) void k_cc_cross(MAP_KERNEL_PARAMS) {
         py[p] = __atomic_load_n(&par[y], __ATOMIC_RELAXED);
       }
     }
+    // one union per run of equal root pairs, the runs' unions concurrently
 #pragma unroll
     for (int p = 0; p < NP; p++) {
       const int ra = py[p] >= 0 ? pc : -1, rb = py[p];
-      bool pend = ra >= 0 && ra != rb;
-      unsigned long long mk = __ballot(pend);
-      while (mk) {
-        const int ld = first_lane(mk);
-        const int a0 = __shfl(ra, ld, 64), b0 = __shfl(rb, ld, 64);
-        if (lane == ld) uf_unite(par, a0, b0);
-        if (pend && ra == a0 && rb == b0) pend = false;
-        mk = __ballot(pend);
-      }
+      const bool head = run_head(ra, rb);
+      if (ra >= 0 && ra != rb && head) uf_unite(par, ra, rb);
     }
   }
 }
@@ -539,7 +542,8 @@ __global__ __launch_bounds__(BFS_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int lay
   using T = BfsTile<L>;
   using H = HaloRows<T>;
   constexpr int PER = T::CELLS / BFS_NT;
-  __shared__ uint8_t ld[T::HALO];
+  __shared__ unsigned long long fm[H::NR];
+  __shared__ unsigned fe[H::NR];
   const MapDims d = m.d;
   const int ntx = (d.nx + 63) / 64, ntm = (d.nm + T::TM - 1) / T::TM;
   const int b = (int)bid;
@@ -560,6 +564,7 @@ __global__ __launch_bounds__(BFS_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int lay
   }
   if (!__syncthreads_or(any)) return;  // block-uniform
   const H hr(d, x0);
+  const uint8_t prev = (uint8_t)(layer - 1);
   uint8_t va[H::RPW], ve[H::RPW];
 #pragma unroll
   for (int j = 0; j < H::RPW; j++) {
@@ -570,28 +575,42 @@ __global__ __launch_bounds__(BFS_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int lay
       if (hr.lane < 2) ve[j] = m.dist[base + (unsigned)hr.xe];
     }
   }
+  // frontier bits of the halo rows: bit l of fm[row] is the cell x0 + l,
+  // bits 0 and 1 of fe[row] the cells x0 - 1 and x0 + 64
 #pragma unroll
   for (int j = 0; j < H::RPW; j++) {
-    if (hr.row(j) < H::NR) {
-      uint8_t* rowp = ld + hr.row(j) * T::LX;
-      rowp[1 + hr.lane] = va[j];
-      if (hr.lane < 2) rowp[hr.lane == 0 ? 0 : T::LX - 1] = ve[j];
+    if (hr.row(j) >= H::NR) continue;  // wave-uniform
+    const unsigned long long bm = __ballot(va[j] == prev);
+    const unsigned long long be = __ballot(hr.lane < 2 && ve[j] == prev);
+    if (hr.lane == 0) {
+      fm[hr.row(j)] = bm;
+      fe[hr.row(j)] = (unsigned)be;
     }
   }
   __syncthreads();
-  const uint8_t prev = (uint8_t)(layer - 1);
   const AxisStep sx(x < d.nx ? x : 0, d.nx, 1);
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    if (!open[k]) continue;
-    const int r = (int)(threadIdx.x >> 6) + k * (BFS_NT / 64);
+    const int r = wv + k * (BFS_NT / 64);
     const int lm = r % T::TM, lz = r / T::TM;
-    const int lc = (lx + 1) + T::LX * ((lm + T::HM) + T::LM * (lz + 1));
+    // the frontier words of the 18 neighbour directions, wave-uniform:
+    // bit l of s[i] is the cell reached from lane l's cell along e_i
+    unsigned long long s[L::Q], reach = 0;
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {
+      const int row = (lm + T::HM + L::em[i]) + T::LM * (lz + 1 + L::ez[i]);
+      const unsigned long long w = fm[row];
+      const unsigned e = fe[row];
+      s[i] = L::ex[i] == 0 ? w
+           : L::ex[i] > 0 ? (w >> 1) | ((unsigned long long)((e >> 1) & 1u) << 63)
+                          : (w << 1) | (unsigned long long)(e & 1u);
+      reach |= s[i];
+    }
+    if (!open[k] || !((reach >> lx) & 1ull)) continue;
     unsigned hit = 0;
 #pragma unroll
-    for (int i = 1; i < L::Q; i++)
-      if (ld[lc + L::ex[i] + T::LX * (L::em[i] + T::LM * L::ez[i])] == prev) hit |= 1u << i;
-    if (!hit) continue;
+    for (int i = 1; i < L::Q; i++) hit |= (unsigned)((s[i] >> lx) & 1ull) << i;
     const AxisStep sm(m0 + lm, d.nm, d.nx), sz(z0 + lz, d.nz, d.nx * d.nm);
     int2 o[L::Q];
 #pragma unroll
@@ -636,18 +655,10 @@ static __global__ __launch_bounds__(MAP_NT) void k_alias_carry1(MAP_KERNEL_PARAM
       b = m.label[c];
       a = m.label_old[c];
     }
-    bool pend = b > 0 && a > 0;
+    const bool pend = b > 0 && a > 0;
     const int r = pend ? uf_root(m.alias_old, a) : 0;
-    unsigned long long mk = __ballot(pend);
-    while (mk) {
-      const int ld = first_lane(mk);
-      const int r0 = __shfl(r, ld, 64);
-      const bool mine = pend && r == r0;
-      const int bmin = wave_min_i32(mine ? b : 0x7fffffff);
-      if (lane == ld && __atomic_load_n(&m.rep[r0], __ATOMIC_RELAXED) > bmin) atomicMin(&m.rep[r0], bmin);
-      if (mine) pend = false;
-      mk = __ballot(pend);
-    }
+    // one atomic per run of equal (root, label), the runs' atomics at once
+    if (run_head(r, b) && pend && __atomic_load_n(&m.rep[r], __ATOMIC_RELAXED) > b) atomicMin(&m.rep[r], b);
   }
 }
 
@@ -664,15 +675,8 @@ static __global__ __launch_bounds__(MAP_NT) void k_alias_carry2(MAP_KERNEL_PARAM
       a = m.label_old[c];
     }
     const int r = (b > 0 && a > 0) ? m.rep[uf_root(m.alias_old, a)] : 0;
-    bool pend = b > 0 && a > 0 && r != b;
-    unsigned long long mk = __ballot(pend);
-    while (mk) {
-      const int ld = first_lane(mk);
-      const int b0 = __shfl(b, ld, 64), r0 = __shfl(r, ld, 64);
-      if (lane == ld) uf_unite(m.alias, b0, r0);
-      if (pend && b == b0 && r == r0) pend = false;
-      mk = __ballot(pend);
-    }
+    const bool pend = b > 0 && a > 0 && r != b;
+    if (run_head(b, r) && pend) uf_unite(m.alias, b, r);
   }
 }
 
