@@ -309,7 +309,7 @@ typedef struct {
 enum { FLB_SERVE_FIFO = 0, FLB_SERVE_SHORTEST = 1 };
 enum { FLB_JOB_QUEUED = 0, FLB_JOB_RUNNING = 1, FLB_JOB_DONE = 2, FLB_JOB_FAILED = 3 };
 
-/* pool 64 GiB, 256 jobs, chunks of 100 steps, graphs of 20 steps, 2^24 cells,
+/* pool 64 GiB, 256 jobs, chunks of 100 steps, graphs of 20 steps, 2^22 cells,
  * FLB_SERVE_FIFO */
 void flb_server_default_config(flb_server_config* cfg);
 int flb_server_create(const flb_server_config* cfg, const flb_allocator* alloc, void* hip_stream,

@@ -75,6 +75,7 @@ struct flb_batch {
   int* ffirst = nullptr;
   int fblk = 0;
   flb_rt::MapSet fms;  // film refresh of the film members, one launch per map kernel
+  flb_rt::Fork fork;   // side stream of the refresh
   bool dirty = true;
   // graphs
   int graph_steps = 16;
@@ -166,9 +167,11 @@ inline int rebuild(flb_batch* b) {
     HIPCHK(hipMemcpyAsync(b->ffirst, ffirst.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, b->st));
   }
   if (nf) {
+    int rc = b->fork.init();  // outside any graph capture
+    if (rc) return rc;
     std::vector<MapArgs> margs;
     for (int k : b->film) margs.push_back(map_args(b->m[k], false, GAS_POP));
-    int rc = mapset_build(b->fms, margs, b->D, [b](size_t bytes) { return b->dalloc(bytes); }, b->st);
+    rc = mapset_build(b->fms, margs, b->D, [b](size_t bytes) { return b->dalloc(bytes); }, b->st);
     if (rc) return rc;
   }
   HIPCHK(hipStreamSynchronize(b->st));
@@ -187,7 +190,8 @@ int batch_one_step(flb_batch* b) {
   bool due = false;
   for (int k : b->film) due = due || b->m[k]->launched % b->m[k]->p.k_own == 0;
   if (due) {
-    int rc = map_pipeline<L, S>(b->fms, b->st, GAS_POP, true);
+    int rc = b->fork.init();
+    if (!rc) rc = map_pipeline<L, S>(b->fms, b->st, GAS_POP, true, &b->fork);
     if (rc) return rc;
   }
   const int n = (int)b->m.size();

@@ -346,24 +346,23 @@ __global__ __launch_bounds__(MAP_NT) void k_cc_cross(MAP_KERNEL_PARAMS) {
   }
 }
 
-static __global__ __launch_bounds__(MAP_NT) void k_cc_compress(MAP_KERNEL_PARAMS) {
-  MAP_MEMBER
-  if (!map_due(m)) return;
-  FOR_SHARE(c, m.d.N) {
-    if (m.par[c] < 0) continue;
-    m.par[c] = uf_find_live(m.par, (int)c);
-  }
-}
-
 // ---- canonical ranks: count roots per block, scan, write labels ----
 constexpr int RANK_BLOCK = 1024;
 constexpr int FW_BLOCK = 1024;  // flag words per workgroup (flagged-list build)
 
-static __global__ __launch_bounds__(RANK_BLOCK) void k_count_roots(MAP_KERNEL_PARAMS) {
+// Every gas cell points at its component's root (path compression: a
+// concurrent reader sees either the old parent or the root, both lead to the
+// root), and each block of RANK_BLOCK cells counts the roots it holds.
+static __global__ __launch_bounds__(RANK_BLOCK) void k_cc_compress(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m)) return;
   const long long c = bid * (long long)RANK_BLOCK + threadIdx.x;
-  const int is_root = (c < m.d.N && m.par[c] == (int)c) ? 1 : 0;
+  int is_root = 0;
+  if (c < m.d.N && m.par[c] >= 0) {
+    const int r = uf_find_live(m.par, (int)c);
+    m.par[c] = r;
+    is_root = r == (int)c;
+  }
   __shared__ int s[RANK_BLOCK / 64];
   const unsigned long long bal = __ballot(is_root);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = __popcll(bal);

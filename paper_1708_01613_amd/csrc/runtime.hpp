@@ -127,6 +127,37 @@ inline size_t ctx_footprint(const flb_params* p) {
   return t;
 }
 
+// A second stream for work of a refresh that does not depend on the work
+// before it in the main stream: the alias carry runs beside the BFS layers
+// (both only read the new labels).  Joined with events, so it also works
+// inside a captured graph.  Default priority, like every stream here.
+struct Fork {
+  hipStream_t side = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  int init() {
+    if (side) return FLB_OK;
+    if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+      release();
+      return fail(FLB_EHIP, "creating the refresh side stream failed");
+    }
+    return FLB_OK;
+  }
+  void release() {
+    if (side) (void)hipStreamSynchronize(side);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (side) (void)hipStreamDestroy(side);
+    side = nullptr;
+    a = b = nullptr;
+  }
+  Fork() = default;
+  Fork(const Fork&) = delete;
+  Fork& operator=(const Fork&) = delete;
+  ~Fork() { release(); }
+};
+
 // A MapSet is a device table of MapArgs plus, per decomposition, the
 // workgroup ranges of its lattices.  Tables of one lattice serve a context;
 // a batch builds one over its film members.
@@ -181,6 +212,7 @@ struct flb_ctx {
   // map-kernel tables: film refresh from the state or the rho array, label
   // queries from the state or a field
   flb_rt::MapSet ms_pop, ms_rho, qs_pop, qs_field, ms_import;
+  flb_rt::Fork fork;  // side stream of the refresh
   bool ms_ready = false;
   // query scratch
   double* qd = nullptr;    // (1 + 3) * N doubles
@@ -398,26 +430,36 @@ int map_masks(const MapSet& s, hipStream_t st) {
 // refresh also owners and distances, alias carry, barrier masks, the list of
 // flagged cells and its density marks.  No synchronisation; capturable.
 template <class L, class S>
-int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh) {
+int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh, const Fork* fk = nullptr) {
   if (refresh) MAPL(k_keep_old, SH_CELLS, MAP_NT);
   if (src == GAS_POP) MAPL((k_gas<L, S, GAS_POP>), SH_SEG, MAP_NT);
   else if (src == GAS_FIELD) MAPL((k_gas<L, S, GAS_FIELD>), SH_CELLS, MAP_NT);
   else MAPL((k_gas<L, S, GAS_RHO>), SH_CELLS, MAP_NT);
   MAPL((k_cc_local<L>), SH_CCT, CC_NT);
   MAPL((k_cc_cross<L>), SH_SEG, MAP_NT);
-  MAPL(k_cc_compress, SH_CELLS, MAP_NT);
-  MAPL(k_count_roots, SH_RANK, RANK_BLOCK);
+  MAPL(k_cc_compress, SH_RANK, RANK_BLOCK);
   MAPL(k_scan_counts, SH_ONE, 1024, 0);
   MAPL(k_write_rank, SH_RANK, RANK_BLOCK);
   MAPL(k_write_labels, SH_CELLS, MAP_NT);
   if (refresh) {
+    const bool fork = fk && fk->side;
+    if (fork) {
+      HIPCHK(hipEventRecord(fk->a, st));
+      HIPCHK(hipStreamWaitEvent(fk->side, fk->a, 0));
+    }
+    {
+      hipStream_t st_main = st;
+      hipStream_t st = fork ? fk->side : st_main;  // the alias carry, beside the BFS
+      MAPL(k_alias_reset, SH_CELLS, MAP_NT);
+      MAPL(k_alias_carry1, SH_CELLS, MAP_NT);
+      MAPL(k_alias_carry2, SH_CELLS, MAP_NT);
+      MAPL(k_alias_compress, SH_CELLS, MAP_NT);
+      if (fork) HIPCHK(hipEventRecord(fk->b, st));
+    }
     MAPL(k_owner_init, SH_CELLS, MAP_NT);
     for (int layer = 1; layer <= std::min(s.max_zone - 1, bfs_hot_layers(s.max_zone)); layer++)
       MAPL((k_bfs_layer<L>), SH_BFST, BFS_NT, layer, 0);
-    MAPL(k_alias_reset, SH_CELLS, MAP_NT);
-    MAPL(k_alias_carry1, SH_CELLS, MAP_NT);
-    MAPL(k_alias_carry2, SH_CELLS, MAP_NT);
-    MAPL(k_alias_compress, SH_CELLS, MAP_NT);
+    if (fork) HIPCHK(hipStreamWaitEvent(st, fk->b, 0));
   }
   if (refresh) return map_masks<L>(s, st);
   HIPCHK(hipGetLastError());
@@ -469,7 +511,9 @@ template <class L, class S>
 int refresh_maps(flb_ctx* c, bool from_rho) {
   int rc = ctx_mapsets(c);
   if (rc) return rc;
-  return map_pipeline<L, S>(from_rho ? c->ms_rho : c->ms_pop, c->st, from_rho ? GAS_RHO : GAS_POP, true);
+  rc = c->fork.init();
+  if (rc) return rc;
+  return map_pipeline<L, S>(from_rho ? c->ms_rho : c->ms_pop, c->st, from_rho ? GAS_RHO : GAS_POP, true, &c->fork);
 }
 
 // ---- the BFS layers a refresh defers, before owner / dist are read ----

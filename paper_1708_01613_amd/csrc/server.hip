@@ -158,7 +158,7 @@ void flb_server_default_config(flb_server_config* cfg) {
   cfg->max_jobs = 256;
   cfg->chunk_steps = 100;
   cfg->graph_steps = 20;
-  cfg->max_cells = (int64_t)1 << 24;
+  cfg->max_cells = (int64_t)1 << 22;
   cfg->policy = FLB_SERVE_FIFO;
 }
 

@@ -8,6 +8,7 @@ PyTorch.  Importing this module fails loudly when the library is not built.
 import ctypes as C
 import math
 import os
+import sys
 
 import numpy as np
 
@@ -74,6 +75,11 @@ class flb_allocator(C.Structure):
 if not os.path.exists(LIBPATH):
     raise ImportError(f"libfoamlbm.so is not built at {LIBPATH}; run __graft_entry__.build() "
                       "(or python paper_1708_01613_amd/build.py)")
+# PyTorch ships its own HIP runtime under the same soname: loading torch
+# first makes the library bind to that one instance, so device memory and
+# streams from torch are valid in the library's calls
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIBPATH)
 
 _D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -172,7 +178,8 @@ def _torch_allocator(device_index):
         try:
             return torch.cuda.caching_allocator_alloc(int(nbytes), device_index,
                                                       torch.cuda.current_stream(device_index))
-        except Exception:
+        except Exception as exc:  # the library reports FLB_ENOMEM; say why
+            print(f"foamlbm: device allocation of {int(nbytes)} bytes failed: {exc}", file=sys.stderr, flush=True)
             return None
 
     def _free(ptr, user):

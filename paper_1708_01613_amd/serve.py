@@ -69,7 +69,8 @@ def offered_mlups(trace, rate):
     return rate * float(np.mean([_cells(j["params"]) * j["steps"] for j in trace])) / 1e6
 
 
-def served(trace, mode="server", pool_bytes=64 << 30, chunk_steps=100, graph_steps=20, policy=None, log=None):
+def served(trace, mode="server", pool_bytes=64 << 30, chunk_steps=100, graph_steps=20, policy=None, max_cells=None,
+           log=None):
     """Run a job trace (list of dicts with arrival, params, nuclei, steps)."""
     import torch
 
@@ -78,7 +79,8 @@ def served(trace, mode="server", pool_bytes=64 << 30, chunk_steps=100, graph_ste
     latency = np.zeros(n)
     work = sum(_cells(j["params"]) * j["steps"] for j in trace)
     if mode == "server":
-        srv = foamlbm.Server(pool_bytes=pool_bytes, chunk_steps=chunk_steps, graph_steps=graph_steps, policy=policy)
+        srv = foamlbm.Server(pool_bytes=pool_bytes, chunk_steps=chunk_steps, graph_steps=graph_steps, policy=policy,
+                             max_cells=max_cells)
         ids = {}
         nxt = 0
         pending = set()
@@ -126,3 +128,42 @@ def served(trace, mode="server", pool_bytes=64 << 30, chunk_steps=100, graph_ste
     return dict(mode=mode, jobs=n, makespan_s=makespan, MLUPS=work / makespan / 1e6,
                 p50_s=float(np.percentile(latency, 50)), p99_s=float(np.percentile(latency, 99)),
                 mean_s=float(latency.mean()))
+
+
+def main(argv=None):
+    """Command line: one batched-ensemble or served-stream measurement, one
+    JSON line (used for the profiles of these workloads)."""
+    import argparse
+    import json
+
+    from . import inputs
+
+    ap = argparse.ArgumentParser(prog="python -m paper_1708_01613_amd.serve")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    e = sub.add_parser("ensemble")
+    e.add_argument("--steps", type=int, default=1000)
+    e.add_argument("--mode", choices=("batched", "sequential"), default="batched")
+    s = sub.add_parser("served")
+    s.add_argument("--jobs", type=int, default=48)
+    s.add_argument("--steps", type=int, default=1000)
+    s.add_argument("--d3-fraction", type=float, default=0.5)
+    s.add_argument("--policy", choices=("fifo", "shortest", "sequential"), default="fifo")
+    s.add_argument("--max-cells", type=int, default=None)
+    a = ap.parse_args(argv)
+    if a.cmd == "ensemble":
+        members, _ = inputs.config_ensemble()
+        r = ensemble(members, a.steps, mode=a.mode)
+    else:
+        trace = inputs.arrival_trace(n_requests=a.jobs, d3_fraction=a.d3_fraction)
+        for j in trace:
+            j["steps"] = a.steps
+        if a.policy == "sequential":
+            r = served(trace, mode="sequential")
+        else:
+            pol = foamlbm.FLB_SERVE_FIFO if a.policy == "fifo" else foamlbm.FLB_SERVE_SHORTEST
+            r = served(trace, mode="server", policy=pol, max_cells=a.max_cells)
+    print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()
