@@ -91,6 +91,8 @@ typedef struct {
   double* f;     /* populations f[i*N + c], post-streaming state f^n */
   double* fpost; /* post-collision scratch */
   double* rho;
+  double* rho_prev; /* density of the state that entered the last step */
+  int32_t have_prev; /* rho_prev holds it (cleared when the state is replaced) */
   double* psi;
   double* force; /* 3*N, last computed force */
   /* film maps (as of the last refresh) */
@@ -203,6 +205,7 @@ or_sim* or_create(const or_params* p) {
   s->f = (double*)calloc((size_t)s->Q * N, sizeof(double));
   s->fpost = (double*)calloc((size_t)s->Q * N, sizeof(double));
   s->rho = (double*)calloc(N, sizeof(double));
+  s->rho_prev = (double*)calloc(N, sizeof(double));
   s->psi = (double*)calloc(N, sizeof(double));
   s->force = (double*)calloc(3 * (size_t)N, sizeof(double));
   s->label = (int32_t*)calloc(N, sizeof(int32_t));
@@ -215,7 +218,7 @@ or_sim* or_create(const or_params* p) {
   s->alias_old = (int32_t*)calloc(N + 2, sizeof(int32_t));
   s->evcap = 1024;
   s->ev = (int64_t*)calloc(3 * (size_t)s->evcap, sizeof(int64_t));
-  if (!s->f || !s->fpost || !s->rho || !s->psi || !s->force || !s->label || !s->label_old ||
+  if (!s->f || !s->fpost || !s->rho || !s->rho_prev || !s->psi || !s->force || !s->label || !s->label_old ||
       !s->owner || !s->owner2 || !s->dist || !s->mask || !s->alias || !s->alias_old || !s->ev) {
     or_destroy(s);
     return NULL;
@@ -226,7 +229,7 @@ or_sim* or_create(const or_params* p) {
 
 void or_destroy(or_sim* s) {
   if (!s) return;
-  free(s->f); free(s->fpost); free(s->rho); free(s->psi); free(s->force);
+  free(s->f); free(s->fpost); free(s->rho); free(s->rho_prev); free(s->psi); free(s->force);
   free(s->label); free(s->label_old); free(s->owner); free(s->owner2); free(s->dist); free(s->mask);
   free(s->alias); free(s->alias_old); free(s->ev);
   free(s);
@@ -299,6 +302,7 @@ int or_set_nuclei(or_sim* s, const double* nuc, int32_t n) {
     for (int i = 0; i < s->Q; i++) s->f[(long)i * N + c] = s->w[i] * rho;
   }
   free(inside);
+  s->have_prev = 0;
   s->step = 0;
   s->stopped = 0;
   s->nev = 0;
@@ -313,6 +317,7 @@ int or_set_nuclei(or_sim* s, const double* nuc, int32_t n) {
 
 void or_set_populations(or_sim* s, const double* f) {
   memcpy(s->f, f, (size_t)s->Q * s->N * sizeof(double));
+  s->have_prev = 0;
 }
 void or_get_populations(const or_sim* s, double* f) {
   memcpy(f, s->f, (size_t)s->Q * s->N * sizeof(double));
@@ -426,14 +431,14 @@ static int roots_differ(const or_sim* s, long c, long y) {
   return a0 != b0 || a1 != b1;
 }
 
-static void refresh_maps(or_sim* s) {
+static void refresh_maps(or_sim* s, const double* rho) {
   long N = s->N;
   /* keep the previous labels and aliases for the alias carry */
   int32_t* t = s->label_old; s->label_old = s->label; s->label = t;
   t = s->alias_old; s->alias_old = s->alias; s->alias = t;
   s->nb_old = s->maps_valid ? s->nb : 0;
 
-  s->nb = label_field(s, s->rho, s->p.rho_th, s->label);
+  s->nb = label_field(s, rho, s->p.rho_th, s->label);
   owner_dist(s, s->label, s->p.zone_width, s->owner, s->owner2, s->dist);
 
   /* alias carry: new bubbles whose gas cells overlap old components of one */
@@ -518,7 +523,10 @@ static void one_step(or_sim* s) {
   double* jz = jy + N;
 
   compute_moments(s, jx, jy, jz);                       /* 1, 2 */
-  if (p->film_on && s->step % p->k_own == 0) refresh_maps(s); /* 3 */
+  /* 3: maps refreshed at steps n = 0 (mod k_own) from the density of the  */
+  /* previous step, rho^(n-1), when that step was taken from the current  */
+  /* state; from rho^n at n = 0 and after the state was replaced (R12)     */
+  if (p->film_on && s->step % p->k_own == 0) refresh_maps(s, s->have_prev ? s->rho_prev : s->rho);
   compute_force(s, p->film_on);                         /* 4 */
 
 #pragma omp parallel for schedule(static)
@@ -576,6 +584,8 @@ static void one_step(or_sim* s) {
     for (int i = 0; i < Q; i++) s->f[(long)i * N + c] = s->fpost[(long)i * N + nbr(s, c, i, -1)];
 
   free(jx);
+  memcpy(s->rho_prev, s->rho, N * sizeof(double));
+  s->have_prev = 1;
   s->step++;
   if (any_rupture && p->on_rupture == 1) s->stopped = 1;
 }

@@ -312,3 +312,40 @@ def test_barrier_force_substitution(mode):
     assert np.abs(F - ref).max() < 1e-13
     Fplain = s.force(with_film=0)
     assert np.abs(F - Fplain).max() > 1e-3
+
+
+@pytest.mark.parametrize("kind,dims", [(0, (1, 40, 48)), (1, (14, 15, 16))])
+def test_refresh_labels_density_of_previous_step(kind, dims):
+    # R12: the maps refreshed at step n > 0 (n = 0 mod k_own) label the gas of
+    # the density that entered step n - 1; at n = 0, and after the state was
+    # replaced, the density of the current state
+    nz, ny, nx = dims
+    rng = np.random.default_rng(3 + kind)
+    nuc = [[rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz) if kind else 0.0, rng.uniform(2.5, 4.5)]
+           for _ in range(6)]
+    k = 3
+    s = OracleSim(lattice=kind, nx=nx, ny=ny, nz=nz, G=-5.5, rho_liquid=2.3, rho_gas=0.11, film_on=1, k_own=k,
+                  zone_width=6, rupture_warmup=10 ** 6, seed=2)
+    s.set_nuclei(nuc)
+    s.step(1)
+    gas0 = (s.maps()["label"] > 0).reshape(dims)
+    s.set_nuclei(nuc)
+    assert np.array_equal(gas0, s.density().reshape(dims) < math.log(2.0))  # step 0: current state
+    s.step(k - 1)
+    prev = s.density().reshape(dims)  # enters step k - 1
+    s.step(1)
+    cur = s.density().reshape(dims)  # enters step k, at which the maps are refreshed
+    s.step(1)
+    lab = s.maps()["label"].reshape(dims)
+    ref, nb = bf.bfs_labels(prev < math.log(2.0), kind)
+    assert np.array_equal(lab, ref) and nb > 1
+    assert not np.array_equal(prev < math.log(2.0), cur < math.log(2.0))  # the two readings differ here
+    # after the state is replaced the next refresh labels the new state
+    s2 = OracleSim(lattice=kind, nx=nx, ny=ny, nz=nz, G=-5.5, rho_liquid=2.3, rho_gas=0.11, film_on=1, k_own=k,
+                   zone_width=6, rupture_warmup=10 ** 6, seed=2)
+    s2.set_nuclei(nuc)
+    s2.step(k)
+    s2.set_populations(s2.populations())
+    s2.step(1)
+    ref2, _ = bf.bfs_labels(cur < math.log(2.0), kind)
+    assert np.array_equal(s2.maps()["label"].reshape(dims), ref2)
