@@ -87,7 +87,8 @@ typedef struct {
   double noise_amp;      /* initial uniform noise amplitude a: rho += a (2U - 1) */
   uint64_t seed;         /* seed of the counter-based noise */
   int32_t film_on;       /* 1: film barrier and rupture test on */
-  int32_t k_own;         /* film maps are rebuilt before every step n with n % k_own == 0 (>= 1) */
+  int32_t k_own;         /* film maps are rebuilt before every step n with n % k_own == 0 (>= 1),
+                            from the density that entered step n - 1 (step 0: the initial one) */
   int32_t zone_width;    /* largest film thickness (lattice links) that carries a barrier, 1..15 */
   double rho_th;         /* gas iff rho < rho_th (default ln 2, the critical density) */
   int32_t psi_bar_mode;  /* psi on barrier links: 0 = psi(rho_liquid), 1 = psi(x) */
@@ -135,7 +136,9 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
 int flb_set_nuclei(flb_ctx* ctx, const flb_nucleus* nuc, int32_t n);
 
 /* Advance nsteps >= 0 steps (asynchronous on the context stream).  Film maps
- * are rebuilt before each step n with n % k_own == 0.  After a rupture with
+ * are rebuilt before each step n with n % k_own == 0 (from the density that
+ * entered step n - 1, or the current one at n = 0 and after flb_set_populations
+ * or flb_set_nuclei).  After a rupture with
  * on_rupture == 1 the remaining steps are no-ops. */
 int flb_step(flb_ctx* ctx, int64_t nsteps);
 

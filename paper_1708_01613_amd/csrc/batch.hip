@@ -117,7 +117,12 @@ int flb_batch_autotune(flb_batch* b, int32_t reps, double* best_ms) {
   const int n = (int)b->m.size();
   std::vector<void*> scratch(n, nullptr);
   bool ok = true;
-  for (int k = 0; k < n && ok; k++) ok = (scratch[k] = b->dalloc(b->m[k]->fbytes)) != nullptr;
+  // per member: populations, then densities (trials keep the member's own)
+  for (int k = 0; k < n && ok; k++) {
+    const flb_ctx* c = b->m[k];
+    const size_t tsz = c->p.storage == FLB_F64 ? 8 : 4;
+    ok = (scratch[k] = b->dalloc(c->fbytes + tsz * (size_t)c->N)) != nullptr;
+  }
   Ctl* sctl = ok ? (Ctl*)b->dalloc(sizeof(Ctl) * n) : nullptr;
   int rc = (ok && sctl) ? FLB_OK : fail(FLB_ENOMEM, "autotune scratch allocation failed");
   const long long targets[] = {256, 512, 1024, 2048, 4096, 8192};

@@ -170,7 +170,7 @@ inline int rebuild(flb_batch* b) {
     int rc = b->fork.init();  // outside any graph capture
     if (rc) return rc;
     std::vector<MapArgs> margs;
-    for (int k : b->film) margs.push_back(map_args(b->m[k], false, GAS_POP));
+    for (int k : b->film) margs.push_back(map_args(b->m[k], false, GAS_AUTO));
     rc = mapset_build(b->fms, margs, b->D, [b](size_t bytes) { return b->dalloc(bytes); }, b->st);
     if (rc) return rc;
   }
@@ -191,7 +191,7 @@ int batch_one_step(flb_batch* b) {
   for (int k : b->film) due = due || b->m[k]->launched % b->m[k]->p.k_own == 0;
   if (due) {
     int rc = b->fork.init();
-    if (!rc) rc = map_pipeline<L, S>(b->fms, b->st, GAS_POP, true, &b->fork);
+    if (!rc) rc = map_pipeline<L, S>(b->fms, b->st, GAS_AUTO, true, &b->fork);
     if (rc) return rc;
   }
   const int n = (int)b->m.size();
@@ -297,6 +297,8 @@ inline int time_trial(flb_batch* b, int reps, void* const* scratch, Ctl* sctl, f
     const int cur = (int)(h.steps & 1);  // the buffer the kernel will read
     tab[k].buf[cur] = c->f[cur];
     tab[k].buf[1 - cur] = scratch[k];
+    tab[k].rho = (char*)scratch[k] + c->fbytes;
+    tab[k].gas_k = 0;
     tab[k].ctl = sctl + k;
     HIPCHK(hipMemcpyAsync(sctl + k, c->ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, b->st));
   }

@@ -118,7 +118,7 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
       hipMemsetAsync(c->qctl, 0, sizeof(Ctl), c->st) != hipSuccess ||
       (p->film_on && hipMemsetAsync(c->flag, 0, (size_t)c->N, c->st) != hipSuccess) ||
       (p->film_on && hipMemsetAsync(c->mask, 0, sizeof(uint32_t) * (size_t)c->N, c->st) != hipSuccess) ||
-      hipStreamSynchronize(c->st) != hipSuccess) {
+      forget_rho(c) != FLB_OK || hipStreamSynchronize(c->st) != hipSuccess) {
     c->dfree_all();
     delete c;
     return fail(FLB_EHIP, "initialising device state failed");
@@ -147,6 +147,7 @@ int flb_set_nuclei(flb_ctx* c, const flb_nucleus* nuc, int32_t n) {
     HIPCHK(hipMemcpyAsync(dn, nuc, sizeof(double4) * (size_t)n, hipMemcpyHostToDevice, c->st));
   }
   HIPCHK(hipMemsetAsync(c->ctl, 0, sizeof(Ctl), c->st));
+  if (forget_rho(c)) return FLB_EHIP;
   const int B = 256, g = grid_for(c->N, B);
   hipLaunchKernelGGL(k_init_density, dim3(g), dim3(B), 0, c->st, c->qd, c->p.nx, c->p.ny, c->p.nz, c->N, dn, n,
                      c->p.rho_liquid, c->p.rho_gas, c->p.noise_amp, (unsigned long long)c->p.seed);
@@ -226,7 +227,10 @@ int flb_autotune(flb_ctx* c, int32_t reps, double* best_ms) {
   int rc = read_ctl(c, &h);
   if (rc) return rc;
   const int cur = (int)(h.steps & 1);
-  void* scratch = c->dalloc(c->fbytes);
+  // trials write their populations to a scratch buffer and their densities
+  // after it, so the state and the densities kept for the next refresh stay
+  const size_t tsz = c->p.storage == FLB_F64 ? 8 : 4;
+  void* scratch = c->dalloc(c->fbytes + tsz * (size_t)c->N);
   Ctl* sctl = (Ctl*)c->dalloc(sizeof(Ctl));
   if (!scratch || !sctl) {
     c->dfree(scratch);
@@ -258,6 +262,8 @@ int flb_autotune(flb_ctx* c, int32_t reps, double* best_ms) {
         StepArgs a = step_args(c);
         a.buf[cur] = c->f[cur];
         a.buf[1 - cur] = scratch;
+        a.rho = (char*)scratch + c->fbytes;
+        a.gas_k = 0;
         a.ctl = sctl;
         e = hipMemcpyAsync(sctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, c->st);
         const StepFn fn = c->tcfg().fn[c->p.storage], coll = c->tcfg().coll[c->p.storage];
@@ -474,6 +480,7 @@ int flb_set_populations(flb_ctx* c, const double* in, size_t n) {
   if (!tmp) return fail(FLB_ENOMEM, "population scratch allocation failed");
   hipError_t e = hipMemcpyAsync(tmp, in, sizeof(double) * n, hipMemcpyHostToDevice, c->st);
   if (e == hipSuccess) rc = FLB_DISPATCH(c, do_pack, c, tmp, 1, (int)(h.steps & 1));
+  if (e == hipSuccess && !rc) rc = forget_rho(c);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   c->dfree(tmp);
   if (e != hipSuccess) return fail(FLB_EHIP, "population import: %s", hipGetErrorString(e));
@@ -547,9 +554,10 @@ struct CkptArrays {
   CkptArrays(flb_ctx* c, size_t n_events, size_t n_flagged) {
     if (!c->p.film_on) return;
     const size_t N = (size_t)c->N;
+    const size_t tsz = c->p.storage == FLB_F64 ? 8 : 4;
     v = {{c->label, 4 * N},       {c->alias, 4 * (N + 1)}, {c->own, 8 * N},
          {c->dist, N},            {c->flag, N},            {c->mask, 4 * N},
-         {c->flist, 4 * n_flagged}, {c->events, 32 * n_events}};
+         {c->flist, 4 * n_flagged}, {c->events, 32 * n_events}, {c->rho, tsz * N}};
   }
 };
 
@@ -568,7 +576,7 @@ int flb_save(flb_ctx* c, const char* path) {
   CkptHeader hd;
   memset(&hd, 0, sizeof hd);
   memcpy(hd.magic, kCkptMagic, 8);
-  hd.version = 1;
+  hd.version = 2;
   hd.params_size = sizeof(flb_params);
   hd.p = c->p;
   hd.ctl = h;
@@ -593,7 +601,7 @@ int flb_load(flb_ctx* c, const char* path) {
   if (!fp) return fail(FLB_EINVAL, "cannot open %s", path);
   CkptHeader hd;
   int rc = fread(&hd, sizeof hd, 1, fp) == 1 ? FLB_OK : fail(FLB_EINVAL, "not a checkpoint");
-  if (!rc && (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1 || hd.params_size != sizeof(flb_params)))
+  if (!rc && (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 2 || hd.params_size != sizeof(flb_params)))
     rc = fail(FLB_EINVAL, "not a checkpoint of this library version");
   if (!rc && (memcmp(&hd.p, &c->p, sizeof(flb_params)) != 0 || hd.fbytes != c->fbytes || hd.N != (uint64_t)c->N))
     rc = fail(FLB_EINVAL, "checkpoint parameters differ from the context's");

@@ -133,6 +133,7 @@ struct Ctl {
   int maps_seen;        // 1 once a refresh has built maps (the next one carries aliases)
   int nb_old;           // labels of the previous refresh, during a refresh
   int maps_partial;     // 1 while owner/dist stop at the layers the masks need
+  long long rho_step;   // the step whose entering densities the rho array holds for every cell (-1: none)
   double mass, mom[3];  // FP64 totals of the state entering the last step
 };
 

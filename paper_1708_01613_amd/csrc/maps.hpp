@@ -111,7 +111,9 @@ __device__ __forceinline__ int first_lane(unsigned long long m) { return __built
 
 
 // ---- per-lattice arguments of the map kernels ----
-enum GasSrc { GAS_POP = 0, GAS_FIELD = 1, GAS_RHO = 2 };
+// GAS_AUTO: the densities a step kernel stored for the refresh (the rho
+// array, when it holds the step before this one), else the stored state
+enum GasSrc { GAS_POP = 0, GAS_FIELD = 1, GAS_RHO = 2, GAS_AUTO = 3 };
 
 struct MapArgs {
   Ctl* ctl;               // gate: run control of the lattice (or a zeroed query control)
@@ -177,7 +179,16 @@ template <class L, class S, int SRC>
 __global__ __launch_bounds__(MAP_NT) void k_gas(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m)) return;
-  if constexpr (SRC == GAS_POP) {
+  if (SRC == GAS_AUTO && m.sctl->steps > 0 && m.sctl->rho_step == m.sctl->steps - 1) {
+    // the densities the previous step stored for this refresh
+    for_cells<false>(
+        m.d,
+        [&](const SegCell& q) {
+          const double r = (double)((const typename S::ct*)m.src)[q.c];
+          m.par[q.c] = r < m.rho_th ? (int)q.c : -1;
+        },
+        bid, nbk);
+  } else if constexpr (SRC == GAS_POP || SRC == GAS_AUTO) {
     // density of the stored state, summed in FP64
     const void* src = (m.sctl->steps & 1) ? m.b1 : m.b0;
     for_cells<false>(

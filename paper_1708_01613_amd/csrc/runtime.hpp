@@ -211,7 +211,7 @@ struct flb_ctx {
   unsigned ev_cap = 1u << 16;
   // map-kernel tables: film refresh from the state or the rho array, label
   // queries from the state or a field
-  flb_rt::MapSet ms_pop, ms_rho, qs_pop, qs_field, ms_import;
+  flb_rt::MapSet ms_refresh, qs_pop, qs_field, ms_import;
   flb_rt::Fork fork;  // side stream of the refresh
   bool ms_ready = false;
   // query scratch
@@ -317,6 +317,7 @@ inline StepArgs step_args(flb_ctx* c) {
   a.rupture_warmup = c->p.rupture_warmup;
   a.on_rupture = c->p.on_rupture;
   a.rupture_filter = c->p.rupture_filter;
+  a.gas_k = c->p.film_on ? c->p.k_own : 0;
   a.flag = c->flag;
   a.mask = c->mask;
   a.flist = c->flist;
@@ -383,7 +384,7 @@ inline MapArgs map_args(flb_ctx* c, bool query, int src) {
   a.geo = c->geo;
   a.b0 = c->f[0];
   a.b1 = c->f[1];
-  a.src = src == GAS_FIELD ? (const void*)c->qd : (src == GAS_RHO ? c->rho : nullptr);
+  a.src = src == GAS_FIELD ? (const void*)c->qd : ((src == GAS_RHO || src == GAS_AUTO) ? c->rho : nullptr);
   a.rho_th = c->p.rho_th;
   a.k_own = query ? 0 : c->p.k_own;
   a.zone_width = c->p.zone_width;
@@ -433,6 +434,7 @@ template <class L, class S>
 int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh, const Fork* fk = nullptr) {
   if (refresh) MAPL(k_keep_old, SH_CELLS, MAP_NT);
   if (src == GAS_POP) MAPL((k_gas<L, S, GAS_POP>), SH_SEG, MAP_NT);
+  else if (src == GAS_AUTO) MAPL((k_gas<L, S, GAS_AUTO>), SH_SEG, MAP_NT);
   else if (src == GAS_FIELD) MAPL((k_gas<L, S, GAS_FIELD>), SH_CELLS, MAP_NT);
   else MAPL((k_gas<L, S, GAS_RHO>), SH_CELLS, MAP_NT);
   MAPL((k_cc_local<L>), SH_CCT, CC_NT);
@@ -490,12 +492,8 @@ inline int ctx_mapsets(flb_ctx* c) {
     rc = mapset_build(c->qs_field, q, c->D, al, c->st);
   }
   if (!rc && c->p.film_on) {
-    std::vector<MapArgs> r{map_args(c, false, GAS_POP)};
-    rc = mapset_build(c->ms_pop, r, c->D, al, c->st);
-    if (!rc) {
-      r[0] = map_args(c, false, GAS_RHO);
-      rc = mapset_build(c->ms_rho, r, c->D, al, c->st);
-    }
+    std::vector<MapArgs> r{map_args(c, false, GAS_AUTO)};
+    rc = mapset_build(c->ms_refresh, r, c->D, al, c->st);
     if (!rc) {  // imported maps: masks at any step
       r[0] = map_args(c, false, GAS_POP);
       r[0].k_own = 0;
@@ -506,14 +504,23 @@ inline int ctx_mapsets(flb_ctx* c) {
   return rc;
 }
 
+// the rho array no longer holds densities for the next refresh (the state was
+// replaced): that refresh labels the state itself
+inline int forget_rho(flb_ctx* c) {
+  static const long long none = -1;
+  HIPCHK(hipMemcpyAsync(&c->ctl->rho_step, &none, sizeof none, hipMemcpyHostToDevice, c->st));
+  return FLB_OK;
+}
+
 // ---- film-map refresh of one context before its step ----
+// (from the densities the previous step stored, else from the state)
 template <class L, class S>
-int refresh_maps(flb_ctx* c, bool from_rho) {
+int refresh_maps(flb_ctx* c) {
   int rc = ctx_mapsets(c);
   if (rc) return rc;
   rc = c->fork.init();
   if (rc) return rc;
-  return map_pipeline<L, S>(from_rho ? c->ms_rho : c->ms_pop, c->st, from_rho ? GAS_RHO : GAS_POP, true, &c->fork);
+  return map_pipeline<L, S>(c->ms_refresh, c->st, GAS_AUTO, true, &c->fork);
 }
 
 // ---- the BFS layers a refresh defers, before owner / dist are read ----
@@ -543,22 +550,18 @@ int do_steps(flb_ctx* c, int64_t nsteps, bool refresh, hipEvent_t* ev = nullptr)
   const StepFn coll = c->tcfg().coll[c->p.storage];
   for (int64_t s = 0; s < nsteps; s++) {
     const bool due = refresh && c->p.film_on && c->launched % c->p.k_own == 0;
+    if (due) {
+      int rc = refresh_maps<L, S>(c);
+      if (rc) return rc;
+    }
     if (coll) {
       if (ev) HIPCHK(hipEventRecord(ev[4 * s], c->st));
       fn(a, nblk, c->st);  // rho / psi of the current state
       if (ev) HIPCHK(hipEventRecord(ev[4 * s + 1], c->st));
-      if (due) {
-        int rc = refresh_maps<L, S>(c, true);
-        if (rc) return rc;
-      }
       if (ev) HIPCHK(hipEventRecord(ev[4 * s + 2], c->st));
       coll(a, nblk, c->st);
       if (ev) HIPCHK(hipEventRecord(ev[4 * s + 3], c->st));
     } else {
-      if (due) {
-        int rc = refresh_maps<L, S>(c, false);
-        if (rc) return rc;
-      }
       if (ev) HIPCHK(hipEventRecord(ev[4 * s], c->st));
       fn(a, nblk, c->st);
       if (ev) HIPCHK(hipEventRecord(ev[4 * s + 1], c->st));

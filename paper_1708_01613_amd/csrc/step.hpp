@@ -32,6 +32,8 @@ struct StepArgs {
   int psi_bar_mode;
   int film_on, rupture_warmup, on_rupture;
   int rupture_filter;    // 1: FP32 sign filter before the FP64 rupture test
+  int gas_k;             // > 0: a step n with (n + 1) % gas_k == 0 stores every cell's density in rho,
+                         // which the film-map refresh at step n + 1 labels
   const uint8_t* flag;   // per cell: 1 if it has candidate barrier links
   const uint32_t* mask;  // per cell: active barrier links (bit i = direction i) and kRhoBit
   const int* flist;      // cells with barrier links at the last refresh (ctl->n_flagged)
@@ -353,6 +355,7 @@ __device__ __forceinline__ void step_finish(const StepArgs& a, int nblk, double 
     const bool any = ctl->step_events != 0;
     ctl->step_events = 0;
     ctl->alias_dirty = 0;
+    if (a.gas_k > 0 && (ctl->steps + 1) % a.gas_k == 0) ctl->rho_step = ctl->steps;
     ctl->steps = ctl->steps + 1;
     if (any && a.on_rupture) ctl->stopped = 1;
   }
@@ -416,7 +419,7 @@ struct StepBlock {
   Ctl* ctl;
   long long step;
   int nx, nm, nz, x0, m0, z0, L_, TXe, TMe, lx, lm, x, m, xc, mc, gx, gm, hx, hm;
-  bool act, has_halo, film, test_rupture, tau_one;
+  bool act, has_halo, film, test_rupture, tau_one, rho_all;
   T G, rho0, tau, omega, psi_bar;
   double acc_m = 0.0, acc_x = 0.0, acc_y = 0.0, acc_z = 0.0;
 
@@ -546,7 +549,7 @@ struct StepBlock {
     io.store_at(0, vo0, tau_one ? feq0 : f[0] - (f[0] - feq0) * omega);
     // the rupture test runs in its own kernel after this one, on the
     // densities of the state entering the step
-    if (test_rupture && act && (flag & kRhoBit)) ((T*)a.rho)[c] = rho;
+    if (act && (rho_all || (test_rupture && (flag & kRhoBit)))) ((T*)a.rho)[c] = rho;
     const double keep = act ? 1.0 : 0.0;
     acc_m += keep * (double)rho;
     acc_x += keep * (double)jx;
@@ -610,6 +613,7 @@ struct StepBlock {
     tau_one = a.tau == 1.0;
     film = a.film_on != 0;
     test_rupture = film && step >= a.rupture_warmup;
+    rho_all = a.gas_k > 0 && (step + 1) % a.gas_k == 0;
     psi_bar = (T)a.psi_bar;
 
     if (interior) {
