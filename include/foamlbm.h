@@ -73,7 +73,7 @@ typedef struct {
   void* user;
 } flb_allocator;
 
-/* Problem definition ("Input DATA", "Geometry define", "Lattice define" of
+/* Problem definition (the input, geometry and lattice boxes of
  * Fig. Mainflowchart).  All quantities in lattice units. */
 typedef struct {
   int32_t lattice;       /* FLB_D2Q9 or FLB_D3Q19 */
@@ -127,7 +127,7 @@ typedef struct {
  * the null stream).  On success *out receives the context. */
 int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream, flb_ctx** out);
 
-/* Initial state (Sec. 2.1.3, "Random nucleation" of Fig. Mainflowchart):
+/* Initial state (Sec. 2.1.3, the random-nucleation box of Fig. Mainflowchart):
  * rho = rho_gas in cells whose periodic minimum-image distance to some nucleus
  * centre is <= its radius, rho_liquid elsewhere, then rho += noise_amp (2U-1)
  * with U the top 53 bits of splitmix64(seed ^ (c * 0x9E3779B97F4A7C15)) / 2^53
@@ -165,7 +165,7 @@ int flb_get_stats(flb_ctx* ctx, flb_stats* out);
  * D2Q9, 18 on D3Q19); component k (1-based) is the one with the k-th smallest
  * minimum cell index; liquid cells are 0.  out[n], n == nx*ny*nz;
  * *n_bubbles receives the number of components.  (Bubble statistics of
- * Sec. 5, computed from the field as "domain gas points" of Sec. 2.1.3.) */
+ * Sec. 5, computed from the field as the gas points of the domain, Sec. 2.1.3.) */
 int flb_get_labels(flb_ctx* ctx, int32_t* out, size_t n, int32_t* n_bubbles);
 
 /* The same labelling applied to a caller-given FP64 density field rho[n]. */

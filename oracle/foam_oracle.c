@@ -250,7 +250,7 @@ void or_lattice(int lattice, int32_t* e_out, double* w_out) {
 }
 
 /* ------------------------------------------------------------------ */
-/* initial state: random nucleation at "domain gas points" (Sec. 2.1.3) */
+/* initial state: random nucleation at gas points of the domain (Sec. 2.1.3) */
 /* rho = rho_gas inside any nucleus (periodic minimum image, cell      */
 /* centres at integer coordinates), rho_liquid elsewhere, plus seeded  */
 /* uniform noise; populations at rest equilibrium f_i = w_i rho.       */
