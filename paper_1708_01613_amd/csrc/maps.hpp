@@ -113,7 +113,7 @@ __device__ __forceinline__ int first_lane(unsigned long long m) { return __built
 // ---- per-lattice arguments of the map kernels ----
 // GAS_AUTO: the densities a step kernel stored for the refresh (the rho
 // array, when it holds the step before this one), else the stored state
-enum GasSrc { GAS_POP = 0, GAS_FIELD = 1, GAS_RHO = 2, GAS_AUTO = 3 };
+enum GasSrc { GAS_POP = 0, GAS_FIELD = 1, GAS_AUTO = 2 };
 
 struct MapArgs {
   Ctl* ctl;               // gate: run control of the lattice (or a zeroed query control)
@@ -122,7 +122,7 @@ struct MapArgs {
   Geo geo;                // population layout (gas from the stored state)
   const void* b0;
   const void* b1;
-  const void* src;        // a cell-linear density field: FP64 (GAS_FIELD) or compute type (GAS_RHO)
+  const void* src;        // a cell-linear density field: FP64 (GAS_FIELD) or compute type (GAS_AUTO)
   double rho_th;
   int k_own;              // refresh steps: steps % k_own == 0 (0: every launch, queries)
   int zone_width;
@@ -180,14 +180,9 @@ __global__ __launch_bounds__(MAP_NT) void k_gas(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m)) return;
   if (SRC == GAS_AUTO && m.sctl->steps > 0 && m.sctl->rho_step == m.sctl->steps - 1) {
-    // the densities the previous step stored for this refresh
-    for_cells<false>(
-        m.d,
-        [&](const SegCell& q) {
-          const double r = (double)((const typename S::ct*)m.src)[q.c];
-          m.par[q.c] = r < m.rho_th ? (int)q.c : -1;
-        },
-        bid, nbk);
+    // the densities the previous step stored for this refresh (cell-linear)
+    const typename S::ct* __restrict__ rho = (const typename S::ct*)m.src;
+    FOR_SHARE(c, m.d.N) m.par[c] = (double)rho[c] < m.rho_th ? (int)c : -1;
   } else if constexpr (SRC == GAS_POP || SRC == GAS_AUTO) {
     // density of the stored state, summed in FP64
     const void* src = (m.sctl->steps & 1) ? m.b1 : m.b0;
@@ -204,7 +199,7 @@ __global__ __launch_bounds__(MAP_NT) void k_gas(MAP_KERNEL_PARAMS) {
         bid, nbk);
   } else {
     FOR_SHARE(c, m.d.N) {
-      const double r = SRC == GAS_FIELD ? ((const double*)m.src)[c] : (double)((const typename S::ct*)m.src)[c];
+      const double r = ((const double*)m.src)[c];  // GAS_FIELD: an FP64 field
       m.par[c] = r < m.rho_th ? (int)c : -1;
     }
   }
@@ -275,27 +270,44 @@ __global__ __launch_bounds__(CC_NT) void k_cc_local(MAP_KERNEL_PARAMS) {
     z = z0 + (l >> 6) / TT::TM;
     return x < d.nx && mm_ < d.nm && z < d.nz;
   };
+  // a wavefront's k-th row is one tile row (lanes = x): the gas runs along x
+  // are components already, so every gas cell starts at its run's first cell
+  const int lane = threadIdx.x & 63;
+  bool gas[PER];
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int l = threadIdx.x + k * CC_NT;
     int x, mm_, z;
-    bool gas = false;
-    if (gcell(l, x, mm_, z)) gas = m.par[x + (unsigned)d.nx * (mm_ + (unsigned)d.nm * z)] >= 0;
-    lp[l] = gas ? l : -1;
+    gas[k] = false;
+    if (gcell(l, x, mm_, z)) gas[k] = m.par[x + (unsigned)d.nx * (mm_ + (unsigned)d.nm * z)] >= 0;
   }
-  __syncthreads();
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int l = threadIdx.x + k * CC_NT;
-    if (lp[l] < 0) continue;
+    const unsigned long long g = __ballot(gas[k]);
+    const unsigned long long starts = g & ~(g << 1);
+    const unsigned long long upto = starts & ((2ull << lane) - 1ull);  // lane 63: all bits
+    lp[l] = gas[k] ? (l & ~63) + (63 - __clzll((long long)upto)) : -1;
+  }
+  __syncthreads();
+  // links leaving the row: one union per run of equal (run, run) pairs, the
+  // runs' unions concurrently
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int l = threadIdx.x + k * CC_NT;
     const int lx = l & 63, lm = (l >> 6) % TT::TM, lz = (l >> 6) / TT::TM;
 #pragma unroll
     for (int i = 1; i < L::Q; i += 2) {  // one direction of each opposite pair
+      if (L::em[i] == 0 && L::ez[i] == 0) continue;  // along x: inside the runs
       const int nx_ = lx + L::ex[i], nm_ = lm + L::em[i], nz_ = lz + L::ez[i];
-      if (nx_ < 0 || nx_ >= 64 || nm_ < 0 || nm_ >= TT::TM || nz_ < 0 || nz_ >= TT::TZ) continue;
-      if (x0 + nx_ >= d.nx || m0 + nm_ >= d.nm || z0 + nz_ >= d.nz) continue;
-      const int ln = nx_ + 64 * (nm_ + TT::TM * nz_);
-      if (lp[ln] >= 0) lds_unite(lp, l, ln);
+      int a = -1, bn = -1;
+      if (gas[k] && nx_ >= 0 && nx_ < 64 && nm_ >= 0 && nm_ < TT::TM && nz_ >= 0 && nz_ < TT::TZ &&
+          x0 + nx_ < d.nx && m0 + nm_ < d.nm && z0 + nz_ < d.nz) {
+        bn = lp[nx_ + 64 * (nm_ + TT::TM * nz_)];
+        if (bn >= 0) a = lp[l];
+      }
+      const bool head = run_head(a, bn);
+      if (a >= 0 && head) lds_unite(lp, a, bn);
     }
   }
   __syncthreads();
@@ -948,8 +960,11 @@ __host__ inline int map_share(int shape, const MapDims& d) {
   const long long nseg = (long long)((d.nx + 63) / 64) * d.nm * d.nz;
   long long g = 1;
   switch (shape) {
-    case SH_CELLS: g = std::min<long long>((N + 1 + MAP_NT - 1) / MAP_NT, 16384); break;
-    case SH_SEG: g = std::min<long long>((nseg + MAP_WAVES - 1) / MAP_WAVES, 65536); break;
+    // grid-stride shapes stop at a few workgroups per CU: every workgroup of a
+    // map kernel first looks up its lattice's arguments (dependent loads), so
+    // many short workgroups spend their time starting
+    case SH_CELLS: g = std::min<long long>((N + 1 + MAP_NT - 1) / MAP_NT, 4096); break;
+    case SH_SEG: g = std::min<long long>((nseg + MAP_WAVES - 1) / MAP_WAVES, 16384); break;
     case SH_CCT: g = cc_tiles(d, CCTile<L>::TM, CCTile<L>::TZ); break;
     case SH_BFST: g = cc_tiles(d, BfsTile<L>::TM, BfsTile<L>::TZ); break;
     case SH_RANK: g = (N + RANK_BLOCK - 1) / RANK_BLOCK; break;

@@ -384,7 +384,7 @@ inline MapArgs map_args(flb_ctx* c, bool query, int src) {
   a.geo = c->geo;
   a.b0 = c->f[0];
   a.b1 = c->f[1];
-  a.src = src == GAS_FIELD ? (const void*)c->qd : ((src == GAS_RHO || src == GAS_AUTO) ? c->rho : nullptr);
+  a.src = src == GAS_FIELD ? (const void*)c->qd : (src == GAS_AUTO ? c->rho : nullptr);
   a.rho_th = c->p.rho_th;
   a.k_own = query ? 0 : c->p.k_own;
   a.zone_width = c->p.zone_width;
@@ -434,9 +434,8 @@ template <class L, class S>
 int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh, const Fork* fk = nullptr) {
   if (refresh) MAPL(k_keep_old, SH_CELLS, MAP_NT);
   if (src == GAS_POP) MAPL((k_gas<L, S, GAS_POP>), SH_SEG, MAP_NT);
-  else if (src == GAS_AUTO) MAPL((k_gas<L, S, GAS_AUTO>), SH_SEG, MAP_NT);
-  else if (src == GAS_FIELD) MAPL((k_gas<L, S, GAS_FIELD>), SH_CELLS, MAP_NT);
-  else MAPL((k_gas<L, S, GAS_RHO>), SH_CELLS, MAP_NT);
+  else if (src == GAS_AUTO) MAPL((k_gas<L, S, GAS_AUTO>), SH_SEG, MAP_NT);  // either path: segments
+  else MAPL((k_gas<L, S, GAS_FIELD>), SH_CELLS, MAP_NT);
   MAPL((k_cc_local<L>), SH_CCT, CC_NT);
   MAPL((k_cc_cross<L>), SH_SEG, MAP_NT);
   MAPL(k_cc_compress, SH_RANK, RANK_BLOCK);

@@ -71,35 +71,47 @@ __device__ __forceinline__ void rupture_cells(const StepArgs& a, unsigned bid, u
             k = min(oc.x, oy.x);
             k2 = max(oc.y, oy.y);
           }
-          // merge identical pairs of the wavefront, then one lane per pair
-          // unites, logs and counts
+          // one lane per distinct pair of the wavefront (its leader); the
+          // leaders unite concurrently, and the wavefront takes its log
+          // records and counts with one atomic each (a burst of ruptures
+          // would otherwise queue on two counters)
           unsigned long long todo = __ballot(hit);
+          bool leader = false;
           while (todo) {
             const int ld = first_lane(todo);
             const int k0 = __shfl(k, ld, 64), k20 = __shfl(k2, ld, 64);
-            if (lane == ld) {
+            if (lane == ld) leader = true;
+            if (hit && k == k0 && k2 == k20) hit = false;
+            todo = __ballot(hit);
+          }
+          const unsigned long long lmask = __ballot(leader);
+          if (lmask) {  // wave-uniform
+            const int first = first_lane(lmask);
+            const bool united = leader && uf_unite(a.alias, k, k2);
+            const unsigned long long umask = __ballot(united);
+            unsigned base = a.ev_cap;
+            if (lane == first) {
               ctl->step_events = 1;
-              if (uf_unite(a.alias, k0, k20)) {
-                atomicAdd((unsigned long long*)&ctl->n_ruptures, 1ull);
+              if (umask) {
+                atomicAdd((unsigned long long*)&ctl->n_ruptures, (unsigned long long)__popcll(umask));
                 ctl->alias_dirty = 1;
               }
-              if (__atomic_load_n(&ctl->ev_count, __ATOMIC_RELAXED) < a.ev_cap) {
-                const unsigned e = atomicAdd(&ctl->ev_count, 1u);
-                if (e < a.ev_cap) {
-                  long long* ev = a.events + 4ll * e;
-                  ev[0] = step;
-                  ev[1] = k0;
-                  ev[2] = k20;
-                  ev[3] = 0;
-                } else {
-                  ctl->ev_full = 1;
-                }
+              if (__atomic_load_n(&ctl->ev_count, __ATOMIC_RELAXED) < a.ev_cap)
+                base = atomicAdd(&ctl->ev_count, (unsigned)__popcll(lmask));
+            }
+            base = __shfl(base, first, 64);
+            if (leader) {
+              const unsigned e = base + (unsigned)__popcll(lmask & ((1ull << lane) - 1ull));
+              if (base < a.ev_cap && e < a.ev_cap) {
+                long long* ev = a.events + 4ll * e;
+                ev[0] = step;
+                ev[1] = k;
+                ev[2] = k2;
+                ev[3] = 0;
               } else {
                 ctl->ev_full = 1;
               }
             }
-            if (hit && k == k0 && k2 == k20) hit = false;
-            todo = __ballot(hit);
           }
         }
       });
