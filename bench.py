@@ -220,10 +220,15 @@ def main():
         p16 = dict(params, storage="f16s")
         s16 = foamlbm.Sim(**p16)
         s16.set_nuclei(nuc)
+        if args.tile < 0:
+            s16.autotune(reps=3)
         s16.step(10)
         ms16 = s16.time_steps(nk, refresh=False, kernel=True)[1] / nk
+        t16 = s16.tuning()
         variants["d3q19_f16s_kernel"] = {"ms": round(ms16, 4), "MLUPS": round(N / (ms16 * 1e-3) / 1e6, 1),
-                                         "GBs_algorithmic": round(77 * N / (ms16 * 1e-3) / 1e9, 1)}
+                                         "GBs_algorithmic": round(77 * N / (ms16 * 1e-3) / 1e9, 1),
+                                         "kernel": (f"k_step<D3Q19K,SF16S,{t16['tile_x']},{t16['tile_m']}>"
+                                                    if t16["tile_x"] else "k_psi+k_collide<D3Q19K,SF16S>")}
         del s16
         torch.cuda.empty_cache()
     except Exception as exc:  # a variant failing must not hide the main line
