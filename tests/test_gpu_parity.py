@@ -374,3 +374,31 @@ def test_film_zone_widths_and_deferred_layers(flb, zw):
     _compare_maps(flb, 0, g, o)
     assert max_rel(g.density(), o.density()) <= 1e-12
     assert g.stats()["n_ruptures"] == o.n_ruptures
+
+
+_TINY = {(0, (30, 20, 1)): [[7.0, 10.0, 0, 4.5], [19.5, 10.0, 0, 4.5]],
+         (0, (7, 90, 1)): [[3.0, 20.0, 0, 3.0], [3.0, 29.0, 0, 3.2]],
+         (1, (13, 7, 9)): [[3.0, 3.0, 4.0, 2.8], [9.5, 3.0, 4.0, 2.8]],
+         (1, (40, 3, 5)): [[10.0, 1.0, 2.0, 3.0], [18.5, 1.0, 2.0, 3.0]]}
+
+
+@pytest.mark.parametrize("kind,dims", list(_TINY))
+def test_film_on_lattices_smaller_than_a_tile(flb, kind, dims):
+    # extents below the 64-cell rows and the tile sizes of the map kernels,
+    # so tiles and their halos wrap around the lattice more than once; two
+    # bubbles with a film that the barrier holds until the rupture test starts
+    nx, ny, nz = dims
+    nuc = _TINY[(kind, dims)]
+    p = _case(flb, lattice=kind, storage="f64", nx=nx, ny=ny, nz=nz, G=-5.5, rho_liquid=2.3, rho_gas=0.11, film_on=1,
+              k_own=2, zone_width=6, rupture_warmup=4, seed=6)
+    g, o = _run_pair(flb, p, nuc, 3)
+    gm = _compare_maps(flb, kind, g, o)
+    assert np.count_nonzero(gm["mask"]) > 0
+    g.step(4)
+    o.step(4)
+    _compare_maps(flb, kind, g, o)
+    assert max_rel(g.density(), o.density()) <= 1e-12
+    assert g.stats()["n_ruptures"] == o.n_ruptures > 0
+    lab, nb = g.labels()
+    olab, onb = o.labels()
+    assert nb == onb and np.array_equal(lab, olab)
