@@ -298,7 +298,14 @@ void flb_batch_destroy(flb_batch* batch);
  * jobs that are done: their final density and statistics are copied to host
  * memory and their device memory is released.  The round synchronises the
  * stream before it returns.  A job's results are exactly those of the same
- * job run alone with flb_create / flb_set_nuclei / flb_step. */
+ * job run alone with flb_create / flb_set_nuclei / flb_step.
+ * Failure handling: after its launches each round reads, for every job it
+ * advanced, the flag that the step kernel's mass reduction sets on a
+ * non-finite value, and retires such a job at once as FLB_JOB_FAILED (its
+ * device memory released, no results; flb_server_result then returns
+ * FLB_ENUMERIC); a job that could not be created on admission fails the same
+ * way with the creation error.  No launch mixes the fields of two jobs, so a
+ * failed job leaves the others' results unchanged. */
 typedef struct flb_server flb_server;
 typedef struct {
   int64_t pool_bytes;  /* device bytes the resident jobs may hold together */
@@ -310,7 +317,7 @@ typedef struct {
   int32_t policy;      /* FLB_SERVE_FIFO or FLB_SERVE_SHORTEST */
 } flb_server_config;
 enum { FLB_SERVE_FIFO = 0, FLB_SERVE_SHORTEST = 1 };
-enum { FLB_JOB_QUEUED = 0, FLB_JOB_RUNNING = 1, FLB_JOB_DONE = 2, FLB_JOB_FAILED = 3 };
+enum { FLB_JOB_QUEUED = 0, FLB_JOB_RUNNING = 1, FLB_JOB_DONE = 2, FLB_JOB_FAILED = 3, FLB_JOB_CANCELLED = 4 };
 
 /* pool 64 GiB, 256 jobs, chunks of 100 steps, graphs of 20 steps, 2^22 cells,
  * FLB_SERVE_FIFO */
@@ -321,13 +328,19 @@ int flb_server_create(const flb_server_config* cfg, const flb_allocator* alloc, 
  * more device bytes than the pool (it could never be admitted). */
 int flb_server_submit(flb_server* srv, const flb_params* p, const flb_nucleus* nuclei, int32_t n, int64_t steps,
                       int64_t* id);
-/* One scheduling round (see above).  Any output pointer may be NULL. */
+/* One scheduling round (see above).  *n_done counts the jobs that have left
+ * the server: done, failed or cancelled.  Any output pointer may be NULL. */
 int flb_server_pump(flb_server* srv, int32_t* n_running, int32_t* n_queued, int64_t* n_done);
 int flb_server_job(flb_server* srv, int64_t id, int32_t* state, int64_t* steps_done);
 /* Final density (n == nx*ny*nz, x fastest) and statistics of a done job. */
 int flb_server_result(flb_server* srv, int64_t id, double* density, size_t n, flb_stats* stats);
-/* Forgets a done or failed job. */
+/* Forgets a done, failed or cancelled job. */
 int flb_server_release(flb_server* srv, int64_t id);
+/* Cancels a queued or running job between rounds: a queued job leaves the
+ * queue, a running one has its device memory released at once (the stream is
+ * synchronised first).  The job ends as FLB_JOB_CANCELLED, without results.
+ * FLB_EINVAL for an unknown job or one that has already finished. */
+int flb_server_cancel(flb_server* srv, int64_t id);
 int flb_server_usage(flb_server* srv, int64_t* used_bytes, int64_t* pool_bytes);
 void flb_server_destroy(flb_server* srv);
 

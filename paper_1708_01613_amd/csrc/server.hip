@@ -19,7 +19,15 @@
 // round: its final density and statistics are copied to host memory and its
 // device memory is released, so the next round can admit more.  A job's
 // fields are exactly those of the same job run alone.
+//
+// Health: every round gathers the non-finite-mass flag of each advanced job
+// (one small kernel over their run-control blocks, one copy back) and
+// retires a job whose mass has blown up as failed at once, instead of
+// letting it hold device memory and launch slots until its last step; the
+// other jobs are unaffected, since no launch mixes the fields of two jobs.
+// A queued or running job may also be cancelled between rounds.
 #include <algorithm>
+#include <cstdio>
 #include <deque>
 #include <map>
 #include <tuple>
@@ -60,11 +68,57 @@ struct flb_server {
   std::map<int64_t, Job*> jobs;
   flb_batch* view[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   std::vector<flb_ctx*> vm[2][3];
+  // health check: device and pinned host arrays of max_jobs run-control
+  // pointers and flags, allocated on the first round
+  void* d_health = nullptr;
+  void* h_health = nullptr;
 };
 
 namespace {
 
 constexpr int kStarveRounds = 8;
+
+// out[k] = the non-finite-mass flag of run-control block ctl[k]
+__global__ __launch_bounds__(256) void k_failed_flags(const Ctl* const* ctl, int n, int* out) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < n) out[k] = ctl[k]->failed;
+}
+
+size_t health_bytes(const flb_server* s) { return (size_t)s->cfg.max_jobs * (sizeof(void*) + sizeof(int)); }
+
+void* dev_alloc(flb_server* s, size_t n) {
+  void* p = nullptr;
+  if (s->have_al) return s->al.alloc(n, s->al.user);
+  return hipMalloc(&p, n) == hipSuccess ? p : nullptr;
+}
+
+void dev_free(flb_server* s, void* p) {
+  if (!p) return;
+  if (s->have_al) s->al.free(p, s->al.user);
+  else (void)hipFree(p);
+}
+
+// failed[k] = 1 if job act[k] saw a non-finite mass; synchronises the stream
+int health(flb_server* s, const std::vector<Job*>& act, std::vector<int>& failed) {
+  const int n = (int)act.size();
+  if (!s->d_health) {
+    s->d_health = dev_alloc(s, health_bytes(s));
+    if (!s->d_health) return fail(FLB_ENOMEM, "device allocation of %zu bytes failed", health_bytes(s));
+  }
+  if (!s->h_health) HIPCHK(hipHostMalloc(&s->h_health, health_bytes(s), hipHostMallocDefault));
+  const Ctl** hp = (const Ctl**)s->h_health;
+  int* hf = (int*)(hp + s->cfg.max_jobs);
+  const Ctl** dp = (const Ctl**)s->d_health;
+  int* df = (int*)(dp + s->cfg.max_jobs);
+  for (int k = 0; k < n; k++) hp[k] = act[k]->c->ctl;
+  HIPCHK(hipMemcpyAsync(dp, hp, sizeof(void*) * n, hipMemcpyHostToDevice, s->st));
+  k_failed_flags<<<(n + 255) / 256, 256, 0, s->st>>>(dp, n, df);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(hf, df, sizeof(int) * n, hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  failed.assign(hf, hf + n);
+  return FLB_OK;
+}
 
 int64_t job_cells(const Job* j) { return (int64_t)j->p.nx * j->p.ny * j->p.nz; }
 
@@ -82,6 +136,7 @@ int admit(flb_server* s) {
       if (j->c) flb_destroy(j->c);
       j->c = nullptr;
       j->state = FLB_JOB_FAILED;
+      s->n_done++;
       continue;
     }
     j->bytes = j->c->bytes;
@@ -131,6 +186,25 @@ int sync_views(flb_server* s, const std::vector<Job*>& act) {
   return FLB_OK;
 }
 
+// Releases a resident job's context.  A batch view's device tables hold its
+// members' device pointers, so every view naming the context goes with it: a
+// context created later at the same host address must never be taken for a
+// member of the old view.
+void release_ctx(flb_server* s, Job* j) {
+  for (int d = 0; d < 2; d++)
+    for (int t = 0; t < 3; t++)
+      if (std::find(s->vm[d][t].begin(), s->vm[d][t].end(), j->c) != s->vm[d][t].end()) {
+        batch_free(s->view[d][t]);
+        s->view[d][t] = nullptr;
+        s->vm[d][t].clear();
+      }
+  s->used -= j->bytes;
+  s->cells -= j->c->N;
+  flb_destroy(j->c);
+  j->c = nullptr;
+  s->n_done++;
+}
+
 void retire(flb_server* s, Job* j) {
   j->density.resize((size_t)j->c->N);
   int rc = flb_get_density(j->c, j->density.data(), j->density.size());
@@ -141,11 +215,17 @@ void retire(flb_server* s, Job* j) {
   } else {
     j->state = FLB_JOB_DONE;
   }
-  s->used -= j->bytes;
-  s->cells -= j->c->N;
-  flb_destroy(j->c);
-  j->c = nullptr;
-  s->n_done++;
+  release_ctx(s, j);
+}
+
+// a job whose mass became non-finite: no results, memory released now
+void retire_failed(flb_server* s, Job* j) {
+  char msg[96];
+  snprintf(msg, sizeof msg, "non-finite mass within its first %lld steps", (long long)j->done);
+  j->err = msg;
+  j->density.clear();
+  j->state = FLB_JOB_FAILED;
+  release_ctx(s, j);
 }
 
 }  // namespace
@@ -234,16 +314,21 @@ int flb_server_pump(flb_server* s, int32_t* n_running, int32_t* n_queued, int64_
       for (int t = 0; t < 3 && !rc; t++)
         if (s->view[d][t]) rc = FLB_BATCH_DISPATCH(s->view[d][t], batch_steps, s->view[d][t], r);
     if (rc) return rc;
-    HIPCHK(hipStreamSynchronize(s->st));
+    std::vector<int> failed;
+    rc = health(s, act, failed);
+    if (rc) return rc;
     std::vector<Job*> still;
     for (Job* j : s->running) {
-      if (std::find(act.begin(), act.end(), j) != act.end()) {
+      const auto it = std::find(act.begin(), act.end(), j);
+      const bool adv = it != act.end();
+      if (adv) {
         j->done += r;
         j->idle = 0;
       } else {
         j->idle++;
       }
-      if (j->done >= j->steps) retire(s, j);
+      if (adv && failed[it - act.begin()]) retire_failed(s, j);
+      else if (j->done >= j->steps) retire(s, j);
       else still.push_back(j);
     }
     s->running.swap(still);
@@ -268,7 +353,11 @@ int flb_server_result(flb_server* s, int64_t id, double* density, size_t n, flb_
   auto it = s->jobs.find(id);
   if (it == s->jobs.end()) return fail(FLB_EINVAL, "unknown job %lld", (long long)id);
   Job* j = it->second;
-  if (j->state == FLB_JOB_FAILED) return fail(FLB_EHIP, "job %lld failed: %s", (long long)id, j->err.c_str());
+  if (j->state == FLB_JOB_FAILED) {
+    const int code = j->err.rfind("non-finite", 0) == 0 ? FLB_ENUMERIC : FLB_EHIP;
+    return fail(code, "job %lld failed: %s", (long long)id, j->err.c_str());
+  }
+  if (j->state == FLB_JOB_CANCELLED) return fail(FLB_EINVAL, "job %lld was cancelled", (long long)id);
   if (j->state != FLB_JOB_DONE) return fail(FLB_EINVAL, "job %lld is not done", (long long)id);
   if (density) {
     if (n != j->density.size()) return fail(FLB_EINVAL, "n must be %zu", j->density.size());
@@ -290,6 +379,24 @@ int flb_server_release(flb_server* s, int64_t id) {
   return FLB_OK;
 }
 
+int flb_server_cancel(flb_server* s, int64_t id) {
+  if (!s) return fail(FLB_EINVAL, "server is NULL");
+  auto it = s->jobs.find(id);
+  if (it == s->jobs.end()) return fail(FLB_EINVAL, "unknown job %lld", (long long)id);
+  Job* j = it->second;
+  if (j->state == FLB_JOB_QUEUED) {
+    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), j));
+    s->n_done++;
+  } else if (j->state == FLB_JOB_RUNNING) {
+    release_ctx(s, j);
+    s->running.erase(std::find(s->running.begin(), s->running.end(), j));
+  } else {
+    return fail(FLB_EINVAL, "job %lld has already finished", (long long)id);
+  }
+  j->state = FLB_JOB_CANCELLED;
+  return FLB_OK;
+}
+
 int flb_server_usage(flb_server* s, int64_t* used_bytes, int64_t* pool_bytes) {
   if (!s) return fail(FLB_EINVAL, "server is NULL");
   if (used_bytes) *used_bytes = (int64_t)s->used;
@@ -306,6 +413,8 @@ void flb_server_destroy(flb_server* s) {
     if (kv.second->c) flb_destroy(kv.second->c);
     delete kv.second;
   }
+  dev_free(s, s->d_health);
+  if (s->h_health) (void)hipHostFree(s->h_health);
   delete s;
 }
 

@@ -61,7 +61,7 @@ class flb_server_config(C.Structure):
                 ("graph_steps", C.c_int32), ("max_cells", C.c_int64), ("policy", C.c_int32)]
 
 
-FLB_JOB_QUEUED, FLB_JOB_RUNNING, FLB_JOB_DONE, FLB_JOB_FAILED = 0, 1, 2, 3
+FLB_JOB_QUEUED, FLB_JOB_RUNNING, FLB_JOB_DONE, FLB_JOB_FAILED, FLB_JOB_CANCELLED = 0, 1, 2, 3, 4
 FLB_SERVE_FIFO, FLB_SERVE_SHORTEST = 0, 1
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -132,6 +132,7 @@ _SIGS = {
     "flb_server_job": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "flb_server_result": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_size_t, C.POINTER(flb_stats)]),
     "flb_server_release": (C.c_int, [C.c_void_p, C.c_int64]),
+    "flb_server_cancel": (C.c_int, [C.c_void_p, C.c_int64]),
     "flb_server_usage": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "flb_server_destroy": (None, [C.c_void_p]),
 }
@@ -506,6 +507,9 @@ class Server:
     def release(self, jid):
         check(flb_server_release(self.h, int(jid)), "flb_server_release")
         self._shape.pop(jid, None)
+
+    def cancel(self, jid):
+        check(flb_server_cancel(self.h, int(jid)), "flb_server_cancel")
 
     def usage(self):
         u, p = C.c_int64(), C.c_int64()
