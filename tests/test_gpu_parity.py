@@ -354,7 +354,7 @@ def test_autotune_keeps_state_and_results(flb, kind):
     assert g.stats()["n_ruptures"] == r.stats()["n_ruptures"]
 
 
-@pytest.mark.parametrize("zw", [2, 3, 7, 9])
+@pytest.mark.parametrize("zw", [2, 3, 4, 5, 7, 9])
 def test_film_zone_widths_and_deferred_layers(flb, zw):
     # a refresh builds owner / dist only as deep as a barrier can reach
     # (zone_width / 2 hops); the deeper layers are filled in when the maps
@@ -372,6 +372,25 @@ def test_film_zone_widths_and_deferred_layers(flb, zw):
     g.step(4)
     o.step(4)
     _compare_maps(flb, 0, g, o)
+    assert max_rel(g.density(), o.density()) <= 1e-12
+    assert g.stats()["n_ruptures"] == o.n_ruptures
+
+
+@pytest.mark.parametrize("zw", [3, 4, 6, 8])
+def test_film_zone_widths_3d(flb, zw):
+    # the same on D3Q19: the hot layers come from one staged pass up to three
+    # layers deep (zone widths up to 7) and layer by layer beyond that
+    rng = np.random.default_rng(60 + zw)
+    nuc = [[float(rng.uniform(0, 40)), float(rng.uniform(0, 28)), float(rng.uniform(0, 22)), float(rng.uniform(3, 5))]
+           for _ in range(10)]
+    p = _case(flb, lattice=1, storage="f64", nx=40, ny=28, nz=22, G=-5.5, rho_liquid=2.3, rho_gas=0.11,
+              film_on=1, k_own=5, zone_width=zw, rupture_warmup=20, seed=11)
+    g, o = _run_pair(flb, p, nuc, 23)
+    gm = _compare_maps(flb, 1, g, o)
+    assert gm["dist"].max() > zw // 2
+    g.step(4)
+    o.step(4)
+    _compare_maps(flb, 1, g, o)
     assert max_rel(g.density(), o.density()) <= 1e-12
     assert g.stats()["n_ruptures"] == o.n_ruptures
 
