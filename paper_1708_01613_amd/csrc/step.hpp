@@ -403,9 +403,13 @@ struct StepBlock {
   static constexpr int HM = L::HAS_M ? 1 : 0;
   static constexpr int LW = TX + 2;
   static constexpr int LH = TM + 2 * HM;
-  // halo waves: one lane per ring cell of a full tile
+  // halo waves: one lane per ring cell of a full tile.  On 2-D lattices the
+  // ring is the two end cells of each plane, which lanes 0 and 1 of the
+  // first interior wave load beside their own cells (HIN) instead of a
+  // wave of their own
+  static constexpr bool HIN = !L::HAS_M;
   static constexpr int NH = 2 * (TM + 2 * HM) + (HM ? 2 * TX : 0);
-  static constexpr int NT = NI + (NH + 63) / 64 * 64;
+  static constexpr int NT = HIN ? NI : NI + (NH + 63) / 64 * 64;
   struct Smem {
     T psi[4][LH][LW];
     T rho[4][LH][LW];
@@ -429,6 +433,7 @@ struct StepBlock {
   // iterations ago, publish rho / psi of the new plane
   __device__ __forceinline__ void iter(int k, T (&ld)[Q], T (&co)[Q], unsigned& fl_ld, unsigned fl_co) {
     const bool loading = k <= L_ + 1;  // uniform over the workgroup
+    T hv[Q];
     if (loading) {
       // every interior lane loads (lanes outside the lattice read clamped
       // cells and never publish), so no divergent branch separates the loads
@@ -437,6 +442,7 @@ struct StepBlock {
       const int zl = wrap_any(z0 - 1 + k, nz);
       if (film) fl_ld = a.mask[(unsigned)(xc + nx * (mc + nm * zl))];
       io.pull(xc, mc, zl, ld);
+      if (HIN && has_halo) io.pull(gx, gm, zl, hv);
     }
     // keep the collide between the loads and their first use
     __builtin_amdgcn_sched_barrier(0);
@@ -457,6 +463,13 @@ struct StepBlock {
       if (act) {
         sm.rho[slot][lm + HM][lx + 1] = r;
         sm.psi[slot][lm + HM][lx + 1] = ps;
+      }
+      if (HIN && has_halo) {
+        T rh = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; i++) rh += hv[i];
+        sm.rho[slot][hm + HM][hx + 1] = rh;
+        sm.psi[slot][hm + HM][hx + 1] = psi_of(rh, rho0);
       }
     }
     __syncthreads();
@@ -590,8 +603,8 @@ struct StepBlock {
     // TMe) over lx in [0, TXe)
     const int ncol = TMe + 2 * HM;
     const int nh = 2 * ncol + (HM ? 2 * TXe : 0);
-    const int h = (int)threadIdx.x - NI;
-    has_halo = !interior && h < nh;
+    const int h = HIN ? (int)threadIdx.x : (int)threadIdx.x - NI;
+    has_halo = (HIN || !interior) && h < nh;
     hx = 0;
     hm = 0;
     if (has_halo) {
