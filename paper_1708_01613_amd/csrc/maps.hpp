@@ -565,6 +565,7 @@ __global__ __launch_bounds__(BFS_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int lay
   using H = HaloRows<T>;
   constexpr int PER = T::CELLS / BFS_NT;
   __shared__ unsigned long long fm[H::NR];
+  __shared__ unsigned long long om[H::NR];
   __shared__ unsigned fe[H::NR];
   const MapDims d = m.d;
   const int ntx = (d.nx + 63) / 64, ntm = (d.nm + T::TM - 1) / T::TM;
@@ -572,19 +573,6 @@ __global__ __launch_bounds__(BFS_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int lay
   const int x0 = (b % ntx) * 64, m0 = ((b / ntx) % ntm) * T::TM, z0 = (b / (ntx * ntm)) * T::TZ;
   const int lx = threadIdx.x & 63;
   const int x = x0 + lx;
-  unsigned cidx[PER];
-  bool open[PER];
-  bool any = false;
-#pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int r = (int)(threadIdx.x >> 6) + k * (BFS_NT / 64);
-    const int mm_ = m0 + r % T::TM, z = z0 + r / T::TM;
-    const bool in = x < d.nx && mm_ < d.nm && z < d.nz;
-    cidx[k] = in ? (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z) : 0u;
-    open[k] = in && m.dist[cidx[k]] == 255;
-    any |= open[k];
-  }
-  if (!__syncthreads_or(any)) return;  // block-uniform
   const H hr(d, x0);
   const uint8_t prev = (uint8_t)(layer - 1);
   uint8_t va[H::RPW], ve[H::RPW];
@@ -598,20 +586,38 @@ __global__ __launch_bounds__(BFS_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int lay
     }
   }
   // frontier bits of the halo rows: bit l of fm[row] is the cell x0 + l,
-  // bits 0 and 1 of fe[row] the cells x0 - 1 and x0 + 64
+  // bits 0 and 1 of fe[row] the cells x0 - 1 and x0 + 64; bit l of om[row]:
+  // cell x0 + l is not reached yet (the tile's own rows are halo rows too,
+  // so one round of loads serves both)
 #pragma unroll
   for (int j = 0; j < H::RPW; j++) {
     if (hr.row(j) >= H::NR) continue;  // wave-uniform
     const unsigned long long bm = __ballot(va[j] == prev);
     const unsigned long long be = __ballot(hr.lane < 2 && ve[j] == prev);
+    const unsigned long long bo = __ballot(va[j] == 255);
     if (hr.lane == 0) {
       fm[hr.row(j)] = bm;
       fe[hr.row(j)] = (unsigned)be;
+      om[hr.row(j)] = bo;
     }
   }
   __syncthreads();
-  const AxisStep sx(x < d.nx ? x : 0, d.nx, 1);
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  unsigned cidx[PER];
+  bool open[PER];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int r = wv + k * (BFS_NT / 64);
+    const int mm_ = m0 + r % T::TM, z = z0 + r / T::TM;
+    const bool in = x < d.nx && mm_ < d.nm && z < d.nz;
+    cidx[k] = in ? (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z) : 0u;
+    const int row = (r % T::TM + T::HM) + T::LM * (r / T::TM + 1);
+    open[k] = in && ((om[row] >> lx) & 1ull);
+    any |= open[k];
+  }
+  if (!__syncthreads_or(any)) return;  // block-uniform
+  const AxisStep sx(x < d.nx ? x : 0, d.nx, 1);
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int r = wv + k * (BFS_NT / 64);
