@@ -127,7 +127,7 @@ template <class L, class T>
 __global__ __launch_bounds__(MAP_NT) void k_rupture_batch(const StepArgs* __restrict__ tab,
                                                           const int* __restrict__ first, int nmem) {
   const int k = batch_member(first, nmem, blockIdx.x);
-  const StepArgs a = tab[k];
+  const StepArgs& a = tab[k];  // read in place: a local copy would live in scratch
   rupture_cells<L, T>(a, blockIdx.x - first[k], first[k + 1] - first[k]);
 }
 

@@ -384,7 +384,7 @@ static __global__ __launch_bounds__(FIN_NT) void k_step_finish_batch(const StepA
                                                               const int* __restrict__ first) {
   __shared__ double red[FIN_NT / 64][4];
   const int k = blockIdx.x;
-  const StepArgs a = tab[k];
+  const StepArgs& a = tab[k];  // read in place: a local copy would live in scratch
   step_finish(a, first[k + 1] - first[k], red);
 }
 
@@ -664,7 +664,7 @@ __global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF>::NT)) void k_step_bat
   using SB = StepBlock<L, S, TX, TM, BUF>;
   __shared__ typename SB::Smem sm;
   const int k = batch_member(first, nmem, blockIdx.x);
-  const StepArgs a = tab[k];
+  const StepArgs& a = tab[k];  // read in place: a local copy would live in scratch
   if (a.ctl->stopped) return;
   SB blk(a, sm);
   blk.run(blockIdx.x - first[k], first[k + 1] - first[k]);
