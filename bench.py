@@ -71,6 +71,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+class _Skipped(Exception):
+    pass
+
+
 def measured_traffic():
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -161,14 +165,14 @@ def main():
     ap.add_argument("--tile", type=int, default=-1, help="fixed tile variant (default: autotune)")
     ap.add_argument("--lz", type=int, default=0)
     ap.add_argument("--xcd", type=int, default=-1)
-    ap.add_argument("--no-forms", action="store_true", help="skip the batched and served measurements")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched, served and 2-D foam measurements")
     ap.add_argument("--ensemble-steps", type=int, default=10000)
     ap.add_argument("--serve-jobs", type=int, default=48)
     ap.add_argument("--serve-steps", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU slab decomposition is a design, not code)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -233,6 +237,43 @@ def main():
         torch.cuda.empty_cache()
     except Exception as exc:  # a variant failing must not hide the main line
         variants["d3q19_f16s_kernel"] = {"error": str(exc)}
+    # the 2-D foam-growth workload: D2Q9 1024^2 FP32, film on, bubble labels
+    # and the size histogram read back every 500 steps (whole path, then the
+    # step kernel alone); measured with the other workloads (not under
+    # --no-forms), always with its own autotuned tile
+    try:
+        if args.no_forms:
+            raise _Skipped()
+        p2, nuc2, _ = inputs.config_foam2d()
+        n2 = p2["nx"] * p2["ny"]
+        s2 = foamlbm.Sim(**p2)
+        s2.set_nuclei(nuc2)
+        s2.autotune(reps=3)
+        s2.step(20)
+        torch.cuda.synchronize()
+        steps2, every = 2000, 500
+        t0 = time.perf_counter()
+        for _ in range(steps2 // every):
+            s2.step(every)
+            _, nb2 = s2.labels()
+            s2.histogram(64, 1.0)
+        torch.cuda.synchronize()
+        w2 = time.perf_counter() - t0
+        ms2 = s2.time_steps(nk, refresh=False, kernel=True)[1] / nk
+        t2 = s2.tuning()
+        variants["d2q9_1024_foam"] = {
+            "steps": steps2, "labels_every": every, "MLUPS": round(n2 * steps2 / w2 / 1e6, 1),
+            "n_bubbles": nb2, "kernel_ms": round(ms2, 4),
+            "kernel_GBs_algorithmic": round(BYTES_PER_UPDATE[("d2q9", "f32")] * n2 / (ms2 * 1e-3) / 1e9, 1),
+            "kernel": (f"k_step<D2Q9K,SF32,{t2['tile_x']},{t2['tile_m']}>" if t2["tile_x"]
+                       else "k_psi+k_collide<D2Q9K,SF32>")}
+        log(f"d2q9 1024^2 foam: {variants['d2q9_1024_foam']['MLUPS']:.0f} MLUPS, step kernel {ms2:.4f} ms")
+        del s2
+        torch.cuda.empty_cache()
+    except _Skipped:
+        pass
+    except Exception as exc:
+        variants["d2q9_1024_foam"] = {"error": str(exc)}
 
     forms = None if args.no_forms else batched_and_served(args)
     cpu = None if args.no_cpu else cpu_baseline()
