@@ -96,6 +96,22 @@ def uniform(seed, idx):
     return _load().or_uniform(int(seed), int(idx))
 
 
+def match_labels(old, new):
+    """Overlap of two bubble labellings of one lattice (coalescence tracking
+    for the bubble statistics of Sec. 5): for every pair (old bubble a, new
+    bubble b) that share at least one cell, (a, b, number of shared cells),
+    sorted by (a, b).  Label 0 is liquid.  The definition written out: count
+    the cells that are gas in both labellings by their label pair."""
+    old = np.asarray(old, np.int64).reshape(-1)
+    new = np.asarray(new, np.int64).reshape(-1)
+    assert old.shape == new.shape
+    both = (old > 0) & (new > 0)
+    pairs, counts = np.unique(np.stack([old[both], new[both]], axis=1), axis=0, return_counts=True)
+    if pairs.size == 0:
+        return np.zeros((0, 3), np.int64)
+    return np.concatenate([pairs, counts[:, None]], axis=1).astype(np.int64)
+
+
 def lattice(kind):
     q = 9 if kind == 0 else 19
     e = np.zeros(3 * q, np.int32)
