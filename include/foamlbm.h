@@ -183,6 +183,19 @@ int flb_get_maps(flb_ctx* ctx, int32_t* label, int32_t* owner, int32_t* owner2, 
  * 2 sqrt(A/pi) (D2Q9) or (6V/pi)^(1/3) (D3Q19) in lattice units, bin
  * floor(d / bin_width), last bin open-ended.  counts[nbins]. */
 int flb_get_histogram(flb_ctx* ctx, int32_t nbins, double bin_width, int64_t* counts, int32_t* n_bubbles);
+/* Overlap of an earlier bubble labelling with the current one, for tracking
+ * coalescence between snapshots (the bubble statistics of Sec. 5 taken over
+ * time).  old_labels: n == nx*ny*nz labels (x fastest, 0 = liquid) as
+ * flb_get_labels returned them earlier; the current labels are those
+ * flb_get_labels would return now (*n_bubbles receives their count).  For
+ * every pair (old bubble a, current bubble b) that share at least one cell,
+ * pairs[3k .. 3k+2] = (a, b, shared cells), sorted by (a, b); up to cap pairs
+ * are written and *n_pairs is their total (call again with cap >= *n_pairs for
+ * all of them).  A current bubble paired with two or more old ones is a
+ * coalescence; an old one paired with two or more current ones split.
+ * FLB_EINVAL on a negative label.  Synchronises the stream. */
+int flb_match_labels(flb_ctx* ctx, const int32_t* old_labels, size_t n, int64_t* pairs, int64_t cap,
+                     int64_t* n_pairs, int32_t* n_bubbles);
 
 /* Rupture log: up to cap records of 3 x int64 (step, k, k2), k < k2: a
  * barrier link between bubbles k and k2 (labels of the refresh in force) met

@@ -403,6 +403,70 @@ int flb_get_histogram(flb_ctx* c, int32_t nbins, double bin_width, int64_t* coun
   return FLB_OK;
 }
 
+int flb_match_labels(flb_ctx* c, const int32_t* old_labels, size_t n, int64_t* pairs, int64_t cap, int64_t* n_pairs,
+                     int32_t* n_bubbles) {
+  if (!c || !old_labels || !n_pairs || (cap > 0 && !pairs)) return fail(FLB_EINVAL, "NULL argument");
+  if (n != (size_t)c->N) return fail(FLB_EINVAL, "n must be nx*ny*nz = %lld", c->N);
+  if (cap < 0) return fail(FLB_EINVAL, "cap must be >= 0");
+  long long n_old = 0;
+  for (size_t k = 0; k < n; k++) {
+    if (old_labels[k] < 0) return fail(FLB_EINVAL, "old_labels[%zu] = %d is negative", k, old_labels[k]);
+    n_old = std::max<long long>(n_old, old_labels[k]);
+  }
+  int rc = FLB_DISPATCH(c, label_query, c, false);
+  if (rc) return rc;
+  int nb = 0;
+  HIPCHK(hipMemcpyAsync(&nb, &c->qctl->n_bubbles, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  int* dold = (int*)c->qd;  // the query field buffer (4 N doubles) holds the old labels
+  int* dflag = (int*)(c->qd + c->N);
+  HIPCHK(hipMemcpyAsync(dold, old_labels, sizeof(int) * n, hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  // a table of at least twice the pairs two labellings of this size usually
+  // overlap in; doubled until every pair finds a slot
+  long long want = 1024;
+  while (want < 2 * (n_old + nb) + 1024) want *= 2;
+  std::vector<unsigned long long> hk, hc;
+  for (;;) {
+    if (want > c->qtab_cap) {
+      c->qtab = (unsigned long long*)c->dalloc(sizeof(unsigned long long) * 2 * (size_t)want);
+      if (!c->qtab) return fail(FLB_ENOMEM, "label-overlap table allocation failed");
+      c->qtab_cap = want;
+    }
+    unsigned long long* keys = c->qtab;
+    unsigned long long* counts = c->qtab + want;
+    HIPCHK(hipMemsetAsync(keys, 0xff, sizeof(unsigned long long) * (size_t)want, c->st));
+    HIPCHK(hipMemsetAsync(counts, 0, sizeof(unsigned long long) * (size_t)want, c->st));
+    HIPCHK(hipMemsetAsync(dflag, 0, sizeof(int), c->st));
+    hipLaunchKernelGGL(k_match_pairs, dim3(grid_for(c->N, 256)), dim3(256), 0, c->st, dold, c->qlabel, c->N, keys,
+                       counts, (unsigned)(want - 1), dflag);
+    HIPCHK(hipGetLastError());
+    int over = 0;
+    hk.resize((size_t)want);
+    hc.resize((size_t)want);
+    HIPCHK(hipMemcpyAsync(hk.data(), keys, sizeof(unsigned long long) * (size_t)want, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(hc.data(), counts, sizeof(unsigned long long) * (size_t)want, hipMemcpyDeviceToHost,
+                          c->st));
+    HIPCHK(hipMemcpyAsync(&over, dflag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (!over) break;
+    if (want >= (long long)1 << 31) return fail(FLB_ENOMEM, "label-overlap table would exceed 2^31 slots");
+    want *= 2;
+  }
+  std::vector<std::pair<unsigned long long, unsigned long long>> found;
+  for (size_t k = 0; k < hk.size(); k++)
+    if (hk[k] != kMatchEmpty) found.emplace_back(hk[k], hc[k]);
+  std::sort(found.begin(), found.end());
+  const int64_t m = (int64_t)found.size();
+  for (int64_t k = 0; k < std::min(m, cap); k++) {
+    pairs[3 * k] = (int64_t)(found[k].first >> 32);
+    pairs[3 * k + 1] = (int64_t)(found[k].first & 0xffffffffu);
+    pairs[3 * k + 2] = (int64_t)found[k].second;
+  }
+  *n_pairs = m;
+  if (n_bubbles) *n_bubbles = nb;
+  return FLB_OK;
+}
+
 int flb_get_rupture_events(flb_ctx* c, int64_t* out, int64_t cap, int64_t* n) {
   if (!c || !n || (cap > 0 && !out)) return fail(FLB_EINVAL, "NULL argument");
   if (cap < 0) return fail(FLB_EINVAL, "cap must be >= 0");

@@ -182,4 +182,52 @@ static __global__ void k_histogram(const unsigned long long* sizes, const int* n
   }
 }
 
+// ---- overlap of two labellings (coalescence tracking, Sec. 5) ----
+// Every cell that is gas in both labellings adds one to the count of its
+// (old label, new label) pair in an open-addressing table of `mask + 1`
+// slots (keys kMatchEmpty when free).  Along a wavefront, equal pairs come in
+// runs (bubbles are contiguous in x); the first lane of a run adds the run's
+// length, so a bubble costs one atomic per row segment.  A key probes at most
+// every slot once; one that finds no room sets *overflow (the host retries
+// with a larger table).
+constexpr unsigned long long kMatchEmpty = ~0ull;
+
+static __global__ __launch_bounds__(256) void k_match_pairs(const int* __restrict__ old_label,
+                                                            const int* __restrict__ new_label, long long N,
+                                                            unsigned long long* keys, unsigned long long* counts,
+                                                            unsigned mask, int* overflow) {
+  const int lane = threadIdx.x & 63;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  // wave-uniform loop: the run detection below needs the whole wavefront
+  for (long long base = blockIdx.x * (long long)blockDim.x + (threadIdx.x & ~63); base < N; base += stride) {
+    const long long c = base + lane;
+    int a = 0, b = 0;
+    if (c < N) {
+      a = old_label[c];
+      b = new_label[c];
+    }
+    const bool valid = a > 0 && b > 0;
+    const bool first = run_head(a, b);  // every lane takes part in the shuffle
+    const bool head = valid && first;
+    // lanes where a run (or a gap of cells that are not gas in both) starts
+    const unsigned long long starts = __ballot(!valid || head);
+    if (!head) continue;
+    const unsigned long long above = lane == 63 ? 0ull : starts >> (lane + 1);
+    const unsigned long long len = above ? (unsigned long long)__builtin_ctzll(above) + 1ull : (unsigned long long)(64 - lane);
+    const unsigned long long key = ((unsigned long long)(unsigned)a << 32) | (unsigned)b;
+    unsigned h = (unsigned)((key * 0x9E3779B97F4A7C15ull) >> 32) & mask;
+    bool placed = false;
+    for (unsigned probe = 0; probe <= mask; probe++) {
+      const unsigned long long prev = atomicCAS(&keys[h], kMatchEmpty, key);
+      if (prev == kMatchEmpty || prev == key) {
+        atomicAdd(&counts[h], len);
+        placed = true;
+        break;
+      }
+      h = (h + 1) & mask;
+    }
+    if (!placed) atomicExch(overflow, 1);
+  }
+}
+
 }  // namespace flb

@@ -221,6 +221,8 @@ struct flb_ctx {
   unsigned long long* qhist = nullptr;
   int qhist_cap = 0;
   double* qtot = nullptr;  // 4 doubles
+  unsigned long long* qtab = nullptr;  // label-overlap table: qtab_cap keys, then qtab_cap counts
+  long long qtab_cap = 0;
   long long launched = 0;
   bool in_batch = false;   // owned by a batch (flb_destroy refuses it)
   std::vector<void*> allocs;

@@ -102,6 +102,8 @@ _SIGS = {
     "flb_label_field": (C.c_int, [_CTX, _D, C.c_size_t, _I, C.POINTER(C.c_int32)]),
     "flb_get_maps": (C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     "flb_get_histogram": (C.c_int, [_CTX, C.c_int32, C.c_double, _L, C.POINTER(C.c_int32)]),
+    "flb_match_labels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int32)]),
     "flb_get_rupture_events": (C.c_int, [_CTX, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
     "flb_set_tuning": (C.c_int, [_CTX, C.c_int32, C.c_int32, C.c_int32]),
     "flb_get_tuning": (C.c_int, [_CTX] + [C.POINTER(C.c_int32)] * 6),
@@ -302,6 +304,19 @@ class Sim:
         nb = C.c_int32(0)
         check(flb_get_histogram(self.h, nbins, float(bin_width), counts, C.byref(nb)), "flb_get_histogram")
         return counts, nb.value
+
+    def match_labels(self, old_labels):
+        """(old label, current label, shared cells) for every pair of bubbles of an
+        earlier labelling and the current one that overlap, sorted; and the
+        current bubble count."""
+        old = np.ascontiguousarray(np.asarray(old_labels, np.int32).reshape(-1))
+        n, nb = C.c_int64(0), C.c_int32(0)
+        check(flb_match_labels(self.h, old.ctypes.data_as(C.c_void_p), old.size, None, 0, C.byref(n), C.byref(nb)),
+              "flb_match_labels")
+        out = np.zeros(3 * max(n.value, 1), np.int64)
+        check(flb_match_labels(self.h, old.ctypes.data_as(C.c_void_p), old.size, out.ctypes.data_as(C.c_void_p),
+                               n.value, C.byref(n), C.byref(nb)), "flb_match_labels")
+        return out[: 3 * n.value].reshape(-1, 3), nb.value
 
     def rupture_events(self):
         n = C.c_int64(0)
