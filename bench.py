@@ -175,6 +175,7 @@ def main():
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     from paper_1708_01613_amd import foamlbm, inputs
@@ -237,9 +238,9 @@ def main():
         torch.cuda.empty_cache()
     except Exception as exc:  # a variant failing must not hide the main line
         variants["d3q19_f16s_kernel"] = {"error": str(exc)}
-    # the 2-D foam-growth workload: D2Q9 1024^2 FP32, film on, bubble labels
-    # and the size histogram read back every 500 steps (whole path, then the
-    # step kernel alone); measured with the other workloads (not under
+    # the 2-D foam-growth workload: D2Q9 1024^2 FP32, film on, bubble labels,
+    # the size histogram and the overlap with the previous labels read back
+    # every 500 steps (whole path, then the step kernel alone); measured with the other workloads (not under
     # --no-forms), always with its own autotuned tile
     try:
         if args.no_forms:
@@ -252,18 +253,26 @@ def main():
         s2.step(20)
         torch.cuda.synchronize()
         steps2, every = 2000, 500
+        prev, _ = s2.labels()
+        merges = 0
         t0 = time.perf_counter()
         for _ in range(steps2 // every):
             s2.step(every)
-            _, nb2 = s2.labels()
+            lab2, nb2 = s2.labels()
             s2.histogram(64, 1.0)
+            # coalescence tracking: current bubbles overlapping two or more
+            # bubbles of the previous snapshot
+            pairs, _ = s2.match_labels(prev)
+            if len(pairs):
+                merges += int((np.bincount(pairs[:, 1]) >= 2).sum())
+            prev = lab2
         torch.cuda.synchronize()
         w2 = time.perf_counter() - t0
         ms2 = s2.time_steps(nk, refresh=False, kernel=True)[1] / nk
         t2 = s2.tuning()
         variants["d2q9_1024_foam"] = {
             "steps": steps2, "labels_every": every, "MLUPS": round(n2 * steps2 / w2 / 1e6, 1),
-            "n_bubbles": nb2, "kernel_ms": round(ms2, 4),
+            "n_bubbles": nb2, "coalescences": merges, "kernel_ms": round(ms2, 4),
             "kernel_GBs_algorithmic": round(BYTES_PER_UPDATE[("d2q9", "f32")] * n2 / (ms2 * 1e-3) / 1e9, 1),
             "kernel": (f"k_step<D2Q9K,SF32,{t2['tile_x']},{t2['tile_m']}>" if t2["tile_x"]
                        else "k_psi+k_collide<D2Q9K,SF32>")}
