@@ -207,3 +207,37 @@ def test_foam3d_256_full_horizon(flb, storage, drift):
     assert st["step"] == 5000
     assert nb0 > 1000 and nbs[-1] < nb0 // 10
     assert st["n_ruptures"] > 100 and len(g.rupture_events()) >= st["n_ruptures"]
+
+
+def test_foam2d_1024_full_horizon(flb):
+    # the 2-D foam-growth workload over its whole 20000 steps, with labels,
+    # histogram and the overlap with the previous labels every 500 steps:
+    # mass drift (measured +3.4e-6 at step 20000; bound about 9x), coarsening
+    # from the 200 nuclei, ruptures, coalescences tracked, and each overlap
+    # table equal to the oracle's definition every 2000 steps
+    from oracle import match_labels
+
+    params, nuc, steps = inputs.config_foam2d()
+    _say(f"D2Q9 1024^2 f32, {steps} steps, statistics and overlap tables every 500")
+    g = flb.Sim(**params)
+    g.set_nuclei(nuc)
+    g.autotune(reps=2)
+    m0 = g.stats()["mass"]
+    prev, nb0 = g.labels()
+    merges = 0
+    for k in range(steps // 500):
+        g.step(500)
+        st = g.stats()
+        assert np.isfinite(st["mass"]) and abs(st["mass"] - m0) / m0 <= 3e-5
+        lab, nb = g.labels()
+        counts, nbh = g.histogram(64, 1.0)
+        assert nbh == nb and int(counts.sum()) == nb
+        pairs, nbm = g.match_labels(prev)
+        assert nbm == nb and int(pairs[:, 2].sum()) == int(np.sum((prev > 0) & (lab > 0)))
+        if k % 4 == 3:
+            assert np.array_equal(pairs, match_labels(prev, lab))
+        merges += int((np.bincount(pairs[:, 1]) >= 2).sum()) if len(pairs) else 0
+        prev = lab
+    assert st["step"] == steps
+    assert nb0 == 200 and nb < 20
+    assert st["n_ruptures"] > 5 and merges >= 5
