@@ -241,3 +241,33 @@ def test_foam2d_1024_full_horizon(flb):
     assert st["step"] == steps
     assert nb0 == 200 and nb < 20
     assert st["n_ruptures"] > 5 and merges >= 5
+
+
+def test_ensemble_full_horizon(flb):
+    # the 64-lattice ensemble over its whole 10000 steps in one batch (graph
+    # replay, autotuned): every member finishes with a finite, conserved mass,
+    # and sampled members (the smallest, the largest and two more) equal their
+    # solo runs bit for bit
+    members, _ = inputs.config_ensemble()
+    steps = 10000
+    _say(f"ensemble of {len(members)} D2Q9 lattices, {steps} steps batched, 4 members solo")
+    b = flb.Batch([p for p, _ in members])
+    for k, (_, nuc) in enumerate(members):
+        b.members[k].set_nuclei(nuc)
+    m0 = [b.members[k].stats()["mass"] for k in range(len(members))]
+    b.autotune(reps=2)
+    b.step(steps)
+    b.synchronize()
+    for k in range(len(members)):
+        st = b.members[k].stats()
+        assert st["step"] == steps and np.isfinite(st["mass"])
+        assert abs(st["mass"] - m0[k]) / m0[k] <= 1e-4, k
+    cells = [p["nx"] * p["ny"] for p, _ in members]
+    pick = sorted({int(np.argmin(cells)), int(np.argmax(cells)), 7, 40})
+    for k in pick:
+        p, nuc = members[k]
+        s = flb.Sim(**p)
+        s.set_nuclei(nuc)
+        s.step(steps)
+        assert np.array_equal(b.members[k].populations(), s.populations()), k
+        assert b.members[k].stats()["n_ruptures"] == s.stats()["n_ruptures"], k
