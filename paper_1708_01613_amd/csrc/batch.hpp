@@ -338,7 +338,7 @@ inline flb_batch* batch_view(const std::vector<flb_ctx*>& ms, hipStream_t st, co
   b->D = ms[0]->D;
   b->storage = ms[0]->p.storage;
   b->tile = b->D == 2 ? 0 : 1;
-  b->target = b->D == 2 ? 2048 : 512;
+  b->target = b->D == 2 ? 4096 : 512;
   return b;
 }
 
