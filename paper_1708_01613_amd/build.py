@@ -26,6 +26,20 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     return out
 
 
+PROBE = os.path.join(HERE, "copy_probe")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile the standalone copy-bandwidth probe (csrc/copy_probe.hip) to
+    `copy_probe` beside this file: the practical HBM ceilings by access width."""
+    cmd = ["hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", os.path.join(HERE, "csrc", "copy_probe.hip"), "-o", PROBE]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return PROBE
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
