@@ -19,6 +19,8 @@
  *   4. force          F = -G psi(x) sum_i w_i psi~(x+e_i) e_i    (Sec. 2.1.2, Eq. shanchen3)
  *   5. velocity shift u_eq = (j + tau F) / rho                  (Sec. 2.1.5, final-velocity equations, read with /rho)
  *   6. BGK collision  f* = f - (f - f^eq(rho, u_eq)) / tau       (Sec. 2.1.1, collision equation; f^eq equation)
+ *   6b. bubble growth (optional) the gas-release law dp/dt = A (dn/dt) / N at
+ *                     each of the N domain gas points             (Sec. 2.1.3, Fig. Mainflowchart "Bubble growth")
  *   7. streaming      f_i(x + e_i) = f*_i(x), periodic           (Sec. 2.1.1, streaming equation)
  *   8. rupture test   d2 p0 / dn2 >= 0 on barrier links          (Sec. 2.1.5, eta_m equation; Sec. 4)
  *
@@ -79,6 +81,11 @@ typedef struct {
   int32_t rupture_warmup; /* first step at which the rupture test runs */
   int32_t on_rupture;     /* 0: remove pair barrier; 1: stop after the step */
   int32_t velocity_mode;  /* 0: j/rho; 1: (j + F/2)/rho */
+  int32_t refresh_src;    /* film maps label 0: rho^n, the state entering step n (default);
+                             1: rho^(n-1), the state entering the previous step */
+  int32_t growth_on;      /* 1: gas release at the domain gas points (Sec. 2.1.3) */
+  double gas_A;           /* A of the gas-release law (lattice units) */
+  double gas_dndt;        /* dn/dt of the gas-release law (lattice units, per step) */
 } or_params;
 
 typedef struct {
@@ -112,6 +119,9 @@ typedef struct {
   int64_t n_ruptures;
   int64_t step;
   int32_t stopped;
+  /* domain gas points: the cells of the nuclei (Sec. 2.1.3), set at nucleation */
+  unsigned char* src;
+  long n_src;
 } or_sim;
 
 /* ------------------------------------------------------------------ */
@@ -216,10 +226,11 @@ or_sim* or_create(const or_params* p) {
   s->mask = (uint32_t*)calloc(N, sizeof(uint32_t));
   s->alias = (int32_t*)calloc(N + 2, sizeof(int32_t));
   s->alias_old = (int32_t*)calloc(N + 2, sizeof(int32_t));
+  s->src = (unsigned char*)calloc(N, 1);
   s->evcap = 1024;
   s->ev = (int64_t*)calloc(3 * (size_t)s->evcap, sizeof(int64_t));
   if (!s->f || !s->fpost || !s->rho || !s->rho_prev || !s->psi || !s->force || !s->label || !s->label_old ||
-      !s->owner || !s->owner2 || !s->dist || !s->mask || !s->alias || !s->alias_old || !s->ev) {
+      !s->owner || !s->owner2 || !s->dist || !s->mask || !s->alias || !s->alias_old || !s->src || !s->ev) {
     or_destroy(s);
     return NULL;
   }
@@ -231,7 +242,7 @@ void or_destroy(or_sim* s) {
   if (!s) return;
   free(s->f); free(s->fpost); free(s->rho); free(s->rho_prev); free(s->psi); free(s->force);
   free(s->label); free(s->label_old); free(s->owner); free(s->owner2); free(s->dist); free(s->mask);
-  free(s->alias); free(s->alias_old); free(s->ev);
+  free(s->alias); free(s->alias_old); free(s->src); free(s->ev);
   free(s);
 }
 
@@ -300,6 +311,12 @@ int or_set_nuclei(or_sim* s, const double* nuc, int32_t n) {
     double rho = inside[c] ? p->rho_gas : p->rho_liquid;
     rho += p->noise_amp * (2.0 * or_uniform(p->seed, (uint64_t)c) - 1.0);
     for (int i = 0; i < s->Q; i++) s->f[(long)i * N + c] = s->w[i] * rho;
+  }
+  /* the nucleus cells are the domain gas points that release gas (Sec. 2.1.3) */
+  s->n_src = 0;
+  for (long c = 0; c < N; c++) {
+    s->src[c] = inside[c];
+    s->n_src += inside[c];
   }
   free(inside);
   s->have_prev = 0;
@@ -523,10 +540,12 @@ static void one_step(or_sim* s) {
   double* jz = jy + N;
 
   compute_moments(s, jx, jy, jz);                       /* 1, 2 */
-  /* 3: maps refreshed at steps n = 0 (mod k_own) from the density of the  */
-  /* previous step, rho^(n-1), when that step was taken from the current  */
-  /* state; from rho^n at n = 0 and after the state was replaced (R12)     */
-  if (p->film_on && s->step % p->k_own == 0) refresh_maps(s, s->have_prev ? s->rho_prev : s->rho);
+  /* 3: maps refreshed at steps n = 0 (mod k_own) from rho^n, the density   */
+  /* of the state entering the step (refresh_src 0), or from rho^(n-1),    */
+  /* that of the previous step when it was taken from the current state    */
+  /* (refresh_src 1; rho^n at n = 0 and after the state was replaced) (R12) */
+  if (p->film_on && s->step % p->k_own == 0)
+    refresh_maps(s, (p->refresh_src == 1 && s->have_prev) ? s->rho_prev : s->rho);
   compute_force(s, p->film_on);                         /* 4 */
 
 #pragma omp parallel for schedule(static)
@@ -542,6 +561,20 @@ static void one_step(or_sim* s) {
       double feq = s->w[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
       double fi = s->f[(long)i * N + c];
       s->fpost[(long)i * N + c] = fi - (fi - feq) / p->tau;
+    }
+  }
+
+  /* 6b: bubble growth (Sec. 2.1.3).  Each of the N domain gas points gets   */
+  /* the pressure increment dp = A (dn/dt) / N in this step, taken as the  */
+  /* ideal-gas density increment drho = dp / c_s^2 = 3 dp and added        */
+  /* isotropically, w_i drho to population i: the cell gains exactly drho  */
+  /* of mass and no momentum (R25).                                         */
+  if (p->growth_on && s->n_src > 0) {
+    double dp = p->gas_A * p->gas_dndt / (double)s->n_src;
+    double drho = 3.0 * dp;
+    for (long c = 0; c < N; c++) {
+      if (!s->src[c]) continue;
+      for (int i = 0; i < Q; i++) s->fpost[(long)i * N + c] += s->w[i] * drho;
     }
   }
 
@@ -678,6 +711,29 @@ void or_stats(or_sim* s, double* mass, double* mom) {
 }
 
 int64_t or_n_ruptures(const or_sim* s) { return s->n_ruptures; }
+
+/* domain gas points (the cells of the nuclei, Sec. 2.1.3): out[N] 0/1 (may */
+/* be NULL); returns their number N of the gas-release law                  */
+long or_gas_points(const or_sim* s, unsigned char* out) {
+  if (out) memcpy(out, s->src, (size_t)s->N);
+  return s->n_src;
+}
+
+/* bulk pressure p0 = rho/3 + (G/6) psi^2 of the current state (Sec. 2.1.2, */
+/* Eq. Pequ), the quantity plotted across a film (Sec. 4, Fig. plot)        */
+void or_pressure(or_sim* s, double* out) {
+  compute_moments(s, NULL, NULL, NULL);
+  for (long c = 0; c < s->N; c++) out[c] = or_p0(s->rho[c], s->p.G, s->p.rho0);
+}
+
+/* Test hook: unite the alias classes of labels a and b of the maps in      */
+/* force, as a rupture between them would.  Returns 1 if they were apart.   */
+int or_alias_unite(or_sim* s, int32_t a, int32_t b) {
+  if (!s->maps_valid || a < 1 || b < 1 || a > s->nb || b > s->nb) return -1;
+  int r = uf_union(s->alias, a, b);
+  s->n_ruptures += r;
+  return r;
+}
 
 /* raw rupture events (step, k, k2) with k < k2, in the order found */
 long or_events(const or_sim* s, int64_t* out, long cap) {

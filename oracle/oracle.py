@@ -25,13 +25,16 @@ class _Params(C.Structure):
         ("rho_th", C.c_double),
         ("psi_bar_mode", C.c_int32), ("rupture_warmup", C.c_int32),
         ("on_rupture", C.c_int32), ("velocity_mode", C.c_int32),
+        ("refresh_src", C.c_int32), ("growth_on", C.c_int32),
+        ("gas_A", C.c_double), ("gas_dndt", C.c_double),
     ]
 
 
 DEFAULTS = dict(lattice=0, nx=16, ny=16, nz=1, tau=1.0, G=-5.0, rho0=1.0,
                 rho_liquid=2.0, rho_gas=0.15, noise_amp=0.01, seed=1,
                 film_on=0, k_own=10, zone_width=6, rho_th=math.log(2.0),
-                psi_bar_mode=0, rupture_warmup=200, on_rupture=0, velocity_mode=0)
+                psi_bar_mode=0, rupture_warmup=200, on_rupture=0, velocity_mode=0,
+                refresh_src=0, growth_on=0, gas_A=0.0, gas_dndt=0.0)
 
 _P = C.c_void_p
 _D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -72,6 +75,9 @@ def _load():
         "or_events": (C.c_long, [_P, _L, C.c_long]),
         "or_histogram": (None, [_P, _I, C.c_int32, C.c_int32, C.c_double, _L, _L]),
         "or_p0": (C.c_double, [C.c_double, C.c_double, C.c_double]),
+        "or_gas_points": (C.c_long, [_P, C.c_void_p]),
+        "or_pressure": (None, [_P, _D]),
+        "or_alias_unite": (C.c_int, [_P, C.c_int32, C.c_int32]),
         "or_threads": (C.c_int, []),
         "or_splitmix64": (C.c_uint64, [C.c_uint64]),
         "or_uniform": (C.c_double, [C.c_uint64, C.c_uint64]),
@@ -231,6 +237,26 @@ class OracleSim:
         return dict(label=label.reshape(s), owner=owner.reshape(s), owner2=owner2.reshape(s),
                     dist=dist.reshape(s),
                     mask=mask.reshape(s), alias_root=alias[: nb + 1].copy(), n_bubbles=nb)
+
+    def pressure(self):
+        """Bulk pressure p0(rho) of the current state (Eq. Pequ)."""
+        out = np.zeros(self.N, np.float64)
+        self._lib.or_pressure(self._h, out)
+        return out.reshape(self.shape)
+
+    def gas_points(self):
+        """The domain gas points of the gas-release law (the nucleus cells) and their number N."""
+        out = np.zeros(self.N, np.uint8)
+        n = self._lib.or_gas_points(self._h, out.ctypes.data_as(C.c_void_p))
+        return out.reshape(self.shape).astype(bool), n
+
+    def alias_unite(self, a, b):
+        """Test hook: unite the alias classes of labels a and b of the maps in
+        force, as a rupture between them would (1 if they were apart)."""
+        r = self._lib.or_alias_unite(self._h, int(a), int(b))
+        if r < 0:
+            raise ValueError("no maps in force, or a label out of range")
+        return r
 
     def stats(self):
         m = C.c_double(0.0)

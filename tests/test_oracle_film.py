@@ -252,8 +252,57 @@ def test_rupture_then_merge():
     # the two bubbles stay aliased across relabelling until they join
     s2, _ = _two_bubbles(1, 50, steps=200)
     m = s2.maps()
-    if m["n_bubbles"] == 2:
-        assert m["alias_root"][1] == m["alias_root"][2]
+    assert m["n_bubbles"] == 2 and m["alias_root"][1] == m["alias_root"][2]
+
+
+def _disc(gas, cx, cy, r):
+    y, x = np.mgrid[0:gas.shape[0], 0:gas.shape[1]]
+    gas[(x - cx) ** 2 + (y - cy) ** 2 <= r * r] = True
+
+
+def test_alias_carry_hand_built_relabel():
+    # R21 (Sec. 2.1.5, the film between a pair is removed once they are one
+    # bubble): at a refresh, new bubbles whose gas overlaps old bubbles of one
+    # alias class become aliases of each other.  Hand-built: old A ~ B by a
+    # rupture; new P overlaps A and Q overlaps B (carried: P ~ Q); old C splits
+    # into C1, C2 (split: C1 ~ C2); old F and H merge into M (merge: one
+    # label, in a class of its own); E' overlaps only E, N overlaps nothing
+    # (non-aliased neighbours).  The films P|Q and C1|C2 then carry no barrier
+    # links, the film M|N does.
+    ny, nx = 40, 72
+    old = np.zeros((ny, nx), bool)
+    for cx, cy, r in ((7, 8, 2), (15, 8, 2), (32, 8, 4), (60, 8, 3), (10, 28, 3), (20, 28, 3)):
+        _disc(old, cx, cy, r)
+    new = np.zeros((ny, nx), bool)
+    for cx, cy, r in ((8, 8, 2), (14, 8, 2), (30, 8, 2), (36, 8, 2), (60, 8, 2), (26, 28, 2)):
+        _disc(new, cx, cy, r)
+    new[26:31, 8:23] = True  # M covers F and H
+    kw = dict(G=-5.5, film_on=1, k_own=1, zone_width=6, rupture_warmup=10 ** 9)
+    s = _sim_with_density(0, np.where(old, 0.1, 2.0)[None], **kw)
+    s.step(1)  # refresh at step 0 labels the old field
+    m1 = s.maps()
+    lab1 = m1["label"]
+    assert m1["n_bubbles"] == 6
+    A, B = lab1[8, 7], lab1[8, 15]
+    assert s.alias_unite(A, B) == 1  # as a rupture of the A|B film would
+    e, w = lattice(0)
+    s.set_populations(w[:, None, None] * np.where(new, 0.1, 2.0)[None])
+    s.step(1)  # refresh at step 1 labels the new field and carries the aliases
+    m2 = s.maps()
+    lab, root = m2["label"], m2["alias_root"]
+    ref, nb = bf.bfs_labels(new[None], 0)
+    assert np.array_equal(lab.reshape(ref.shape), ref) and nb == 7
+    P, Q, C1, C2, E2, M, N = (lab[8, 8], lab[8, 14], lab[8, 30], lab[8, 36], lab[8, 60], lab[28, 15], lab[28, 26])
+    assert len({P, Q, C1, C2, E2, M, N}) == 7 and 0 not in (P, Q, C1, C2, E2, M, N)
+    assert root[P] == root[Q]                      # carried through the rupture of A|B
+    assert root[C1] == root[C2]                    # split of one old bubble
+    classes = {root[P], root[C1], root[M], root[E2], root[N]}
+    assert len(classes) == 5                       # merge, E', N each in a class of their own
+    assert root[M] == M and root[E2] == E2 and root[N] == N
+    mask = m2["mask"]
+    assert mask[8, 11] == 0 and mask[8, 10] == 0 and mask[8, 12] == 0   # P|Q film: no barrier
+    assert mask[8, 33] == 0 and mask[8, 32] == 0 and mask[8, 34] == 0   # C1|C2 film: no barrier
+    assert mask[28, 23] != 0                                          # M|N film: barrier
 
 
 def test_stop_on_first_rupture():
@@ -314,18 +363,22 @@ def test_barrier_force_substitution(mode):
     assert np.abs(F - Fplain).max() > 1e-3
 
 
+@pytest.mark.parametrize("src", [0, 1])
 @pytest.mark.parametrize("kind,dims", [(0, (1, 40, 48)), (1, (14, 15, 16))])
-def test_refresh_labels_density_of_previous_step(kind, dims):
-    # R12: the maps refreshed at step n > 0 (n = 0 mod k_own) label the gas of
-    # the density that entered step n - 1; at n = 0, and after the state was
-    # replaced, the density of the current state
+def test_refresh_labels_density_reading(kind, dims, src):
+    # R12: the maps refreshed at step n (n = 0 mod k_own) label the gas of the
+    # density that enters step n (refresh_src 0, the default), or of the one
+    # that entered step n - 1 (refresh_src 1); at n = 0, and after the state
+    # was replaced, both label the density of the current state.  Each is
+    # checked against a brute-force flood fill of that density < ln 2.
     nz, ny, nx = dims
     rng = np.random.default_rng(3 + kind)
     nuc = [[rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz) if kind else 0.0, rng.uniform(2.5, 4.5)]
            for _ in range(6)]
     k = 3
-    s = OracleSim(lattice=kind, nx=nx, ny=ny, nz=nz, G=-5.5, rho_liquid=2.3, rho_gas=0.11, film_on=1, k_own=k,
-                  zone_width=6, rupture_warmup=10 ** 6, seed=2)
+    kw = dict(lattice=kind, nx=nx, ny=ny, nz=nz, G=-5.5, rho_liquid=2.3, rho_gas=0.11, film_on=1, k_own=k,
+              zone_width=6, rupture_warmup=10 ** 6, seed=2, refresh_src=src)
+    s = OracleSim(**kw)
     s.set_nuclei(nuc)
     s.step(1)
     gas0 = (s.maps()["label"] > 0).reshape(dims)
@@ -337,12 +390,11 @@ def test_refresh_labels_density_of_previous_step(kind, dims):
     cur = s.density().reshape(dims)  # enters step k, at which the maps are refreshed
     s.step(1)
     lab = s.maps()["label"].reshape(dims)
-    ref, nb = bf.bfs_labels(prev < math.log(2.0), kind)
+    ref, nb = bf.bfs_labels((cur if src == 0 else prev) < math.log(2.0), kind)
     assert np.array_equal(lab, ref) and nb > 1
     assert not np.array_equal(prev < math.log(2.0), cur < math.log(2.0))  # the two readings differ here
     # after the state is replaced the next refresh labels the new state
-    s2 = OracleSim(lattice=kind, nx=nx, ny=ny, nz=nz, G=-5.5, rho_liquid=2.3, rho_gas=0.11, film_on=1, k_own=k,
-                   zone_width=6, rupture_warmup=10 ** 6, seed=2)
+    s2 = OracleSim(**kw)
     s2.set_nuclei(nuc)
     s2.step(k)
     s2.set_populations(s2.populations())

@@ -219,6 +219,40 @@ def test_force_closed_form_sinusoid(kind):
         assert np.abs(F[2] - ez).max() < 1e-13
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_velocity_query_closed_form(kind, mode):
+    # The reported velocity (Eq. vel_dens): mode 0 is j / rho, mode 1 is
+    # (j + F/2) / rho.  Populations w_i rho (1 + 3 e_i.U) carry density rho and
+    # momentum rho U exactly (the lattice's second moment is I/3), and with a
+    # separable sinusoidal psi the force has the closed form of the force pin
+    # above, so both modes are known per component without the oracle's sums.
+    nx, ny, nz = (30, 26, 1) if kind == 0 else (18, 16, 14)
+    kx, ky, kz = 2 * np.pi / nx, 2 * np.pi / ny, 2 * np.pi / nz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    A, B, C = 0.2, 0.15, (0.1 if kind == 1 else 0.0)
+    psi = 0.5 + A * np.sin(kx * x) + B * np.sin(ky * y) + C * np.sin(kz * z)
+    rho = _psi_to_rho(psi)
+    U = [0.03 * np.cos(ky * y), -0.02 * np.sin(kx * x) + 0.01, (0.015 * np.cos(kx * x) if kind == 1 else 0 * x)]
+    e, w = lattice(kind)
+    D = 2 if kind == 0 else 3
+    eu = sum(e[:, k].reshape(-1, 1, 1, 1) * U[k][None] for k in range(D))
+    f = w.reshape(-1, 1, 1, 1) * rho[None] * (1 + 3 * eu)
+    G = -5.0
+    s = OracleSim(lattice=kind, nx=nx, ny=ny, nz=nz, G=G, velocity_mode=mode)
+    s.set_populations(f if kind == 1 else f[:, 0])
+    got = s.velocity()
+    F = [-G * psi * (1 / 3) * A * np.sin(kx) * np.cos(kx * x), -G * psi * (1 / 3) * B * np.sin(ky) * np.cos(ky * y),
+         -G * psi * (1 / 3) * C * np.sin(kz) * np.cos(kz * z)]
+    for k in range(D):
+        ref = U[k] + (0.5 * F[k] / rho if mode == 1 else 0.0)
+        if kind == 0:
+            ref = ref[0]
+        assert np.abs(got[k] - ref).max() < 1e-14, (k, np.abs(got[k] - ref).max())
+    if mode == 1:  # the force term is not negligible here
+        assert max(np.abs(0.5 * F[k] / rho).max() for k in range(D)) > 1e-2
+
+
 def test_force_taylor_coefficients_match_paper():
     # F = -G psi (a psi' + b psi''') + O(k^5) with (a, b) printed in Eq. tylor
     tc = GOLD["taylor_coefficients"]
