@@ -6,7 +6,9 @@ Workload: D3Q19 256^3, FP32 populations, tau 1, G -5.5, 2000 seeded nuclei
 steps), inputs resident in HBM.  A "step" is one time step of the whole hot
 path: fused step kernel (pull, moments, psi, force with barrier, velocity
 shift, BGK, store, FP64 partials, rupture test) plus its share of the map
-refreshes.  Prints one JSON line.
+refreshes.  The lattice is first advanced past the step at which the rupture
+test starts (untimed), so every timed step runs the whole path.  Prints one
+JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -34,7 +36,9 @@ def log(msg):
 def cpu_baseline(steps=10):
     """The FP64 oracle on the host cores over a bounded sample of the same
     workload: the same 256^3 lattice and nuclei, film on, the first `steps`
-    steps (including the map refresh at step 0)."""
+    steps (including the map refresh at step 0) on all cores; then one more
+    step (not a refresh step) on one thread.  Returns the report and the
+    oracle, whose state after `steps` steps the per-field errors use."""
     from oracle import OracleSim
     from paper_1708_01613_amd import inputs
 
@@ -48,10 +52,51 @@ def cpu_baseline(steps=10):
     s.step(steps)
     dt = time.perf_counter() - t0
     threads = s.threads()
+    rho, u = s.density(), s.velocity()
+    rep = {"value": round(n ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"D3Q19 {n}^3 FP64 oracle, the same {len(nuc)} nuclei, film on, first {steps} steps "
+                     f"incl. one map refresh, {dt:.1f} s on {threads} OpenMP threads"}
+    if steps % 10:
+        return rep, (rho, u)
+    # one thread, one step that is not a refresh step (step steps + 1)
+    s.step(1)
+    s.set_threads(1)
+    t0 = time.perf_counter()
+    s.step(1)
+    d1 = time.perf_counter() - t0
+    s.set_threads(threads)
+    rep["single_thread"] = {"value": round(n ** 3 / d1 / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                            "sample": f"one step without a map refresh (step {steps + 1}), {d1:.1f} s"}
     del s
-    return {"value": round(n ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"D3Q19 {n}^3 FP64 oracle, the same {len(nuc)} nuclei, film on, first {steps} steps "
-                      f"incl. one map refresh, {dt:.1f} s on {threads} OpenMP threads"}
+    return rep, (rho, u)
+
+
+def spinodals(G):
+    """Gas and liquid spinodal densities of p0 = rho/3 + (G/6) psi^2 with
+    psi = 1 - exp(-rho): dp0/drho = 0 at exp(-rho) = (1 -+ sqrt(1 + 4/G)) / 2."""
+    import math
+
+    y = math.sqrt(1.0 + 4.0 / G)
+    return -math.log((1.0 + y) / 2.0), -math.log((1.0 - y) / 2.0)
+
+
+def field_errors(sim_rho, sim_u, o_rho, o_u, G):
+    """Density (max relative) and velocity (max absolute over the largest
+    oracle speed) errors against the FP64 oracle, per phase: gas below the
+    gas spinodal, liquid above the liquid spinodal, interface between."""
+    import numpy as np
+
+    rg, rl = spinodals(G)
+    umax = float(np.abs(o_u).max())
+    phases = {"gas": o_rho < rg, "interface": (o_rho >= rg) & (o_rho <= rl), "liquid": o_rho > rl}
+    out = {}
+    for name, sel in phases.items():
+        if not sel.any():
+            continue
+        out[name] = {"cells": int(sel.sum()),
+                     "density_max_rel": float(np.max(np.abs(sim_rho[sel] - o_rho[sel]) / o_rho[sel])),
+                     "velocity_max_abs_over_umax": float(np.max(np.abs(sim_u[:, sel] - o_u[:, sel])) / umax)}
+    return out
 
 
 # rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the step kernel on this
@@ -136,39 +181,21 @@ def batched_and_served(args):
     return out
 
 
-def copy_ceiling(torch, nbytes=1 << 30, reps=20):
-    """Device-to-device copy rate (read + write bytes / time) of a 1 GiB
-    buffer: the practical HBM ceiling the stencil is compared with."""
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    a.fill_(1.0)
-    b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del a, b
-    torch.cuda.empty_cache()
-    return 2 * nbytes / (ms * 1e-3) / 1e9
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="cube side (the workload is 256)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the per-field errors")
     ap.add_argument("--tile", type=int, default=-1, help="fixed tile variant (default: autotune)")
     ap.add_argument("--lz", type=int, default=0)
     ap.add_argument("--xcd", type=int, default=-1)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched, served and 2-D foam measurements")
     ap.add_argument("--ensemble-steps", type=int, default=10000)
     ap.add_argument("--serve-jobs", type=int, default=48)
-    ap.add_argument("--serve-steps", type=int, default=1000)
+    ap.add_argument("--serve-steps", type=int, default=5000)
+    ap.add_argument("--foam2d-steps", type=int, default=20000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library has no "
@@ -195,16 +222,30 @@ def main():
     tun = sim.tuning()
     log(f"tuning {tun}")
 
+    # untimed set-up: past the step at which the rupture test starts (its
+    # first evaluation unites a burst of pairs), so that every warmup and
+    # timed step runs the rupture test and the mask pruning as well
+    setup = params["rupture_warmup"] + 1
+    sim.step(setup)
     sim.step(args.warmup)
     torch.cuda.synchronize()
-    log("warmup done")
+    r0 = sim.stats()["n_ruptures"]
+    log(f"set-up {setup} + warmup {args.warmup} steps done")
     t0 = time.perf_counter()
     sim.step(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
     mlups = N * args.steps / wall / 1e6
-    log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.3f} ms/step, {mlups:.0f} MLUPS")
+    st = sim.stats()
+    log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.3f} ms/step, {mlups:.0f} MLUPS, "
+        f"{st['n_ruptures'] - r0} ruptures in the window")
+
+    # the same number of steps again with every phase bracketed by HIP events
+    # on the library's stream: the share of each kernel group in a step
+    ph_total, ph = sim.time_phases(args.steps)
+    shares = {k: {"ms_per_step": round(v / args.steps, 4), "share": round(v / ph_total, 4)} for k, v in ph.items()}
+    log("phases " + ", ".join(f"{k} {v['ms_per_step']:.4f} ms" for k, v in shares.items()))
 
     # dominant kernel alone: every step-kernel launch bracketed by HIP events
     # on the library's stream (maps frozen, so no refresh runs in between)
@@ -214,14 +255,13 @@ def main():
     bpu = BYTES_PER_UPDATE[("d3q19", "f32")]
     achieved = bpu * N / (kms * 1e-3) / 1e9
     log(f"step kernel {kms:.4f} ms, {achieved:.0f} GB/s algorithmic")
-    st = sim.stats()
-    copy = copy_ceiling(torch)
-    log(f"device copy ceiling {copy:.0f} GB/s")
+    del sim
+    torch.cuda.empty_cache()
+    copy = foamlbm.copy_bandwidth(1 << 30, reps=10)
+    log(f"device copy ceiling (16-byte accesses) {copy:.0f} GB/s")
     # FP16-shifted storage variant of the same workload (kernel time only)
     variants = {}
     try:
-        del sim
-        torch.cuda.empty_cache()
         p16 = dict(params, storage="f16s")
         s16 = foamlbm.Sim(**p16)
         s16.set_nuclei(nuc)
@@ -240,8 +280,8 @@ def main():
         variants["d3q19_f16s_kernel"] = {"error": str(exc)}
     # the 2-D foam-growth workload: D2Q9 1024^2 FP32, film on, bubble labels,
     # the size histogram and the overlap with the previous labels read back
-    # every 500 steps (whole path, then the step kernel alone); measured with the other workloads (not under
-    # --no-forms), always with its own autotuned tile
+    # every 500 steps over its full horizon (whole path, then the step kernel
+    # alone), always with its own autotuned tile
     try:
         if args.no_forms:
             raise _Skipped()
@@ -250,9 +290,8 @@ def main():
         s2 = foamlbm.Sim(**p2)
         s2.set_nuclei(nuc2)
         s2.autotune(reps=3)
-        s2.step(20)
         torch.cuda.synchronize()
-        steps2, every = 2000, 500
+        steps2, every = args.foam2d_steps, 500
         prev, _ = s2.labels()
         merges = 0
         t0 = time.perf_counter()
@@ -270,13 +309,15 @@ def main():
         w2 = time.perf_counter() - t0
         ms2 = s2.time_steps(nk, refresh=False, kernel=True)[1] / nk
         t2 = s2.tuning()
+        st2 = s2.stats()
         variants["d2q9_1024_foam"] = {
             "steps": steps2, "labels_every": every, "MLUPS": round(n2 * steps2 / w2 / 1e6, 1),
-            "n_bubbles": nb2, "coalescences": merges, "kernel_ms": round(ms2, 4),
+            "n_bubbles": nb2, "coalescences": merges, "n_ruptures": st2["n_ruptures"], "kernel_ms": round(ms2, 4),
             "kernel_GBs_algorithmic": round(BYTES_PER_UPDATE[("d2q9", "f32")] * n2 / (ms2 * 1e-3) / 1e9, 1),
             "kernel": (f"k_step<D2Q9K,SF32,{t2['tile_x']},{t2['tile_m']}>" if t2["tile_x"]
                        else "k_psi+k_collide<D2Q9K,SF32>")}
-        log(f"d2q9 1024^2 foam: {variants['d2q9_1024_foam']['MLUPS']:.0f} MLUPS, step kernel {ms2:.4f} ms")
+        log(f"d2q9 1024^2 foam: {variants['d2q9_1024_foam']['MLUPS']:.0f} MLUPS over {steps2} steps, "
+            f"step kernel {ms2:.4f} ms")
         del s2
         torch.cuda.empty_cache()
     except _Skipped:
@@ -285,7 +326,23 @@ def main():
         variants["d2q9_1024_foam"] = {"error": str(exc)}
 
     forms = None if args.no_forms else batched_and_served(args)
-    cpu = None if args.no_cpu else cpu_baseline()
+    cpu, errors = None, None
+    if not args.no_cpu:
+        cpu, (o_rho, o_u) = cpu_baseline()
+        log(f"cpu oracle {cpu['value']} MLUPS on {cpu['cores']} threads; "
+            f"one thread {cpu.get('single_thread', {}).get('value')} MLUPS")
+        # per-field errors of the two storage forms against the oracle after
+        # the same 10 steps from the same initial state
+        errors = {"steps": 10, "phases": "gas: rho below the gas spinodal; liquid: above the liquid spinodal; "
+                                         "interface: between (spinodals of p0 at G)"}
+        for stor in ("f32", "f16s"):
+            g = foamlbm.Sim(**dict(params, storage=stor))
+            g.set_nuclei(nuc)
+            g.step(10)
+            errors[stor] = field_errors(g.density(), g.velocity(), o_rho, o_u, params["G"])
+            del g
+            torch.cuda.empty_cache()
+        log("per-field errors " + json.dumps(errors))
     line = {
         "metric": "MLUPS & %HBM peak (D3Q19 256^3 FP32); batched MLUPS + p50/p99 latency",
         "value": round(mlups, 1),
@@ -300,8 +357,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"D3Q19 {params['nx']}^3 FP32 foam, {len(nuc)} uniform nuclei r~U[3,8], G=-5.5, "
-                               "tau=1, film barrier + rupture on, maps every 10 steps",
-                   "cells": N, "tuning": tun},
+                               "tau=1, film barrier + rupture on, maps every 10 steps from the current density",
+                   "cells": N, "tuning": tun, "setup_steps": setup,
+                   "timed_steps_from": setup + args.warmup},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": (f"k_step<D3Q19K,SF32,{tun['tile_x']},{tun['tile_m']}>" if tun["tile_x"]
@@ -309,10 +367,12 @@ def main():
                      "bytes_per_update": bpu, "design_bytes_per_update": DESIGN_BYTES,
                      "copy_ceiling_GBs": round(copy, 1), "frac_of_copy": round(achieved / copy, 4)},
         "cpu_baseline": cpu,
+        "phases": shares,
+        "field_errors": errors,
         "variants": variants,
         "batched_and_served": forms,
         "checks": {"mass": st["mass"], "n_bubbles": st["n_bubbles"], "n_ruptures": st["n_ruptures"],
-                   "step": st["step"]},
+                   "ruptures_in_window": st["n_ruptures"] - r0, "step": st["step"]},
     }
     print(json.dumps(line), flush=True)
 

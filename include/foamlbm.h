@@ -14,7 +14,9 @@
  *   u_eq = (j + tau F) / rho                             (Sec. 2.1.5, final-velocity equations)
  *   f*_i = f_i - (f_i - f_i^eq(rho, u_eq)) / tau          (collision and f^eq equations)
  *   f_i(x + e_i, n + 1) = f*_i(x)                        (streaming equation)
- * and, on active barrier links from step rupture_warmup on, the FP64 test
+ * optionally the gas release of Sec. 2.1.3 (dp/dt = A (dn/dt) / N at each of
+ * the N domain gas points, added as the density 3 A (dn/dt) / N after the
+ * collision), and, on active barrier links from step rupture_warmup on, the FP64 test
  * p0(rho(x+e_i)) - 2 p0(rho(x)) + p0(rho(x-e_i)) >= 0 with
  * p0 = rho/3 + (G/6) psi^2 (Eq. Pequ; eta_m equation), which removes the
  * barrier between that pair of bubbles from step n+1 on.
@@ -88,7 +90,7 @@ typedef struct {
   uint64_t seed;         /* seed of the counter-based noise */
   int32_t film_on;       /* 1: film barrier and rupture test on */
   int32_t k_own;         /* film maps are rebuilt before every step n with n % k_own == 0 (>= 1),
-                            from the density that entered step n - 1 (step 0: the initial one) */
+                            from the density refresh_src names */
   int32_t zone_width;    /* largest film thickness (lattice links) that carries a barrier, 1..15 */
   double rho_th;         /* gas iff rho < rho_th (default ln 2, the critical density) */
   int32_t psi_bar_mode;  /* psi on barrier links: 0 = psi(rho_liquid), 1 = psi(x) */
@@ -100,11 +102,30 @@ typedef struct {
                              evaluation with a rigorous error bound already
                              proves the second difference negative; 0 always
                              evaluates in FP64.  Both take identical decisions. */
+  int32_t refresh_src;   /* density a map refresh before step n labels (Sec. 2.1.5 evaluates
+                            the bubbles continuously): 0 (default) = rho^n, the state entering
+                            step n, formed by one pass over the populations; 1 = rho^(n-1), the
+                            density that entered step n - 1, which that step's kernel stores
+                            (no extra pass; the maps lag the state by one step; at n = 0 and
+                            after the state was replaced, the current density) */
+  int32_t growth_on;     /* 1: gas release (Sec. 2.1.3, the bubble-growth box of
+                            Fig. Mainflowchart) at the domain gas points, the cells inside a
+                            nucleus at flb_set_nuclei; each gains the density 3 dp per step,
+                            dp = gas_A * gas_dndt / N for N gas points, as w_i 3 dp on
+                            population i after the collision (mass, no momentum) */
+  double gas_A;          /* A of the gas-release law dp/dt = A (dn/dt) / N, lattice units */
+  double gas_dndt;       /* dn/dt of the gas-release law, lattice units per step */
+  double f16_rho_ref;    /* FLB_F16S: population i is stored as FP16 of f_i - w_i f16_rho_ref
+                            (default 1: f_i - w_i).  One FP16 rounding then costs about
+                            2^-12 |rho - f16_rho_ref| / rho of f_i at density rho, so a value
+                            between the phase densities (their harmonic mean balances the
+                            relative error of both phases) suits two-phase runs; >= 0 */
 } flb_params;
 
 /* Fills p with defaults: D2Q9 F32 64x64x1, tau 1, G -5, rho0 1, rho_liquid 2,
  * rho_gas 0.15, noise 0.01, seed 1, film off, k_own 10, zone_width 6,
- * rho_th ln 2, psi_bar_mode 0, rupture_warmup 200, on_rupture 0, velocity 0. */
+ * rho_th ln 2, psi_bar_mode 0, rupture_warmup 200, on_rupture 0, velocity 0,
+ * rupture_filter 1, refresh_src 0, growth off (A = dn/dt = 0), f16_rho_ref 1. */
 void flb_default_params(flb_params* p);
 
 /* A gas nucleus: centre (cell centres at integer coordinates) and radius. */
@@ -137,9 +158,8 @@ int flb_set_nuclei(flb_ctx* ctx, const flb_nucleus* nuc, int32_t n);
 
 /* Advance nsteps >= 0 steps (asynchronous on the context stream).  Film maps
  * are rebuilt before each step n with n % k_own == 0 (from the density that
- * entered step n - 1, or the current one at n = 0 and after flb_set_populations
- * or flb_set_nuclei).  After a rupture with
- * on_rupture == 1 the remaining steps are no-ops. */
+ * refresh_src names).  After a rupture with on_rupture == 1 the remaining
+ * steps are no-ops. */
 int flb_step(flb_ctx* ctx, int64_t nsteps);
 
 /* Density of the current state into host_out[n], n == nx*ny*nz (FP64). */
@@ -148,6 +168,18 @@ int flb_get_density(flb_ctx* ctx, double* host_out, size_t n);
 /* Velocity of the current state into host_out[n], n == D*nx*ny*nz, component
  * planes (x plane, then y, then z for D3Q19); mode per params.velocity_mode. */
 int flb_get_velocity(flb_ctx* ctx, double* host_out, size_t n);
+
+/* Bulk pressure p0 = rho/3 + (G/6) psi^2 (Eq. Pequ) of the current state
+ * into host_out[n], n == nx*ny*nz (FP64): the pressure the paper plots across
+ * a film (Sec. 4, Fig. plot) and whose second difference the rupture test
+ * reads. */
+int flb_get_pressure(flb_ctx* ctx, double* host_out, size_t n);
+
+/* Domain gas points of the gas-release source (growth_on; the cells inside a
+ * nucleus at the last flb_set_nuclei): out[n] receives 1 at a gas point, 0
+ * elsewhere (n == nx*ny*nz; out may be NULL), *n_points their number N (0
+ * with growth off). */
+int flb_get_gas_points(flb_ctx* ctx, uint8_t* out, size_t n, int64_t* n_points);
 
 /* Populations of the current state, host_out[n], n == Q*nx*ny*nz, population
  * planes in the order listed above (FP64 values of the stored precision). */
@@ -230,6 +262,20 @@ int flb_autotune(flb_ctx* ctx, int32_t reps, double* best_ms);
  * bracketed by its own pair of events and *kernel_ms receives the sum of
  * those durations, i.e. the time of the step kernel alone. */
 int flb_time_steps(flb_ctx* ctx, int64_t nsteps, int32_t refresh, double* ms, double* kernel_ms);
+
+/* Runs nsteps (0..100000) steps like flb_step and times every phase of each
+ * step with HIP events on the context stream: *ms = elapsed milliseconds,
+ * phase_ms[0] = map refreshes, [1] = step kernel(s), [2] = rupture test and
+ * mask pruning, [3] = the per-step finisher (sums over the steps). */
+int flb_time_phases(flb_ctx* ctx, int64_t nsteps, double* ms, double* phase_ms);
+
+/* Device-copy bandwidth: copies `bytes` (a multiple of 16 in 2^20..2^36)
+ * between two buffers from alloc (NULL: hipMalloc) with 16-byte accesses per
+ * lane, four loads in flight, non-temporal stores, on hip_stream, `reps`
+ * times per grid size, and returns the best read + write rate in *gbs
+ * (GB/s): the practical HBM ceiling of a kernel that reads and writes equal
+ * amounts.  The buffers are freed before return. */
+int flb_copy_bandwidth(const flb_allocator* alloc, void* hip_stream, int64_t bytes, int32_t reps, double* gbs);
 
 /* Checkpoint and resume: flb_save writes the current state (populations,
  * run control, film maps, aliases, rupture log) to a file; flb_load restores

@@ -38,6 +38,9 @@
 #endif
 
 #define OR_MAXQ 19
+/* lattices smaller than this run their per-cell loops on one thread: there
+   the start-up cost of a parallel region exceeds the loop */
+#define OR_OMP_MIN_CELLS 32768
 
 /* ------------------------------------------------------------------ */
 /* Lattices.                                                           */
@@ -152,6 +155,15 @@ int or_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+
+/* Sets the OpenMP threads of later loops (no-op without OpenMP). */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
 #endif
 }
 
@@ -306,7 +318,7 @@ int or_set_nuclei(or_sim* s, const double* nuc, int32_t n) {
           if (in_nucleus(p, x, y, z, nk)) inside[(z * p->ny + y) * p->nx + x] = 1;
         }
   }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
   for (long c = 0; c < N; c++) {
     double rho = inside[c] ? p->rho_gas : p->rho_liquid;
     rho += p->noise_amp * (2.0 * or_uniform(p->seed, (uint64_t)c) - 1.0);
@@ -345,7 +357,7 @@ void or_get_populations(const or_sim* s, double* f) {
 /* ------------------------------------------------------------------ */
 static void compute_moments(or_sim* s, double* jx, double* jy, double* jz) {
   long N = s->N;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
   for (long c = 0; c < N; c++) {
     double r = 0, a = 0, b = 0, d = 0;
     for (int i = 0; i < s->Q; i++) {
@@ -509,7 +521,7 @@ static void compute_force(or_sim* s, int with_film) {
   long N = s->N;
   const or_params* p = &s->p;
   double psi_liq = psi_of(p, p->rho_liquid);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
   for (long c = 0; c < N; c++) {
     double acc[3] = {0, 0, 0};
     for (int i = 1; i < s->Q; i++) {
@@ -548,7 +560,7 @@ static void one_step(or_sim* s) {
     refresh_maps(s, (p->refresh_src == 1 && s->have_prev) ? s->rho_prev : s->rho);
   compute_force(s, p->film_on);                         /* 4 */
 
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
   for (long c = 0; c < N; c++) {
     double rho = s->rho[c];
     double u[3];
@@ -612,7 +624,7 @@ static void one_step(or_sim* s) {
   }
 
   /* 7: pull form of f_i(x + e_i) <- f*_i(x) */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
   for (long c = 0; c < N; c++)
     for (int i = 0; i < Q; i++) s->f[(long)i * N + c] = s->fpost[(long)i * N + nbr(s, c, i, -1)];
 

@@ -79,6 +79,7 @@ def _load():
         "or_pressure": (None, [_P, _D]),
         "or_alias_unite": (C.c_int, [_P, C.c_int32, C.c_int32]),
         "or_threads": (C.c_int, []),
+        "or_set_threads": (None, [C.c_int]),
         "or_splitmix64": (C.c_uint64, [C.c_uint64]),
         "or_uniform": (C.c_double, [C.c_uint64, C.c_uint64]),
     }
@@ -271,6 +272,10 @@ class OracleSim:
     def threads(self):
         """OpenMP threads the oracle runs on."""
         return self._lib.or_threads()
+
+    def set_threads(self, n):
+        """OpenMP threads for the oracle's later loops (process-wide)."""
+        self._lib.or_set_threads(int(n))
 
     def events(self):
         n = self._lib.or_events(self._h, np.zeros(3, np.int64), 0)

@@ -30,6 +30,11 @@ void flb_default_params(flb_params* p) {
   p->on_rupture = 0;
   p->velocity_mode = 0;
   p->rupture_filter = 1;
+  p->refresh_src = 0;
+  p->growth_on = 0;
+  p->gas_A = 0.0;
+  p->gas_dndt = 0.0;
+  p->f16_rho_ref = 1.0;
 }
 
 const char* flb_last_error(void) { return g_err.c_str(); }
@@ -62,7 +67,9 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
   c->geo.block_bytes = p->storage == FLB_F64   ? block_bytes<SF64>(c->Q)
                        : p->storage == FLB_F32 ? block_bytes<SF32>(c->Q)
                                                : block_bytes<SF16S>(c->Q);
+  c->geo.href = (float)p->f16_rho_ref;
   c->fbytes = (size_t)c->geo.nxb * c->md.nm * c->md.nz * c->geo.block_bytes;
+  c->nwords = (long long)c->geo.nxb * c->md.nm * c->md.nz;
   default_tuning(c);
   // the largest block count any tile variant can produce (one plane per
   // segment), which sizes the per-workgroup partials
@@ -106,9 +113,10 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     ok = ok && (c->alias_old = (int*)c->dalloc(sizeof(int) * (size_t)(c->N + 1)));
     ok = ok && (c->rep = (int*)c->dalloc(sizeof(int) * (size_t)(c->N + 1)));
     ok = ok && (c->events = (long long*)c->dalloc(sizeof(long long) * 4 * (size_t)c->ev_cap));
-    c->nwords = (long long)((c->md.nx + 63) / 64) * c->md.nm * c->md.nz;
     ok = ok && (c->bits = (unsigned long long*)c->dalloc(sizeof(unsigned long long) * (size_t)c->nwords));
   }
+  if (ok && p->growth_on)
+    ok = ok && (c->srcw = (unsigned long long*)c->dalloc(sizeof(unsigned long long) * (size_t)c->nwords));
   if (!ok) {
     c->dfree_all();
     delete c;
@@ -118,6 +126,7 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
       hipMemsetAsync(c->qctl, 0, sizeof(Ctl), c->st) != hipSuccess ||
       (p->film_on && hipMemsetAsync(c->flag, 0, (size_t)c->N, c->st) != hipSuccess) ||
       (p->film_on && hipMemsetAsync(c->mask, 0, sizeof(uint32_t) * (size_t)c->N, c->st) != hipSuccess) ||
+      (p->growth_on && hipMemsetAsync(c->srcw, 0, sizeof(unsigned long long) * (size_t)c->nwords, c->st) != hipSuccess) ||
       forget_rho(c) != FLB_OK || hipStreamSynchronize(c->st) != hipSuccess) {
     c->dfree_all();
     delete c;
@@ -148,10 +157,20 @@ int flb_set_nuclei(flb_ctx* c, const flb_nucleus* nuc, int32_t n) {
   }
   HIPCHK(hipMemsetAsync(c->ctl, 0, sizeof(Ctl), c->st));
   if (forget_rho(c)) return FLB_EHIP;
+  // the nucleus cells become the domain gas points of the gas-release source;
+  // their count goes to the run control
+  unsigned long long* nsrc = (unsigned long long*)c->qtot;
+  if (c->srcw) {
+    HIPCHK(hipMemsetAsync(c->srcw, 0, sizeof(unsigned long long) * (size_t)c->nwords, c->st));
+    HIPCHK(hipMemsetAsync(nsrc, 0, sizeof(unsigned long long), c->st));
+  }
   const int B = 256, g = grid_for(c->N, B);
   hipLaunchKernelGGL(k_init_density, dim3(g), dim3(B), 0, c->st, c->qd, c->p.nx, c->p.ny, c->p.nz, c->N, dn, n,
-                     c->p.rho_liquid, c->p.rho_gas, c->p.noise_amp, (unsigned long long)c->p.seed);
+                     c->p.rho_liquid, c->p.rho_gas, c->p.noise_amp, (unsigned long long)c->p.seed, c->srcw,
+                     c->geo.nxb, nsrc);
   HIPCHK(hipGetLastError());
+  if (c->srcw)
+    HIPCHK(hipMemcpyAsync(&c->ctl->n_src, nsrc, sizeof(long long), hipMemcpyDeviceToDevice, c->st));
   int rc = FLB_DISPATCH(c, do_pack, c, c->qd, 0, 0);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(c->st));
@@ -170,31 +189,27 @@ int flb_step(flb_ctx* c, int64_t nsteps) {
   return FLB_DISPATCH(c, do_steps, c, nsteps, true);
 }
 
-int flb_time_steps(flb_ctx* c, int64_t nsteps, int32_t refresh, double* ms, double* kernel_ms) {
-  if (!c || !ms) return fail(FLB_EINVAL, "NULL argument");
-  if (nsteps < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
-  if (kernel_ms && nsteps > 100000) return fail(FLB_EINVAL, "nsteps must be <= 100000 with kernel_ms");
-  // per-launch events for the kernel time, created up front
-  std::vector<hipEvent_t> kev(kernel_ms ? 4 * (size_t)nsteps : 0, nullptr);
+// Runs nsteps steps with optional per-phase events (kPhaseEv per step).
+static int timed_steps(flb_ctx* c, int64_t nsteps, bool refresh, bool phases, double* ms, double ph[4]) {
+  std::vector<hipEvent_t> kev(phases ? kPhaseEv * (size_t)nsteps : 0, nullptr);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   for (size_t k = 0; k < kev.size() && e == hipSuccess; k++) e = hipEventCreate(&kev[k]);
   int rc = FLB_OK;
   if (e == hipSuccess) e = hipEventRecord(e0, c->st);
-  if (e == hipSuccess) rc = FLB_DISPATCH(c, do_steps, c, nsteps, refresh != 0, kernel_ms ? kev.data() : nullptr);
+  if (e == hipSuccess) rc = FLB_DISPATCH(c, do_steps, c, nsteps, refresh, phases ? kev.data() : nullptr);
   if (e == hipSuccess && !rc) e = hipEventRecord(e1, c->st);
   if (e == hipSuccess && !rc) e = hipEventSynchronize(e1);
   float f = 0.f;
   if (e == hipSuccess && !rc) e = hipEventElapsedTime(&f, e0, e1);
-  double ksum = 0.0;
-  const bool two = c->two_pass();
-  for (int64_t s = 0; s < nsteps && kernel_ms && e == hipSuccess && !rc; s++) {
-    float a = 0.f, b = 0.f;
-    e = hipEventElapsedTime(&a, kev[4 * s], kev[4 * s + 1]);
-    if (e == hipSuccess && two) e = hipEventElapsedTime(&b, kev[4 * s + 2], kev[4 * s + 3]);
-    ksum += (double)a + (double)b;
-  }
+  double sum[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t s = 0; s < nsteps && phases && e == hipSuccess && !rc; s++)
+    for (int q = 0; q < 4 && e == hipSuccess; q++) {
+      float a = 0.f;
+      e = hipEventElapsedTime(&a, kev[kPhaseEv * s + q], kev[kPhaseEv * s + q + 1]);
+      sum[q] += (double)a;
+    }
   for (hipEvent_t ev : kev)
     if (ev) (void)hipEventDestroy(ev);
   if (e0) (void)hipEventDestroy(e0);
@@ -202,8 +217,25 @@ int flb_time_steps(flb_ctx* c, int64_t nsteps, int32_t refresh, double* ms, doub
   if (rc) return rc;
   if (e != hipSuccess) return fail(FLB_EHIP, "timing: %s", hipGetErrorString(e));
   *ms = f;
-  if (kernel_ms) *kernel_ms = ksum;
+  if (ph)
+    for (int q = 0; q < 4; q++) ph[q] = sum[q];
   return FLB_OK;
+}
+
+int flb_time_steps(flb_ctx* c, int64_t nsteps, int32_t refresh, double* ms, double* kernel_ms) {
+  if (!c || !ms) return fail(FLB_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(FLB_EINVAL, "nsteps must be >= 0");
+  if (kernel_ms && nsteps > 100000) return fail(FLB_EINVAL, "nsteps must be <= 100000 with kernel_ms");
+  double ph[4];
+  int rc = timed_steps(c, nsteps, refresh != 0, kernel_ms != nullptr, ms, ph);
+  if (!rc && kernel_ms) *kernel_ms = ph[1];
+  return rc;
+}
+
+int flb_time_phases(flb_ctx* c, int64_t nsteps, double* ms, double* phase_ms) {
+  if (!c || !ms || !phase_ms) return fail(FLB_EINVAL, "NULL argument");
+  if (nsteps < 0 || nsteps > 100000) return fail(FLB_EINVAL, "nsteps must be in 0..100000");
+  return timed_steps(c, nsteps, true, true, ms, phase_ms);
 }
 
 int flb_set_tuning(flb_ctx* c, int32_t tile, int32_t lz, int32_t xcd) {
@@ -519,6 +551,95 @@ int flb_get_velocity(flb_ctx* c, double* out, size_t n) {
   return FLB_OK;
 }
 
+int flb_copy_bandwidth(const flb_allocator* alloc, void* hip_stream, int64_t bytes, int32_t reps, double* gbs) {
+  if (!gbs) return fail(FLB_EINVAL, "NULL argument");
+  if (bytes < (1 << 20) || bytes > (1ll << 36) || bytes % 16) return fail(FLB_EINVAL, "bytes must be a multiple of 16 in 2^20..2^36");
+  if (reps < 1 || reps > 1000) return fail(FLB_EINVAL, "reps must be in 1..1000");
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(FLB_EINVAL, "allocator needs alloc and free");
+  hipStream_t st = (hipStream_t)hip_stream;
+  void* buf[2] = {nullptr, nullptr};
+  for (int k = 0; k < 2; k++) {
+    if (alloc) buf[k] = alloc->alloc((size_t)bytes, alloc->user);
+    else if (hipMalloc(&buf[k], (size_t)bytes) != hipSuccess) buf[k] = nullptr;
+  }
+  auto release = [&]() {
+    for (int k = 0; k < 2; k++)
+      if (buf[k]) {
+        if (alloc) alloc->free(buf[k], alloc->user);
+        else (void)hipFree(buf[k]);
+      }
+  };
+  if (!buf[0] || !buf[1]) {
+    release();
+    return fail(FLB_ENOMEM, "copy buffers allocation failed");
+  }
+  const long long n = bytes / 16;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipMemsetAsync(buf[0], 0, (size_t)bytes, st);
+  double best = 0.0;
+  for (int grid : {8192, 32768}) {
+    if (e != hipSuccess) break;
+    auto launch = [&]() {
+      hipLaunchKernelGGL(k_copy16<4>, dim3(grid), dim3(256), 0, st, (const f4v*)buf[0], (f4v*)buf[1], n);
+    };
+    launch();  // warm-up
+    e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && e == hipSuccess; r++) launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && ms > 0.f) best = std::max(best, 2.0 * (double)bytes * reps / ((double)ms * 1e6));
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  release();
+  if (e != hipSuccess) return fail(FLB_EHIP, "copy bandwidth: %s", hipGetErrorString(e));
+  *gbs = best;
+  return FLB_OK;
+}
+
+int flb_get_pressure(flb_ctx* c, double* out, size_t n) {
+  if (!c || !out) return fail(FLB_EINVAL, "NULL argument");
+  if (n != (size_t)c->N) return fail(FLB_EINVAL, "n must be nx*ny*nz = %lld", c->N);
+  int rc = FLB_DISPATCH(c, do_moments, c, false);
+  if (rc) return rc;
+  const int B = 256, g = grid_for(c->N, B);
+  hipLaunchKernelGGL(k_pressure, dim3(g), dim3(B), 0, c->st, c->qd, c->N, c->p.G, c->p.rho0, c->qd + c->N);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(out, c->qd + c->N, sizeof(double) * n, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return FLB_OK;
+}
+
+int flb_get_gas_points(flb_ctx* c, uint8_t* out, size_t n, int64_t* n_points) {
+  if (!c || !n_points) return fail(FLB_EINVAL, "NULL argument");
+  if (out && n != (size_t)c->N) return fail(FLB_EINVAL, "n must be nx*ny*nz = %lld", c->N);
+  Ctl h;
+  int rc = read_ctl(c, &h);
+  if (rc) return rc;
+  *n_points = c->srcw ? h.n_src : 0;
+  if (!out) return FLB_OK;
+  if (!c->srcw) {
+    memset(out, 0, n);
+    return FLB_OK;
+  }
+  std::vector<unsigned long long> w((size_t)c->nwords);
+  HIPCHK(hipMemcpyAsync(w.data(), c->srcw, sizeof(unsigned long long) * w.size(), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  const int nx = c->p.nx, nxb = c->geo.nxb;
+  for (size_t k = 0; k < n; k++) {
+    const size_t row = k / (size_t)nx;
+    const int x = (int)(k - row * nx);
+    out[k] = (uint8_t)((w[(size_t)(x >> 6) + (size_t)nxb * row] >> (x & 63)) & 1ull);
+  }
+  return FLB_OK;
+}
+
 int flb_get_populations(flb_ctx* c, double* out, size_t n) {
   if (!c || !out) return fail(FLB_EINVAL, "NULL argument");
   if (n != (size_t)c->Q * c->N) return fail(FLB_EINVAL, "n must be Q*nx*ny*nz = %lld", c->Q * c->N);
@@ -616,12 +737,16 @@ int file_to_dev(FILE* fp, void* dev, size_t bytes, hipStream_t st) {
 struct CkptArrays {
   std::vector<std::pair<void*, size_t>> v;
   CkptArrays(flb_ctx* c, size_t n_events, size_t n_flagged) {
-    if (!c->p.film_on) return;
+    if (!c->p.film_on) {
+      if (c->srcw) v.push_back({c->srcw, 8 * (size_t)c->nwords});
+      return;
+    }
     const size_t N = (size_t)c->N;
     const size_t tsz = c->p.storage == FLB_F64 ? 8 : 4;
     v = {{c->label, 4 * N},       {c->alias, 4 * (N + 1)}, {c->own, 8 * N},
          {c->dist, N},            {c->flag, N},            {c->mask, 4 * N},
          {c->flist, 4 * n_flagged}, {c->events, 32 * n_events}, {c->rho, tsz * N}};
+    if (c->srcw) v.push_back({c->srcw, 8 * (size_t)c->nwords});
   }
 };
 
@@ -640,7 +765,7 @@ int flb_save(flb_ctx* c, const char* path) {
   CkptHeader hd;
   memset(&hd, 0, sizeof hd);
   memcpy(hd.magic, kCkptMagic, 8);
-  hd.version = 2;
+  hd.version = 3;
   hd.params_size = sizeof(flb_params);
   hd.p = c->p;
   hd.ctl = h;
@@ -665,7 +790,7 @@ int flb_load(flb_ctx* c, const char* path) {
   if (!fp) return fail(FLB_EINVAL, "cannot open %s", path);
   CkptHeader hd;
   int rc = fread(&hd, sizeof hd, 1, fp) == 1 ? FLB_OK : fail(FLB_EINVAL, "not a checkpoint");
-  if (!rc && (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 2 || hd.params_size != sizeof(flb_params)))
+  if (!rc && (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 3 || hd.params_size != sizeof(flb_params)))
     rc = fail(FLB_EINVAL, "not a checkpoint of this library version");
   if (!rc && (memcmp(&hd.p, &c->p, sizeof(flb_params)) != 0 || hd.fbytes != c->fbytes || hd.N != (uint64_t)c->N))
     rc = fail(FLB_EINVAL, "checkpoint parameters differ from the context's");

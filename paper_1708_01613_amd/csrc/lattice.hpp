@@ -58,6 +58,7 @@ struct Geo {
   int nx, nm, nz;  // kernel-coordinate extents
   int nxb;         // blocks per row, ceil(nx / 64)
   unsigned block_bytes;
+  float href;      // FP16-shifted storage: population i is stored as FP16 of f_i - w_i href
 };
 
 // Storage formats: `ct` is the compute type; esz / pofs give the element
@@ -75,8 +76,9 @@ struct SF32 {
   __host__ __device__ static constexpr unsigned esz(int) { return 4; }
   __host__ __device__ static constexpr unsigned pofs(int i) { return 256u * i; }
 };
-// FP16 of the shifted population f_i - w_i for the moving directions, and the
-// rest population (the largest, never streamed) in FP32; compute in FP32.
+// FP16 of the shifted population f_i - w_i href for the moving directions
+// (href = 1: f_i - w_i), and the rest population (the largest, never
+// streamed) in FP32; compute in FP32.
 struct SF16S {
   using ct = float;
   static constexpr bool HALF = true;
@@ -99,14 +101,14 @@ template <class L, class S>
 __device__ inline typename S::ct pop_ld(const void* base, const Geo& g, int i, int x, int m, int z) {
   const char* p = (const char*)base + block_of(g, x, m, z) + S::pofs(i) + (unsigned)(x & 63) * S::esz(i);
   if constexpr (sizeof(typename S::ct) == 8) return *(const double*)p;
-  else if (S::HALF && i > 0) return (float)*(const _Float16*)p + (float)L::w[i];
+  else if (S::HALF && i > 0) return (float)*(const _Float16*)p + (float)L::w[i] * g.href;
   else return *(const float*)p;
 }
 template <class L, class S>
 __device__ inline void pop_st(void* base, const Geo& g, int i, int x, int m, int z, typename S::ct v) {
   char* p = (char*)base + block_of(g, x, m, z) + S::pofs(i) + (unsigned)(x & 63) * S::esz(i);
   if constexpr (sizeof(typename S::ct) == 8) *(double*)p = v;
-  else if (S::HALF && i > 0) *(_Float16*)p = (_Float16)(v - (float)L::w[i]);
+  else if (S::HALF && i > 0) *(_Float16*)p = (_Float16)(v - (float)L::w[i] * g.href);
   else *(float*)p = v;
 }
 
@@ -134,6 +136,7 @@ struct Ctl {
   int nb_old;           // labels of the previous refresh, during a refresh
   int maps_partial;     // 1 while owner/dist stop at the layers the masks need
   long long rho_step;   // the step whose entering densities the rho array holds for every cell (-1: none)
+  long long n_src;      // domain gas points of the gas-release source (cells of the nuclei)
   double mass, mom[3];  // FP64 totals of the state entering the last step
 };
 

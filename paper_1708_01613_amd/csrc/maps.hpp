@@ -933,11 +933,16 @@ __global__ __launch_bounds__(MAP_NT) void k_rho_marks(MAP_KERNEL_PARAMS) {
     const ListCell q(d, c);
     const unsigned mk = m.mask[c] & kLinkBits;
     atomicOr(&m.mask[c], kRhoBit);
+    // the flag byte marks every cell whose mask word is not zero (the step
+    // kernel reads the word only there); racing writers store the same 1
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
       if (!(mk & (1u << i))) continue;
-      atomicOr(&m.mask[q.nb(d, L::ex[i], L::em[i], L::ez[i])], kRhoBit);
-      atomicOr(&m.mask[q.nb(d, -L::ex[i], -L::em[i], -L::ez[i])], kRhoBit);
+      const unsigned yp = q.nb(d, L::ex[i], L::em[i], L::ez[i]), ym = q.nb(d, -L::ex[i], -L::em[i], -L::ez[i]);
+      atomicOr(&m.mask[yp], kRhoBit);
+      atomicOr(&m.mask[ym], kRhoBit);
+      m.flag[yp] = 1;
+      m.flag[ym] = 1;
     }
   });
 }
@@ -1013,8 +1018,7 @@ __device__ __forceinline__ void mask_prune(const PruneArgs& p, unsigned bid, uns
       if (rq.x != rp.x || rq.y != rp.y) keep |= 1u << i;
     }
     if (keep != mk) {
-      p.mask[c] = keep | (word & kRhoBit);
-      p.flag[c] = keep ? 1 : 0;
+      p.mask[c] = keep | (word & kRhoBit);  // a listed cell keeps its density mark, and its flag byte
     }
   });
 }

@@ -15,9 +15,14 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
 // Initial density (Sec. 2.1.3): rho_gas inside any nucleus (periodic minimum
 // image, integer cell centres), rho_liquid elsewhere, plus a (2U - 1) noise.
 // Lattice coordinates (x, y, z); FP64 without contraction so that the inside
-// test rounds exactly like a plain C evaluation.
+// test rounds exactly like a plain C evaluation.  With srcw given, the cells
+// inside a nucleus are also the domain gas points of the gas-release source:
+// their bits are set in srcw (one word per 64-cell row block, the population
+// block order: word x / 64 + nxb * (c / nx)) and counted in *nsrc; both must
+// start at zero.
 static __global__ void k_init_density(double* rho, int nx, int ny, int nz, long long N, const double4* nuc, int nn,
-                               double rl, double rg, double amp, unsigned long long seed) {
+                               double rl, double rg, double amp, unsigned long long seed,
+                               unsigned long long* srcw, int nxb, unsigned long long* nsrc) {
 #pragma clang fp contract(off)
   for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
        c += (long long)gridDim.x * blockDim.x) {
@@ -35,7 +40,41 @@ static __global__ void k_init_density(double* rho, int nx, int ny, int nz, long 
     const unsigned long long h = splitmix64(seed ^ ((unsigned long long)c * 0x9E3779B97F4A7C15ull));
     const double u = (double)(h >> 11) * (1.0 / 9007199254740992.0);
     rho[c] = (inside ? rg : rl) + amp * (2.0 * u - 1.0);
+    if (srcw && inside) {
+      atomicOr(&srcw[(x >> 6) + (long long)nxb * (c / nx)], 1ull << (x & 63));
+      atomicAdd(nsrc, 1ull);
+    }
   }
+}
+
+// Plain device copy dst[i] = src[i] of n 16-byte elements, U loads in flight
+// per lane, grid-stride, non-temporal stores: the practical HBM ceiling of a
+// kernel that reads and writes the same number of bytes, which the step
+// kernel is compared with.
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <int U>
+__global__ __launch_bounds__(256) void k_copy16(const f4v* __restrict__ src, f4v* __restrict__ dst, long long n) {
+  const long long stride = (long long)gridDim.x * 256 * U;
+  for (long long base = (long long)blockIdx.x * 256 * U + threadIdx.x; base < n; base += stride) {
+    f4v v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const long long i = base + (long long)u * 256;
+      if (i < n) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const long long i = base + (long long)u * 256;
+      if (i < n) __builtin_nontemporal_store(v[u], &dst[i]);
+    }
+  }
+}
+
+// Bulk pressure p0 = rho/3 + (G/6) psi^2 (Eq. Pequ) of an FP64 density field.
+static __global__ void k_pressure(const double* rho, long long N, double G, double rho0, double* out) {
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
+       c += (long long)gridDim.x * blockDim.x)
+    out[c] = p0_of(rho[c], G, rho0);
 }
 
 // Write a state into the pull layout: buffer[i][c] holds f_i(c + e_i).

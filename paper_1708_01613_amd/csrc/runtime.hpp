@@ -45,14 +45,21 @@ inline int fail(int code, const char* fmt, ...) {
 // ---------------------------------------------------------------------------
 using StepFn = void (*)(const StepArgs&, int, hipStream_t);
 
-// buffers below 2 GiB use buffer-resource loads with 32-bit offsets
+// buffers below 2 GiB use buffer-resource loads with 32-bit offsets; the
+// gas-release source has a variant of its own
+template <class L, class S, int TX, int TM, bool GROW>
+void launch_step_g(const StepArgs& a, int nblk, hipStream_t s) {
+  if (a.buf_bytes < kBufPathLimit)
+    hipLaunchKernelGGL((k_step<L, S, TX, TM, true, GROW>), dim3(nblk), dim3(StepBlock<L, S, TX, TM, true, GROW>::NT),
+                       0, s, a);
+  else
+    hipLaunchKernelGGL((k_step<L, S, TX, TM, false, GROW>), dim3(nblk),
+                       dim3(StepBlock<L, S, TX, TM, false, GROW>::NT), 0, s, a);
+}
 template <class L, class S, int TX, int TM>
 void launch_step(const StepArgs& a, int nblk, hipStream_t s) {
-  if (a.buf_bytes < kBufPathLimit)
-    hipLaunchKernelGGL((k_step<L, S, TX, TM, true>), dim3(nblk), dim3(StepBlock<L, S, TX, TM, true>::NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_step<L, S, TX, TM, false>), dim3(nblk), dim3(StepBlock<L, S, TX, TM, false>::NT), 0, s,
-                       a);
+  if (a.srcw) launch_step_g<L, S, TX, TM, true>(a, nblk, s);
+  else launch_step_g<L, S, TX, TM, false>(a, nblk, s);
 }
 
 // two-pass path: k_psi then k_collide
@@ -119,11 +126,11 @@ inline size_t ctx_footprint(const flb_params* p) {
   const size_t max_blk = nxb * (size_t)nm * nz;
   size_t t = 2 * r(fbytes) + 2 * r(sizeof(Ctl)) + r(32 * max_blk) + 2 * r(tsz * N) + r(32 * N) + r(32 * 4096) +
              2 * r(4 * N) + r(4 * (N / 1024 + 2)) + r(4 * N) + r(8 * (N + 1));
-  if (p->film_on) {
-    const size_t nwords = nxb * nm * nz;
+  const size_t nwords = nxb * nm * nz;
+  if (p->film_on)
     t += 2 * r(N) + r(4 * N) + r(8 * N) + 2 * r(4 * N) + 3 * r(4 * (N + 1)) + r(32 * 65536) +
          r(4 * N) + r(8 * nwords);
-  }
+  if (p->growth_on) t += r(8 * nwords);
   return t;
 }
 
@@ -207,6 +214,8 @@ struct flb_ctx {
   int* counts = nullptr;
   unsigned long long* bits = nullptr;  // flag words: one bit per cell, set where the cell has barrier links
   long long nwords = 0;                // 64-bit words per bitset
+  unsigned long long* srcw = nullptr;  // gas-release source: bits of the domain gas points (growth_on);
+                                       // their number is ctl->n_src
   long long* events = nullptr;
   unsigned ev_cap = 1u << 16;
   // map-kernel tables: film refresh from the state or the rho array, label
@@ -319,7 +328,12 @@ inline StepArgs step_args(flb_ctx* c) {
   a.rupture_warmup = c->p.rupture_warmup;
   a.on_rupture = c->p.on_rupture;
   a.rupture_filter = c->p.rupture_filter;
-  a.gas_k = c->p.film_on ? c->p.k_own : 0;
+  // refresh_src 1: the step before a refresh stores every density for it
+  a.gas_k = (c->p.film_on && c->p.refresh_src == 1) ? c->p.k_own : 0;
+  if (c->p.growth_on) {
+    a.srcw = c->srcw;  // the kernels read N from the run control
+    a.src_rate = c->p.gas_A * c->p.gas_dndt;
+  }
   a.flag = c->flag;
   a.mask = c->mask;
   a.flist = c->flist;
@@ -542,7 +556,11 @@ int label_query(flb_ctx* c, bool from_field) {
   return map_pipeline<L, S>(from_field ? c->qs_field : c->qs_pop, c->st, from_field ? GAS_FIELD : GAS_POP, false);
 }
 
-// `ev`, if given, holds 4 events per step that bracket the step-kernel launches
+// `ev`, if given, holds kPhaseEv events per step recorded on the context
+// stream: before the refresh (if due), before the step kernel(s), after them,
+// after the rupture test and pruning, and after the finisher; consecutive
+// pairs bracket the four phases of the step
+constexpr int kPhaseEv = 5;
 template <class L, class S>
 int do_steps(flb_ctx* c, int64_t nsteps, bool refresh, hipEvent_t* ev = nullptr) {
   const StepArgs a = step_args(c);
@@ -550,30 +568,26 @@ int do_steps(flb_ctx* c, int64_t nsteps, bool refresh, hipEvent_t* ev = nullptr)
   const StepFn fn = c->tcfg().fn[c->p.storage];
   const StepFn coll = c->tcfg().coll[c->p.storage];
   for (int64_t s = 0; s < nsteps; s++) {
+    hipEvent_t* e = ev ? ev + kPhaseEv * s : nullptr;
     const bool due = refresh && c->p.film_on && c->launched % c->p.k_own == 0;
+    if (e) HIPCHK(hipEventRecord(e[0], c->st));
     if (due) {
       int rc = refresh_maps<L, S>(c);
       if (rc) return rc;
     }
-    if (coll) {
-      if (ev) HIPCHK(hipEventRecord(ev[4 * s], c->st));
-      fn(a, nblk, c->st);  // rho / psi of the current state
-      if (ev) HIPCHK(hipEventRecord(ev[4 * s + 1], c->st));
-      if (ev) HIPCHK(hipEventRecord(ev[4 * s + 2], c->st));
-      coll(a, nblk, c->st);
-      if (ev) HIPCHK(hipEventRecord(ev[4 * s + 3], c->st));
-    } else {
-      if (ev) HIPCHK(hipEventRecord(ev[4 * s], c->st));
-      fn(a, nblk, c->st);
-      if (ev) HIPCHK(hipEventRecord(ev[4 * s + 1], c->st));
-    }
+    if (e) HIPCHK(hipEventRecord(e[1], c->st));
+    fn(a, nblk, c->st);              // fused step, or rho / psi of the two-pass variant
+    if (coll) coll(a, nblk, c->st);  // the two-pass collide
+    if (e) HIPCHK(hipEventRecord(e[2], c->st));
     // rupture test (applies its unions), pruning of united pairs' links,
     // then the finisher, which closes the step
     if (c->p.film_on && c->launched >= c->p.rupture_warmup) {
       hipLaunchKernelGGL((k_rupture<L, typename S::ct>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, a);
       hipLaunchKernelGGL((k_mask_prune<L>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, prune_args(c));
     }
+    if (e) HIPCHK(hipEventRecord(e[3], c->st));
     hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(FIN_NT), 0, c->st, a, nblk);
+    if (e) HIPCHK(hipEventRecord(e[4], c->st));
     c->launched++;
   }
   HIPCHK(hipGetLastError());
@@ -635,6 +649,10 @@ inline int validate(const flb_params* p) {
   if (p->on_rupture != 0 && p->on_rupture != 1) return fail(FLB_EINVAL, "on_rupture must be 0 or 1");
   if (p->velocity_mode != 0 && p->velocity_mode != 1) return fail(FLB_EINVAL, "velocity_mode must be 0 or 1");
   if (p->rupture_filter != 0 && p->rupture_filter != 1) return fail(FLB_EINVAL, "rupture_filter must be 0 or 1");
+  if (p->refresh_src != 0 && p->refresh_src != 1) return fail(FLB_EINVAL, "refresh_src must be 0 or 1");
+  if (p->growth_on != 0 && p->growth_on != 1) return fail(FLB_EINVAL, "growth_on must be 0 or 1");
+  if (!isfinite(p->gas_A) || !isfinite(p->gas_dndt)) return fail(FLB_EINVAL, "non-finite gas-release parameter");
+  if (!(p->f16_rho_ref >= 0.0) || !(p->f16_rho_ref <= 1e4)) return fail(FLB_EINVAL, "f16_rho_ref must be in 0..1e4");
   return FLB_OK;
 }
 

@@ -34,10 +34,14 @@ struct StepArgs {
   int rupture_filter;    // 1: FP32 sign filter before the FP64 rupture test
   int gas_k;             // > 0: a step n with (n + 1) % gas_k == 0 stores every cell's density in rho,
                          // which the film-map refresh at step n + 1 labels
-  const uint8_t* flag;   // per cell: 1 if it has candidate barrier links
+  const uint8_t* flag;   // per cell: 1 where the mask word is not zero (barrier links or kRhoBit)
   const uint32_t* mask;  // per cell: active barrier links (bit i = direction i) and kRhoBit
   const int* flist;      // cells with barrier links at the last refresh (ctl->n_flagged)
   const int2* own;       // per cell: (smallest, largest) nearest bubble label
+  const unsigned long long* srcw;  // gas-release source: one bit per cell (the domain gas points),
+                                   // one word per 64-cell row block (population block order); null: off
+  double src_rate;       // A (dn/dt) of the gas-release law; a step adds the density 3 A (dn/dt) / N
+                         // at each of the ctl->n_src = N domain gas points
   int* alias;            // union-find parents over labels
   unsigned long long buf_bytes;  // bytes of one population buffer
   long long* events;     // rupture log, 4 x int64 per event: step, k, k2, 0
@@ -241,7 +245,7 @@ struct PopIO {
       _Float16 h;
       if (BUF) h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, vo, po, kLdCpol));
       else h = *(const _Float16*)(gs + off + po);
-      return (float)h + (float)L::w[i];
+      return (float)h + (float)L::w[i] * g.href;
     } else {
       if (BUF) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, po, kLdCpol));
       return *(const float*)(gs + off + po);
@@ -260,7 +264,7 @@ struct PopIO {
         *(double*)(gd + off + po) = v;
       }
     } else if (S::HALF && i > 0) {
-      const _Float16 h = (_Float16)(v - (float)L::w[i]);
+      const _Float16 h = (_Float16)(v - (float)L::w[i] * g.href);
       if (BUF) __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), rd, vo, po, kStCpol);
       else *(_Float16*)(gd + off + po) = h;
     } else {
@@ -395,7 +399,7 @@ static __global__ __launch_bounds__(FIN_NT) void k_step_finish_batch(const StepA
 // z0-1+j; a collide at iteration k reads slots k-3..k-1, and the slot written
 // at iteration k was last read before the barrier of iteration k-1.  The three
 // register sets rotate by unrolling the loop three times.
-template <class L, class S, int TX, int TM, bool BUF>
+template <class L, class S, int TX, int TM, bool BUF, bool GROW>
 struct StepBlock {
   using T = typename S::ct;
   static constexpr int Q = L::Q;
@@ -423,26 +427,36 @@ struct StepBlock {
   Ctl* ctl;
   long long step;
   int nx, nm, nz, x0, m0, z0, L_, TXe, TMe, lx, lm, x, m, xc, mc, gx, gm, hx, hm;
-  bool act, has_halo, film, test_rupture, tau_one, rho_all;
-  T G, rho0, tau, omega, psi_bar;
+  bool act, has_halo, film, grow, test_rupture, tau_one, rho_all;
+  T G, rho0, tau, omega, psi_bar, drho;
   double acc_m = 0.0, acc_x = 0.0, acc_y = 0.0, acc_z = 0.0;
 
   __device__ __forceinline__ StepBlock(const StepArgs& a_, Smem& sm_) : a(a_), sm(sm_) {}
 
   // interior waves: load the new plane, collide the plane loaded two
-  // iterations ago, publish rho / psi of the new plane
-  __device__ __forceinline__ void iter(int k, T (&ld)[Q], T (&co)[Q], unsigned& fl_ld, unsigned fl_co) {
+  // iterations ago, publish rho / psi of the new plane.  A plane's film word
+  // arrives in two stages: the cell's flag byte (set where the mask word is
+  // not zero) with the plane's populations, then, one iteration later when
+  // the byte has arrived, the 4-byte mask word at the few cells whose byte is
+  // set; the collide one iteration after that uses it
+  __device__ __forceinline__ void iter(int k, T (&ld)[Q], T (&co)[Q], unsigned& fl_ld, unsigned& fl_mid,
+                                       unsigned fl_co) {
     const bool loading = k <= L_ + 1;  // uniform over the workgroup
     T hv[Q];
     if (loading) {
       // every interior lane loads (lanes outside the lattice read clamped
       // cells and never publish), so no divergent branch separates the loads
-      // from the collide that overlaps them; the film flag is read first so
+      // from the collide that overlaps them; the flag byte is read first so
       // the wait that ends this iteration covers it too
       const int zl = wrap_any(z0 - 1 + k, nz);
-      if (film) fl_ld = a.mask[(unsigned)(xc + nx * (mc + nm * zl))];
+      if (film) fl_ld = a.flag[(unsigned)(xc + nx * (mc + nm * zl))];
       io.pull(xc, mc, zl, ld);
       if (HIN && has_halo) io.pull(gx, gm, zl, hv);
+    }
+    if (film && k >= 1 && k <= L_ + 2) {
+      // second stage for the plane loaded in the previous iteration
+      const int zp = wrap_any(z0 - 2 + k, nz);
+      fl_mid = fl_mid ? a.mask[(unsigned)(xc + nx * (mc + nm * zp))] : 0u;
     }
     // keep the collide between the loads and their first use
     __builtin_amdgcn_sched_barrier(0);
@@ -539,6 +553,16 @@ struct StepBlock {
     const T um = (jm + tau * fm) * inv;
     const T uz = (jz + tau * fz) * inv;
     const T base = T(1) - T(1.5) * (ux * ux + um * um + uz * uz);
+    // gas release at a domain gas point: w_i drho added to every population
+    // after the collision (Sec. 2.1.3), zero elsewhere.  The bit's word is
+    // one per 64-cell row block: with tiles a whole number of rows wide a
+    // wavefront reads one word, through the scalar cache
+    T ds = T(0);
+    if (GROW && grow) {
+      unsigned widx = (unsigned)(xc >> 6) + (unsigned)a.geo.nxb * (unsigned)(mc + nm * zc);
+      if constexpr (TX % 64 == 0) widx = __builtin_amdgcn_readfirstlane(widx);
+      if ((a.srcw[widx] >> (xc & 63)) & 1ull) ds = drho;
+    }
     // equilibria in opposite pairs: common part w rho (base + 4.5 (e.u)^2),
     // odd part w rho 3 e.u; the rest equilibrium is rho minus the moving ones
     // (equal in exact arithmetic, and it keeps the common rounding of the FP32
@@ -555,11 +579,12 @@ struct StepBlock {
       const T odd = wr * (T(3) * eu);
       const T fp = even + odd, fq = even - odd;
       feq_moving += fp + fq;
-      io.store_at(i, vo, tau_one ? fp : f[i] - (f[i] - fp) * omega);
-      io.store_at(i + 1, vo, tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega);
+      const T wd = (T)L::w[i] * ds;
+      io.store_at(i, vo, (tau_one ? fp : f[i] - (f[i] - fp) * omega) + wd);
+      io.store_at(i + 1, vo, (tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega) + wd);
     }
     const T feq0 = rho - feq_moving;
-    io.store_at(0, vo0, tau_one ? feq0 : f[0] - (f[0] - feq0) * omega);
+    io.store_at(0, vo0, (tau_one ? feq0 : f[0] - (f[0] - feq0) * omega) + (T)L::w[0] * ds);
     // the rupture test runs in its own kernel after this one, on the
     // densities of the state entering the step
     if (act && (rho_all || (test_rupture && (flag & kRhoBit)))) ((T*)a.rho)[c] = rho;
@@ -625,6 +650,8 @@ struct StepBlock {
     omega = T(1) / (T)a.tau;
     tau_one = a.tau == 1.0;
     film = a.film_on != 0;
+    grow = GROW && a.srcw != nullptr && ctl->n_src > 0;
+    drho = grow ? (T)(3.0 * (a.src_rate / (double)ctl->n_src)) : T(0);
     test_rupture = film && step >= a.rupture_warmup;
     rho_all = a.gas_k > 0 && (step + 1) % a.gas_k == 0;
     psi_bar = (T)a.psi_bar;
@@ -634,11 +661,11 @@ struct StepBlock {
       unsigned g0 = 0, g1 = 0, g2 = 0;
       const int kend = L_ + 2;
       for (int k = 0; k <= kend; k += 3) {
-        iter(k, r0, r1, g0, g1);
+        iter(k, r0, r1, g0, g2, g1);
         if (k + 1 > kend) break;
-        iter(k + 1, r1, r2, g1, g2);
+        iter(k + 1, r1, r2, g1, g0, g2);
         if (k + 2 > kend) break;
-        iter(k + 2, r2, r0, g2, g0);
+        iter(k + 2, r2, r0, g2, g1, g0);
       }
     } else {
       halo_loop();
@@ -648,20 +675,21 @@ struct StepBlock {
   }
 };
 
-template <class L, class S, int TX, int TM, bool BUF>
-__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF>::NT)) void k_step(StepArgs a) {
-  using SB = StepBlock<L, S, TX, TM, BUF>;
+// GROW: the variant with the gas-release source (its code costs registers,
+// so lattices without the source run the variant without it)
+template <class L, class S, int TX, int TM, bool BUF, bool GROW>
+__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF, GROW>::NT)) void k_step(StepArgs a) {
+  using SB = StepBlock<L, S, TX, TM, BUF, GROW>;
   __shared__ typename SB::Smem sm;
   if (a.ctl->stopped) return;
   SB blk(a, sm);
   blk.run(blockIdx.x, gridDim.x);
 }
 
-template <class L, class S, int TX, int TM, bool BUF>
-__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF>::NT)) void k_step_batch(const StepArgs* __restrict__ tab,
-                                                                                  const int* __restrict__ first,
-                                                                                  int nmem) {
-  using SB = StepBlock<L, S, TX, TM, BUF>;
+template <class L, class S, int TX, int TM, bool BUF, bool GROW>
+__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF, GROW>::NT)) void k_step_batch(
+    const StepArgs* __restrict__ tab, const int* __restrict__ first, int nmem) {
+  using SB = StepBlock<L, S, TX, TM, BUF, GROW>;
   __shared__ typename SB::Smem sm;
   const int k = batch_member(first, nmem, blockIdx.x);
   const StepArgs& a = tab[k];  // read in place: a local copy would live in scratch

@@ -145,6 +145,10 @@ __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
   const T base = T(1) - T(1.5) * (ux * ux + um * um + uz * uz);
   const unsigned long long vo = act ? io.lane_off(x, m, z, 1) : kDrop;
   const unsigned long long vo0 = act ? io.lane_off(x, m, z, 0) : kDrop;
+  // gas release at a domain gas point (Sec. 2.1.3): w_i drho on every population
+  const long long nsrc = a.srcw ? a.ctl->n_src : 0;
+  const bool src = nsrc > 0 && ((a.srcw[(xc >> 6) + a.geo.nxb * row] >> (xc & 63)) & 1ull);
+  const T ds = src ? (T)(3.0 * (a.src_rate / (double)nsrc)) : T(0);
   // paired equilibria; the rest equilibrium is rho minus the moving ones
   T feq_moving = T(0);
 #pragma unroll
@@ -158,11 +162,12 @@ __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
     const T odd = wr * (T(3) * eu);
     const T fp = even + odd, fq = even - odd;
     feq_moving += fp + fq;
-    io.store_at(i, vo, tau_one ? fp : f[i] - (f[i] - fp) * omega);
-    io.store_at(i + 1, vo, tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega);
+    const T wd = (T)L::w[i] * ds;
+    io.store_at(i, vo, (tau_one ? fp : f[i] - (f[i] - fp) * omega) + wd);
+    io.store_at(i + 1, vo, (tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega) + wd);
   }
   const T feq0 = rho - feq_moving;
-  io.store_at(0, vo0, tau_one ? feq0 : f[0] - (f[0] - feq0) * omega);
+  io.store_at(0, vo0, (tau_one ? feq0 : f[0] - (f[0] - feq0) * omega) + (T)L::w[0] * ds);
 
   // the rupture test runs in its own kernel, on the rho array of k_psi
   const double keep = act ? 1.0 : 0.0;

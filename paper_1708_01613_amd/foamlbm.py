@@ -6,7 +6,6 @@ only marshal arguments; every step of the method runs in the HIP library.
 PyTorch.  Importing this module fails loudly when the library is not built.
 """
 import ctypes as C
-import math
 import os
 import sys
 
@@ -43,6 +42,9 @@ class flb_params(C.Structure):
         ("psi_bar_mode", C.c_int32), ("rupture_warmup", C.c_int32),
         ("on_rupture", C.c_int32), ("velocity_mode", C.c_int32),
         ("rupture_filter", C.c_int32),
+        ("refresh_src", C.c_int32), ("growth_on", C.c_int32),
+        ("gas_A", C.c_double), ("gas_dndt", C.c_double),
+        ("f16_rho_ref", C.c_double),
     ]
 
 
@@ -75,6 +77,14 @@ class flb_allocator(C.Structure):
 if not os.path.exists(LIBPATH):
     raise ImportError(f"libfoamlbm.so is not built at {LIBPATH}; run __graft_entry__.build() "
                       "(or python paper_1708_01613_amd/build.py)")
+if not os.environ.get("FOAMLBM_LIB"):
+    # the in-tree library must have been built from the sources beside it
+    from .build import source_hash, stamp_of  # noqa: E402
+
+    _stamp = stamp_of(LIBPATH)
+    if _stamp != source_hash():
+        raise ImportError(f"{LIBPATH} was built from other sources (stamp {_stamp!r}, sources "
+                          f"{source_hash()!r}); rebuild it with __graft_entry__.build()")
 # PyTorch ships its own HIP runtime under the same soname: loading torch
 # first makes the library bind to that one instance, so device memory and
 # streams from torch are valid in the library's calls
@@ -112,6 +122,11 @@ _SIGS = {
     "flb_load": (C.c_int, [_CTX, C.c_char_p]),
     "flb_import_maps": (C.c_int, [_CTX, _I, _I, _I, _I, C.c_size_t, C.c_void_p, C.c_int32]),
     "flb_time_steps": (C.c_int, [_CTX, C.c_int64, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "flb_time_phases": (C.c_int, [_CTX, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "flb_copy_bandwidth": (C.c_int, [C.POINTER(flb_allocator), C.c_void_p, C.c_int64, C.c_int32,
+                                     C.POINTER(C.c_double)]),
+    "flb_get_pressure": (C.c_int, [_CTX, _D, C.c_size_t]),
+    "flb_get_gas_points": (C.c_int, [_CTX, C.c_void_p, C.c_size_t, C.POINTER(C.c_int64)]),
     "flb_destroy": (None, [_CTX]),
     "flb_last_error": (C.c_char_p, []),
     "flb_batch_create": (C.c_int, [C.POINTER(flb_params), C.c_int32, C.POINTER(flb_allocator), C.c_void_p,
@@ -173,14 +188,14 @@ def default_params(**kw):
     return p
 
 
-def _torch_allocator(device_index):
-    """Device memory from PyTorch's caching allocator, on the current stream."""
-    import torch
+def _torch_allocator(device_index, stream):
+    """Device memory from PyTorch's caching allocator, tagged with the stream
+    the library enqueues its work on (so a block is reused only in that
+    stream's order)."""
 
     def _alloc(nbytes, user):
         try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes), device_index,
-                                                      torch.cuda.current_stream(device_index))
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device_index, stream)
         except Exception as exc:  # the library reports FLB_ENOMEM; say why
             print(f"foamlbm: device allocation of {int(nbytes)} bytes failed: {exc}", file=sys.stderr, flush=True)
             return None
@@ -209,7 +224,7 @@ class Sim:
         self._keep = None
         alloc = None
         if use_torch_memory:
-            al, self._keep = _torch_allocator(dev)
+            al, self._keep = _torch_allocator(dev, self.stream)
             alloc = C.byref(al)
             self._al = al
         h = _CTX()
@@ -352,6 +367,27 @@ class Sim:
         check(flb_autotune(self.h, int(reps), C.byref(ms)), "flb_autotune")
         return ms.value
 
+    def pressure(self):
+        """Bulk pressure p0(rho) of the current state (Eq. Pequ), FP64."""
+        out = np.empty(self.N, np.float64)
+        check(flb_get_pressure(self.h, out, out.size), "flb_get_pressure")
+        return out.reshape(self.shape)
+
+    def gas_points(self):
+        """Domain gas points of the gas-release source (bool array) and their number."""
+        out = np.empty(self.N, np.uint8)
+        n = C.c_int64(0)
+        check(flb_get_gas_points(self.h, out.ctypes.data_as(C.c_void_p), out.size, C.byref(n)),
+              "flb_get_gas_points")
+        return out.reshape(self.shape).astype(bool), n.value
+
+    def time_phases(self, n):
+        """n steps timed per phase: (total ms, {refresh, step, rupture, finish} ms sums)."""
+        ms = C.c_double(0.0)
+        ph = (C.c_double * 4)()
+        check(flb_time_phases(self.h, int(n), C.byref(ms), ph), "flb_time_phases")
+        return ms.value, dict(zip(("refresh", "step", "rupture", "finish"), list(ph)))
+
     def time_steps(self, n, refresh=True, kernel=False):
         """Milliseconds for n steps; with kernel=True, (total, step-kernel sum)."""
         ms = C.c_double(0.0)
@@ -367,8 +403,17 @@ class Sim:
                     n_ruptures=s.n_ruptures, stopped=bool(s.stopped), events_lost=s.events_lost)
 
 
-def psi_liquid(rho_liquid, rho0=1.0):
-    return rho0 * (1.0 - math.exp(-rho_liquid / rho0))
+def copy_bandwidth(nbytes=1 << 30, reps=10, stream=None):
+    """Read + write GB/s of the library's 16-byte-per-lane device copy of
+    nbytes (the practical HBM ceiling of the step kernel)."""
+    dev = torch.cuda.current_device()
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    al, keep = _torch_allocator(dev, stream)
+    gbs = C.c_double(0.0)
+    check(flb_copy_bandwidth(C.byref(al), C.c_void_p(stream.cuda_stream), int(nbytes), int(reps), C.byref(gbs)),
+          "flb_copy_bandwidth")
+    del keep
+    return gbs.value
 
 
 class Batch:
@@ -389,7 +434,7 @@ class Batch:
         self._keep = None
         alloc = None
         if use_torch_memory:
-            al, self._keep = _torch_allocator(dev)
+            al, self._keep = _torch_allocator(dev, self.stream)
             alloc = C.byref(al)
             self._al = al
         h = C.c_void_p()
@@ -473,7 +518,7 @@ class Server:
         self._keep = None
         alloc = None
         if use_torch_memory:
-            al, self._keep = _torch_allocator(dev)
+            al, self._keep = _torch_allocator(dev, self.stream)
             alloc = C.byref(al)
             self._al = al
         h = C.c_void_p()

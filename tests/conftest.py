@@ -3,6 +3,11 @@ import sys
 
 import pytest
 
+# parallel test workers each load the OpenMP oracle: keep their threads few so
+# the workers do not oversubscribe the cores (read when the oracle loads)
+if "PYTEST_XDIST_WORKER" in os.environ:
+    os.environ.setdefault("OMP_NUM_THREADS", "2")
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

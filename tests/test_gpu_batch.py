@@ -122,3 +122,25 @@ def test_batch_autotune_leaves_state_unchanged(flb):
     for k, (p, nuc) in enumerate(members):
         s = _solo(flb, p, nuc, 20)
         assert np.array_equal(b.members[k].populations(), s.populations()), k
+
+
+def test_batch_with_gas_release_matches_solo(flb):
+    # members with and without the gas-release source (Sec. 2.1.3) in one
+    # batch: the batch runs the source variant of the step kernel for all of
+    # them, and every member still equals its solo run bit for bit
+    members = _members_2d("f32")
+    for k, (p, _) in enumerate(members):
+        if k % 3 != 1:
+            p.update(growth_on=1, gas_A=1.0 + k, gas_dndt=0.01)
+    _say("batch of 6 D2Q9 f32, gas release in 4 members")
+    b = flb.Batch([p for p, _ in members])
+    for k, (_, nuc) in enumerate(members):
+        b.members[k].set_nuclei(nuc)
+    steps = 57
+    b.step(steps)
+    b.synchronize()
+    for k, (p, nuc) in enumerate(members):
+        s = _solo(flb, p, nuc, steps)
+        m = b.members[k]
+        assert np.array_equal(m.populations(), s.populations()), k
+        assert m.gas_points()[1] == s.gas_points()[1] == (s.gas_points()[1] if p.get("growth_on") else 0)

@@ -1,0 +1,175 @@
+"""GPU against the FP64 oracle on the parameter paths of the boundary: BGK
+relaxation times other than 1 (Sec. 2.1.1), a pseudopotential scale rho0 other
+than 1 (Sec. 2.1.2), the mirror barrier value (psi_bar_mode 1, Sec. 2.1.5),
+both refresh readings (refresh_src), the gas-release source (Sec. 2.1.3), the
+FP64 mass and momentum totals, the pressure query, and FP16-shifted storage
+with the film on.  Every case has the film on with bubbles close enough for
+barrier links and ruptures within its horizon.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from .gpu_helpers import active_links, max_rel, oracle_for, oracle_order, vel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16s": 2e-3}
+
+
+@pytest.fixture(scope="module")
+def flb():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1708_01613_amd import foamlbm
+
+    return foamlbm
+
+
+def _case(kind, storage, tau=1.0, rho0=1.0, psi_bar_mode=0, refresh_src=0, growth=0, velocity_mode=1, **kw):
+    # the rho0-scaled problem: psi = rho0 phi(rho / rho0) with G rho0 and the
+    # densities / rho0 held fixed is the same physics at another scale
+    p = dict(lattice=kind, storage=storage, tau=tau, rho0=rho0, G=-5.5 / rho0, rho_liquid=2.3 * rho0,
+             rho_gas=0.11 * rho0, rho_th=math.log(2.0) * rho0, noise_amp=0.01 * rho0, film_on=1, k_own=3,
+             zone_width=6, rupture_warmup=30, psi_bar_mode=psi_bar_mode, refresh_src=refresh_src,
+             velocity_mode=velocity_mode, seed=5)
+    if growth:
+        p.update(growth_on=1, gas_A=1.5 * rho0, gas_dndt=0.01)
+    if kind == 0:
+        p.update(nx=72, ny=44, nz=1)
+        nuc = [[20.0, 22.0, 0, 9.0], [40.5, 22.0, 0, 9.0], [60.0, 8.0, 0, 5.0]]
+        steps = 90
+    else:
+        # liquid below coexistence, so the small 3-D bubbles do not condense
+        p.update(nx=32, ny=24, nz=22, rho_liquid=2.0 * rho0)
+        nuc = [[7.5, 12.0, 11.0, 6.0], [24.5, 12.0, 11.0, 6.0], [28.0, 4.0, 4.0, 3.5]]
+        steps = 50
+    p.update(kw)
+    print(f"\n[case] {p}", flush=True)
+    sys.stdout.flush()
+    return p, nuc, steps
+
+
+def _run(flb, p, nuc, steps, tile=None):
+    g = flb.Sim(**p)
+    if tile is not None:
+        g.set_tuning(tile, 0, -1)
+    g.set_nuclei(nuc)
+    o = oracle_for(p, nuc)
+    g.step(steps)
+    o.step(steps)
+    return g, o
+
+
+def _check(flb, kind, storage, g, o, events_exact=True):
+    tol = TOL[storage]
+    ro = o.density()
+    assert max_rel(g.density(), ro) <= tol
+    assert vel_err(g.velocity(), o.velocity()) <= tol
+    st = g.stats()
+    m, mom = o.stats()
+    assert abs(st["mass"] - m) <= tol * m
+    assert np.abs(st["mom"] - mom).max() <= tol * m
+    assert max_rel(g.pressure(), o.pressure()) <= 10 * tol or np.abs(g.pressure() - o.pressure()).max() <= tol
+    gm, om = g.maps(), o.maps()
+    for key in ("label", "owner", "owner2", "dist"):
+        assert np.array_equal(gm[key], om[key]), key
+    order = oracle_order(kind, flb.DIRECTIONS[kind])
+    oa = active_links(kind, om)
+    omask = np.zeros_like(gm["mask"])
+    for i, j in enumerate(order):
+        omask |= ((oa >> np.uint32(j)) & np.uint32(1)) << np.uint32(i)
+    assert np.array_equal(gm["mask"], omask)
+    if events_exact:
+        ge = {tuple(r) for r in g.rupture_events().tolist()}
+        oe = {tuple(r) for r in o.events().tolist()}
+        assert ge == oe
+        assert st["n_ruptures"] == o.n_ruptures
+    return st
+
+
+CASES = [
+    dict(tau=0.8, psi_bar_mode=1, refresh_src=0),
+    dict(tau=1.3, rho0=0.5, refresh_src=1),
+    dict(tau=1.0, rho0=1.5, growth=1, refresh_src=0),
+    dict(tau=0.75, growth=1, psi_bar_mode=1, refresh_src=1),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_parameter_paths(flb, kind, storage, case):
+    p, nuc, steps = _case(kind, storage, **CASES[case])
+    g, o = _run(flb, p, nuc, steps)
+    st = _check(flb, kind, storage, g, o, events_exact=(storage == "f64"))
+    assert st["n_bubbles"] >= 2
+    if storage == "f64":
+        assert o.n_ruptures > 0  # the horizon reaches past the first rupture
+    # the momentum totals are not trivially zero: barrier links break the
+    # pairwise cancellation of the interaction force
+    assert np.abs(o.stats()[1]).max() > 1e-9
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_two_pass_variant_parameter_paths(flb, kind):
+    p, nuc, steps = _case(kind, "f64", tau=0.8, growth=1, psi_bar_mode=1)
+    ntiles = flb.Sim(**p).tuning()["n_tiles"]
+    g, o = _run(flb, p, nuc, steps, tile=ntiles - 1)  # the two-pass variant is the last
+    _check(flb, kind, "f64", g, o)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_gas_points_and_released_mass(flb, kind):
+    p, nuc, steps = _case(kind, "f64", growth=1)
+    g, o = _run(flb, p, nuc, steps)
+    gp, gn = g.gas_points()
+    op, on = o.gas_points()
+    assert gn == on > 0 and np.array_equal(gp, op)
+    m0 = oracle_for(p, nuc).stats()[0]
+    # every step releases 3 A (dn/dt) of mass at the gas points
+    assert abs(g.stats()["mass"] - (m0 + steps * 3 * p["gas_A"] * p["gas_dndt"])) <= 1e-11 * m0
+
+
+@pytest.mark.parametrize("ref", ["one", "harmonic"])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_fp16s_with_film(flb, kind, ref):
+    # FP16-shifted storage with the barrier and the rupture test.  One FP16
+    # rounding of f_i - w_i href costs about 2^-12 |rho - href| / rho of f_i.
+    # With href = 1 (f_i - w_i) that is ~2e-3 of f_i in the gas (rho ~ 0.1),
+    # the survey's FP16S budget of Sec. 8(c) (up to 4.6e-3 at rho = 0.06 on
+    # D2Q9), and j / rho carries it into the gas velocity: measured ~5e-3 of
+    # the largest speed, checked at 1e-2.  With href the harmonic mean of the
+    # phase densities both phases see ~2e-4 per rounding, and every field
+    # stays within 2e-3.
+    p, nuc, steps = _case(kind, "f16s", tau=1.0, refresh_src=0, velocity_mode=0)
+    if ref == "harmonic":
+        p["f16_rho_ref"] = 2 * p["rho_liquid"] * p["rho_gas"] / (p["rho_liquid"] + p["rho_gas"])
+    g, o = _run(flb, p, nuc, 40 if kind == 0 else 30)
+    ro, uo = o.density(), o.velocity()
+    assert max_rel(g.density(), ro) <= 2e-3
+    gas = ro < math.log(2.0)
+    ug = g.velocity()
+    umax = np.abs(uo).max()
+    err_out = np.abs(ug - uo)[:, ~gas].max() / umax
+    err_gas = np.abs(ug - uo)[:, gas].max() / umax
+    print(f"f16s href={ref}: velocity error outside the gas {err_out:.2e}, in the gas {err_gas:.2e}", flush=True)
+    assert err_out <= 2e-3
+    assert err_gas <= (2e-3 if ref == "harmonic" else 1e-2)
+    gm, om = g.maps(), o.maps()
+    assert np.array_equal(gm["label"], om["label"])
+
+
+def test_refresh_readings_differ_and_each_matches(flb):
+    # the two refresh readings give different maps on this case, and each
+    # equals the oracle's under the same reading
+    maps = []
+    for src in (0, 1):
+        p, nuc, _ = _case(0, "f64", refresh_src=src, k_own=5, rupture_warmup=10 ** 6)
+        g, o = _run(flb, p, nuc, 26)
+        _check(flb, 0, "f64", g, o)
+        maps.append(g.maps()["dist"])
+    assert not np.array_equal(maps[0], maps[1])
