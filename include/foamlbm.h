@@ -215,6 +215,17 @@ int flb_get_maps(flb_ctx* ctx, int32_t* label, int32_t* owner, int32_t* owner2, 
  * 2 sqrt(A/pi) (D2Q9) or (6V/pi)^(1/3) (D3Q19) in lattice units, bin
  * floor(d / bin_width), last bin open-ended.  counts[nbins]. */
 int flb_get_histogram(flb_ctx* ctx, int32_t nbins, double bin_width, int64_t* counts, int32_t* n_bubbles);
+/* flb_get_histogram for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same result, computed without any hipMalloc, hipFree or
+ * allocator call.  The bins live in a device array the library holds on
+ * every GPU it runs on until the process ends (512 KiB), so nbins must be in
+ * 1..65536 (FLB_EINVAL beyond).  All contexts on one GPU share that array and
+ * each call clears it first: calls on one GPU that overlap in time (from
+ * several threads or streams) race and must be serialised by the caller.
+ * Synchronises the context stream. */
+int flb_get_histogram_noalloc(flb_ctx* ctx, int32_t nbins, double bin_width, int64_t* counts, int32_t* n_bubbles);
+
 /* Overlap of an earlier bubble labelling with the current one, for tracking
  * coalescence between snapshots (the bubble statistics of Sec. 5 taken over
  * time).  old_labels: n == nx*ny*nz labels (x fastest, 0 = liquid) as

@@ -1,7 +1,50 @@
 // foamlbm.hip -- C ABI (include/foamlbm.h) of the gfx950 path: single lattices.
+#include <mutex>
+
 #include "runtime.hpp"
 
 using namespace flb_rt;
+
+// ---- the allocation-free histogram's device array ----
+// A file-scope array every device holds its own copy of, for the bins of
+// flb_get_histogram_noalloc.  In host code `scratch` names a host-side stand-in,
+// not a device address: kernels and copies only ever see the address that
+// hipGetSymbolAddress returned for the device, kept per device below.
+constexpr int kNoAllocMaxBins = 65536;
+static __device__ __align__(256) unsigned long long scratch[kNoAllocMaxBins];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch[kMaxDevices] = {};
+
+// looks up this device's copy once, with the device current
+int scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FLB_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return FLB_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return fail(FLB_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch[dev] = (unsigned long long*)ptr;
+  return FLB_OK;
+}
+
+unsigned long long* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return dev >= 0 && dev < kMaxDevices ? g_scratch[dev] : nullptr;
+}
+
+// labels of the current state without allocating: the context's query
+// tables exist from creation, and every clear is a kernel
+template <class L, class S>
+int label_query_noalloc(flb_ctx* c) {
+  const int B = 256;
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(B), 0, c->st, (unsigned long long*)c->qctl,
+                     (long long)(sizeof(Ctl) / 8), 0ull);
+  return map_pipeline<L, S>(c->qs_pop, c->st, GAS_POP, false);
+}
+}  // namespace
 
 
 extern "C" {
@@ -122,6 +165,12 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     delete c;
     return fail(FLB_ENOMEM, "device allocation failed");
   }
+  static_assert(sizeof(Ctl) % 8 == 0, "the run control is cleared as 64-bit words");
+  if (hipGetDevice(&c->dev) != hipSuccess || scratch_init(c->dev) != FLB_OK) {
+    c->dfree_all();
+    delete c;
+    return g_err.empty() ? fail(FLB_EHIP, "hipGetDevice failed") : FLB_EHIP;
+  }
   if (hipMemsetAsync(c->ctl, 0, sizeof(Ctl), c->st) != hipSuccess ||
       hipMemsetAsync(c->qctl, 0, sizeof(Ctl), c->st) != hipSuccess ||
       (p->film_on && hipMemsetAsync(c->flag, 0, (size_t)c->N, c->st) != hipSuccess) ||
@@ -131,6 +180,13 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     c->dfree_all();
     delete c;
     return fail(FLB_EHIP, "initialising device state failed");
+  }
+  // the map tables of queries and refreshes, built now so later calls need no allocation
+  rc = ctx_mapsets(c);
+  if (rc) {
+    c->dfree_all();
+    delete c;
+    return rc;
   }
   *out = c;
   return FLB_OK;
@@ -431,6 +487,32 @@ int flb_get_histogram(flb_ctx* c, int32_t nbins, double bin_width, int64_t* coun
   HIPCHK(hipMemcpyAsync(&nb, &c->qctl->n_bubbles, sizeof(int), hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   for (int k = 0; k < nbins; k++) counts[k] = (int64_t)h[k];
+  if (n_bubbles) *n_bubbles = nb;
+  return FLB_OK;
+}
+
+int flb_get_histogram_noalloc(flb_ctx* c, int32_t nbins, double bin_width, int64_t* counts, int32_t* n_bubbles) {
+  if (!c || !counts) return fail(FLB_EINVAL, "NULL argument");
+  if (nbins < 1 || nbins > kNoAllocMaxBins)
+    return fail(FLB_EINVAL, "nbins must be in 1..%d (the allocation-free maximum)", kNoAllocMaxBins);
+  if (!(bin_width > 0) || !isfinite(bin_width)) return fail(FLB_EINVAL, "bin_width must be > 0");
+  if (!c->ms_ready) return fail(FLB_EINVAL, "context has no query tables");
+  unsigned long long* bins = scratch_of(c->dev);
+  if (!bins) return fail(FLB_EINVAL, "device %d has no histogram array (no context created on it)", c->dev);
+  int rc = FLB_DISPATCH(c, label_query_noalloc, c);
+  if (rc) return rc;
+  const int B = 256;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(c->N + 1, B)), dim3(B), 0, c->st, c->qsizes, c->N + 1, 0ull);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nbins, B)), dim3(B), 0, c->st, bins, (long long)nbins, 0ull);
+  hipLaunchKernelGGL(k_label_sizes, dim3(grid_for(c->N, B)), dim3(B), 0, c->st, c->qlabel, c->N, c->qsizes);
+  hipLaunchKernelGGL(k_histogram, dim3(grid_for(c->N, B)), dim3(B), 0, c->st, c->qsizes, &c->qctl->n_bubbles, c->D,
+                     nbins, bin_width, bins);
+  HIPCHK(hipGetLastError());
+  static_assert(sizeof(int64_t) == sizeof(unsigned long long), "bins copy straight into the caller's counts");
+  int nb = 0;
+  HIPCHK(hipMemcpyAsync(counts, bins, sizeof(unsigned long long) * (size_t)nbins, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(&nb, &c->qctl->n_bubbles, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
   if (n_bubbles) *n_bubbles = nb;
   return FLB_OK;
 }

@@ -200,6 +200,12 @@ static __global__ __launch_bounds__(64) void k_reduce_final(const double* partia
 }
 
 // bubble sizes (cells per label) and equivalent-diameter histogram
+// p[0 .. n) = v (clears without hipMemset, which captured graphs mishandle)
+static __global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 static __global__ void k_label_sizes(const int* label, long long N, unsigned long long* sizes) {
   for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
        c += (long long)gridDim.x * blockDim.x) {

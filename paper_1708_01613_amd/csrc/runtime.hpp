@@ -234,6 +234,7 @@ struct flb_ctx {
   long long qtab_cap = 0;
   long long launched = 0;
   bool in_batch = false;   // owned by a batch (flb_destroy refuses it)
+  int dev = 0;             // the device current at creation (holds every buffer)
   std::vector<void*> allocs;
 
   size_t bytes = 0;  // device bytes held

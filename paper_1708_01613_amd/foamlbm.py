@@ -112,6 +112,7 @@ _SIGS = {
     "flb_label_field": (C.c_int, [_CTX, _D, C.c_size_t, _I, C.POINTER(C.c_int32)]),
     "flb_get_maps": (C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     "flb_get_histogram": (C.c_int, [_CTX, C.c_int32, C.c_double, _L, C.POINTER(C.c_int32)]),
+    "flb_get_histogram_noalloc": (C.c_int, [_CTX, C.c_int32, C.c_double, _L, C.POINTER(C.c_int32)]),
     "flb_match_labels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int32)]),
     "flb_get_rupture_events": (C.c_int, [_CTX, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
