@@ -215,6 +215,23 @@ int flb_get_maps(flb_ctx* ctx, int32_t* label, int32_t* owner, int32_t* owner2, 
  * 2 sqrt(A/pi) (D2Q9) or (6V/pi)^(1/3) (D3Q19) in lattice units, bin
  * floor(d / bin_width), last bin open-ended.  counts[nbins]. */
 int flb_get_histogram(flb_ctx* ctx, int32_t nbins, double bin_width, int64_t* counts, int32_t* n_bubbles);
+/* Foam statistics of the current labels, the quantities the paper reads off
+ * its virtual metallography (Sec. 5, Table 5 and Fig. 14): the bubble cell
+ * fraction (bubble percentage), the relative foam density 1 - fraction
+ * (Table 5's foam density is the melt density times it), and the mean and
+ * largest equivalent diameter (2 sqrt(A/pi) on D2Q9, (6V/pi)^(1/3) on D3Q19,
+ * lattice units; 0 without bubbles).  Sums run in a fixed order on the
+ * device, so results do not depend on timing.  Synchronises the stream. */
+typedef struct {
+  int32_t n_bubbles;
+  int64_t gas_cells;
+  double gas_fraction;
+  double relative_density;
+  double mean_diameter;
+  double max_diameter;
+} flb_foam_stats;
+int flb_get_foam_stats(flb_ctx* ctx, flb_foam_stats* out);
+
 /* flb_get_histogram for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same result, computed without any hipMalloc, hipFree or

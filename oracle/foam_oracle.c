@@ -724,6 +724,34 @@ void or_stats(or_sim* s, double* mass, double* mom) {
 
 int64_t or_n_ruptures(const or_sim* s) { return s->n_ruptures; }
 
+/* Foam statistics of a label field, the quantities of the paper's virtual  */
+/* metallography (Sec. 5, Table 5 and Fig. 14): out[0] = bubble (gas) cell   */
+/* fraction, out[1] = relative foam density 1 - fraction (Table 5's foam     */
+/* density is the melt density times this), out[2] = mean equivalent         */
+/* diameter over the bubbles (2-D: area-equivalent circle, 3-D: volume-      */
+/* equivalent sphere; 0 without bubbles), out[3] = largest equivalent        */
+/* diameter.  Plain loops: sizes by counting, diameters summed in label order. */
+void or_foam_stats(const or_sim* s, const int32_t* lab, int32_t nb, double* out) {
+  int64_t* sizes = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
+  int64_t gas = 0;
+  for (long c = 0; c < s->N; c++) {
+    sizes[lab[c]]++;
+    if (lab[c] > 0) gas++;
+  }
+  double sum = 0.0, dmax = 0.0;
+  for (int32_t b = 1; b <= nb; b++) {
+    double v = (double)sizes[b];
+    double d = s->D == 2 ? 2.0 * sqrt(v / M_PI) : cbrt(6.0 * v / M_PI);
+    sum += d;
+    if (d > dmax) dmax = d;
+  }
+  free(sizes);
+  out[0] = (double)gas / (double)s->N;
+  out[1] = 1.0 - out[0];
+  out[2] = nb > 0 ? sum / (double)nb : 0.0;
+  out[3] = dmax;
+}
+
 /* domain gas points (the cells of the nuclei, Sec. 2.1.3): out[N] 0/1 (may */
 /* be NULL); returns their number N of the gas-release law                  */
 long or_gas_points(const or_sim* s, unsigned char* out) {

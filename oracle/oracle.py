@@ -78,6 +78,7 @@ def _load():
         "or_gas_points": (C.c_long, [_P, C.c_void_p]),
         "or_pressure": (None, [_P, _D]),
         "or_alias_unite": (C.c_int, [_P, C.c_int32, C.c_int32]),
+        "or_foam_stats": (None, [_P, _I, C.c_int32, _D]),
         "or_threads": (C.c_int, []),
         "or_set_threads": (None, [C.c_int]),
         "or_splitmix64": (C.c_uint64, [C.c_uint64]),
@@ -238,6 +239,14 @@ class OracleSim:
         return dict(label=label.reshape(s), owner=owner.reshape(s), owner2=owner2.reshape(s),
                     dist=dist.reshape(s),
                     mask=mask.reshape(s), alias_root=alias[: nb + 1].copy(), n_bubbles=nb)
+
+    def foam_stats(self, labels, nb):
+        """Virtual-metallography statistics of a label field (Sec. 5, Table 5):
+        gas fraction, relative foam density, mean and largest equivalent diameter."""
+        lab = np.ascontiguousarray(np.asarray(labels, np.int32).reshape(-1))
+        out = np.zeros(4, np.float64)
+        self._lib.or_foam_stats(self._h, lab, int(nb), out)
+        return dict(gas_fraction=out[0], relative_density=out[1], mean_diameter=out[2], max_diameter=out[3])
 
     def pressure(self):
         """Bulk pressure p0(rho) of the current state (Eq. Pequ)."""

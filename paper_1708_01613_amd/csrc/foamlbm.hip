@@ -491,6 +491,30 @@ int flb_get_histogram(flb_ctx* c, int32_t nbins, double bin_width, int64_t* coun
   return FLB_OK;
 }
 
+int flb_get_foam_stats(flb_ctx* c, flb_foam_stats* out) {
+  if (!c || !out) return fail(FLB_EINVAL, "NULL argument");
+  int rc = FLB_DISPATCH(c, label_query, c, false);
+  if (rc) return rc;
+  const int B = 256;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(c->N + 1, B)), dim3(B), 0, c->st, c->qsizes, c->N + 1, 0ull);
+  hipLaunchKernelGGL(k_label_sizes, dim3(grid_for(c->N, B)), dim3(B), 0, c->st, c->qlabel, c->N, c->qsizes);
+  hipLaunchKernelGGL(k_foam_stats, dim3(1), dim3(FS_NT), 0, c->st, c->qsizes, &c->qctl->n_bubbles, c->D, c->N,
+                     c->qtot);
+  HIPCHK(hipGetLastError());
+  double v[5];
+  int nb = 0;
+  HIPCHK(hipMemcpyAsync(v, c->qtot, sizeof v, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(&nb, &c->qctl->n_bubbles, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  out->n_bubbles = nb;
+  out->gas_cells = (int64_t)v[4];
+  out->gas_fraction = v[0];
+  out->relative_density = v[1];
+  out->mean_diameter = v[2];
+  out->max_diameter = v[3];
+  return FLB_OK;
+}
+
 int flb_get_histogram_noalloc(flb_ctx* c, int32_t nbins, double bin_width, int64_t* counts, int32_t* n_bubbles) {
   if (!c || !counts) return fail(FLB_EINVAL, "NULL argument");
   if (nbins < 1 || nbins > kNoAllocMaxBins)

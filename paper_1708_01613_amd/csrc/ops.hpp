@@ -227,6 +227,55 @@ static __global__ void k_histogram(const unsigned long long* sizes, const int* n
   }
 }
 
+// Foam statistics of the label sizes (Sec. 5, Table 5): out[0] bubble cell
+// fraction, out[1] relative foam density 1 - fraction, out[2] mean and
+// out[3] largest equivalent diameter, out[4] bubble cells.  One workgroup;
+// thread t sums bubbles t+1, t+1+FS_NT, ... in order, then fixed-order
+// wavefront and workgroup reductions, so the result does not depend on timing.
+constexpr int FS_NT = 1024;
+static __global__ __launch_bounds__(FS_NT) void k_foam_stats(const unsigned long long* __restrict__ sizes,
+                                                            const int* n_bubbles, int D, long long N, double* out) {
+  __shared__ double s_sum[FS_NT / 64], s_max[FS_NT / 64];
+  __shared__ unsigned long long s_gas[FS_NT / 64];
+  const int nb = *n_bubbles;
+  double sum = 0.0, dmax = 0.0;
+  unsigned long long gas = 0;
+  for (int b = 1 + (int)threadIdx.x; b <= nb; b += FS_NT) {
+    const double v = (double)sizes[b];
+    const double dm = D == 2 ? 2.0 * sqrt(v / 3.141592653589793) : cbrt(6.0 * v / 3.141592653589793);
+    sum += dm;
+    dmax = fmax(dmax, dm);
+    gas += sizes[b];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sum += __shfl_down(sum, off, 64);
+    dmax = fmax(dmax, __shfl_down(dmax, off, 64));
+    gas += __shfl_down(gas, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_sum[wave] = sum;
+    s_max[wave] = dmax;
+    s_gas[wave] = gas;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S = 0.0, M = 0.0;
+    unsigned long long Gc = 0;
+    for (int w = 0; w < FS_NT / 64; w++) {
+      S += s_sum[w];
+      M = fmax(M, s_max[w]);
+      Gc += s_gas[w];
+    }
+    out[0] = (double)Gc / (double)N;
+    out[1] = 1.0 - out[0];
+    out[2] = nb > 0 ? S / (double)nb : 0.0;
+    out[3] = M;
+    out[4] = (double)Gc;
+  }
+}
+
 // ---- overlap of two labellings (coalescence tracking, Sec. 5) ----
 // Every cell that is gas in both labellings adds one to the count of its
 // (old label, new label) pair in an open-addressing table of `mask + 1`

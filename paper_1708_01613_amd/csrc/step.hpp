@@ -11,7 +11,7 @@
 // Work decomposition: a workgroup owns a TX x TM tile of the (x, m) plane and
 // a segment of LZ planes along z.  It marches z: for plane zz it pulls the Q
 // populations of its own cells (kept in registers) and of a one-cell halo ring
-// (summed to rho only), writes rho and psi into a 4-plane LDS ring, and after
+// (summed to rho only), writes psi into a 4-plane LDS ring, and after
 // one barrier collides plane zz-1, whose psi neighbours (planes zz-2..zz) are
 // all in the ring.  Each population is read once per step plus the halo and
 // segment-end planes, and written once.
@@ -394,7 +394,7 @@ static __global__ __launch_bounds__(FIN_NT) void k_step_finish_batch(const StepA
 
 // Plane loop: iteration k loads plane z0-1+k (k <= L+1) into one register
 // set, collides plane z0+k-3 (k >= 3) from the set loaded two iterations
-// earlier while the new loads are in flight, then stores rho / psi of the new
+// earlier while the new loads are in flight, then stores psi of the new
 // plane into LDS slot k & 3 and synchronises once.  Slot j & 3 holds plane
 // z0-1+j; a collide at iteration k reads slots k-3..k-1, and the slot written
 // at iteration k was last read before the barrier of iteration k-1.  The three
@@ -416,7 +416,6 @@ struct StepBlock {
   static constexpr int NT = HIN ? NI : NI + (NH + 63) / 64 * 64;
   struct Smem {
     T psi[4][LH][LW];
-    T rho[4][LH][LW];
     double red[NT / 64][4];
     int last;
   };
@@ -434,29 +433,22 @@ struct StepBlock {
   __device__ __forceinline__ StepBlock(const StepArgs& a_, Smem& sm_) : a(a_), sm(sm_) {}
 
   // interior waves: load the new plane, collide the plane loaded two
-  // iterations ago, publish rho / psi of the new plane.  A plane's film word
-  // arrives in two stages: the cell's flag byte (set where the mask word is
-  // not zero) with the plane's populations, then, one iteration later when
-  // the byte has arrived, the 4-byte mask word at the few cells whose byte is
-  // set; the collide one iteration after that uses it
-  __device__ __forceinline__ void iter(int k, T (&ld)[Q], T (&co)[Q], unsigned& fl_ld, unsigned& fl_mid,
-                                       unsigned fl_co) {
+  // iterations ago, publish psi of the new plane
+  __device__ __forceinline__ void iter(int k, T (&ld)[Q], T (&co)[Q], unsigned& fl_ld, unsigned fl_co) {
     const bool loading = k <= L_ + 1;  // uniform over the workgroup
     T hv[Q];
     if (loading) {
       // every interior lane loads (lanes outside the lattice read clamped
       // cells and never publish), so no divergent branch separates the loads
-      // from the collide that overlaps them; the flag byte is read first so
-      // the wait that ends this iteration covers it too
+      // from the collide that overlaps them; the film mask word is read
+      // first so the wait that ends this iteration covers it too (one 4-byte
+      // word per cell: measured faster than a 1-byte flag with the word read
+      // one iteration later only where the flag is set, whose dependent load
+      // and branch cost more than the 3 bytes they save)
       const int zl = wrap_any(z0 - 1 + k, nz);
-      if (film) fl_ld = a.flag[(unsigned)(xc + nx * (mc + nm * zl))];
+      if (film) fl_ld = a.mask[(unsigned)(xc + nx * (mc + nm * zl))];
       io.pull(xc, mc, zl, ld);
       if (HIN && has_halo) io.pull(gx, gm, zl, hv);
-    }
-    if (film && k >= 1 && k <= L_ + 2) {
-      // second stage for the plane loaded in the previous iteration
-      const int zp = wrap_any(z0 - 2 + k, nz);
-      fl_mid = fl_mid ? a.mask[(unsigned)(xc + nx * (mc + nm * zp))] : 0u;
     }
     // keep the collide between the loads and their first use
     __builtin_amdgcn_sched_barrier(0);
@@ -474,22 +466,18 @@ struct StepBlock {
 #pragma unroll
       for (int i = 0; i < Q; i++) r += ld[i];
       const T ps = psi_of(r, rho0);
-      if (act) {
-        sm.rho[slot][lm + HM][lx + 1] = r;
-        sm.psi[slot][lm + HM][lx + 1] = ps;
-      }
+      if (act) sm.psi[slot][lm + HM][lx + 1] = ps;
       if (HIN && has_halo) {
         T rh = T(0);
 #pragma unroll
         for (int i = 0; i < Q; i++) rh += hv[i];
-        sm.rho[slot][hm + HM][hx + 1] = rh;
         sm.psi[slot][hm + HM][hx + 1] = psi_of(rh, rho0);
       }
     }
     __syncthreads();
   }
 
-  // halo waves: rho / psi of the ring cells of every loaded plane
+  // halo waves: psi of the ring cells of every loaded plane
   __device__ __forceinline__ void halo_loop() {
     const int kend = L_ + 2;
     for (int k = 0; k <= kend; ++k) {
@@ -500,7 +488,6 @@ struct StepBlock {
 #pragma unroll
         for (int i = 0; i < Q; i++) r += hv[i];
         const int slot = k & 3;
-        sm.rho[slot][hm + HM][hx + 1] = r;
         sm.psi[slot][hm + HM][hx + 1] = psi_of(r, rho0);
       }
       __syncthreads();
@@ -661,11 +648,11 @@ struct StepBlock {
       unsigned g0 = 0, g1 = 0, g2 = 0;
       const int kend = L_ + 2;
       for (int k = 0; k <= kend; k += 3) {
-        iter(k, r0, r1, g0, g2, g1);
+        iter(k, r0, r1, g0, g1);
         if (k + 1 > kend) break;
-        iter(k + 1, r1, r2, g1, g0, g2);
+        iter(k + 1, r1, r2, g1, g2);
         if (k + 2 > kend) break;
-        iter(k + 2, r2, r0, g2, g1, g0);
+        iter(k + 2, r2, r0, g2, g0);
       }
     } else {
       halo_loop();

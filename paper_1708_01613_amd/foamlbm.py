@@ -58,6 +58,11 @@ class flb_stats(C.Structure):
                 ("events_lost", C.c_int32)]
 
 
+class flb_foam_stats(C.Structure):
+    _fields_ = [("n_bubbles", C.c_int32), ("gas_cells", C.c_int64), ("gas_fraction", C.c_double),
+                ("relative_density", C.c_double), ("mean_diameter", C.c_double), ("max_diameter", C.c_double)]
+
+
 class flb_server_config(C.Structure):
     _fields_ = [("pool_bytes", C.c_int64), ("max_jobs", C.c_int32), ("chunk_steps", C.c_int32),
                 ("graph_steps", C.c_int32), ("max_cells", C.c_int64), ("policy", C.c_int32)]
@@ -113,6 +118,7 @@ _SIGS = {
     "flb_get_maps": (C.c_int, [_CTX, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     "flb_get_histogram": (C.c_int, [_CTX, C.c_int32, C.c_double, _L, C.POINTER(C.c_int32)]),
     "flb_get_histogram_noalloc": (C.c_int, [_CTX, C.c_int32, C.c_double, _L, C.POINTER(C.c_int32)]),
+    "flb_get_foam_stats": (C.c_int, [_CTX, C.POINTER(flb_foam_stats)]),
     "flb_match_labels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int32)]),
     "flb_get_rupture_events": (C.c_int, [_CTX, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
@@ -320,6 +326,14 @@ class Sim:
         nb = C.c_int32(0)
         check(flb_get_histogram(self.h, nbins, float(bin_width), counts, C.byref(nb)), "flb_get_histogram")
         return counts, nb.value
+
+    def foam_stats(self):
+        """Virtual-metallography statistics of the current labels (Sec. 5, Table 5)."""
+        s = flb_foam_stats()
+        check(flb_get_foam_stats(self.h, C.byref(s)), "flb_get_foam_stats")
+        return dict(n_bubbles=s.n_bubbles, gas_cells=s.gas_cells, gas_fraction=s.gas_fraction,
+                    relative_density=s.relative_density, mean_diameter=s.mean_diameter,
+                    max_diameter=s.max_diameter)
 
     def match_labels(self, old_labels):
         """(old label, current label, shared cells) for every pair of bubbles of an

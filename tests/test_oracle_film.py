@@ -1,7 +1,9 @@
 """Pins of the oracle's film model: labels, owner/dist maps, barrier links,
 rupture criterion and the film behaviour the paper describes (Sec. 2.1.5, Sec. 4).
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -401,3 +403,34 @@ def test_refresh_labels_density_reading(kind, dims, src):
     s2.step(1)
     ref2, _ = bf.bfs_labels(cur < math.log(2.0), kind)
     assert np.array_equal(s2.maps()["label"].reshape(dims), ref2)
+
+
+def test_foam_statistics_hand_built():
+    # Table 5 of Sec. 5: bubble percentage, foam density (the melt density
+    # times one minus that fraction: 2.7 (1 - 0.443) = 1.50 g/cm^3 as printed)
+    # and the mean bubble size, here from labels of two hand-drawn discs and,
+    # in 3-D, two boxes of known volume
+    rho = np.full((1, 40, 50), 2.0)
+    y, x = np.mgrid[0:40, 0:50]
+    rho[0][(x - 10) ** 2 + (y - 10) ** 2 <= 25] = 0.1     # 81 cells
+    rho[0][(x - 35) ** 2 + (y - 25) ** 2 <= 64] = 0.1     # 197 cells
+    s = _sim_with_density(0, rho)
+    lab, nb = s.label_field(rho[0])
+    st = s.foam_stats(lab, nb)
+    d = [2 * math.sqrt(81 / math.pi), 2 * math.sqrt(197 / math.pi)]
+    assert st["gas_fraction"] == 278 / 2000 and st["relative_density"] == 1 - 278 / 2000
+    assert abs(st["mean_diameter"] - sum(d) / 2) < 1e-14 and st["max_diameter"] == max(d)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    t5 = gold["table5_simulation"]
+    assert abs(t5["melt_density_g_cm3"] * (1 - t5["bubble_fraction"]) - t5["foam_density_g_cm3"]) < 0.005
+    rho3 = np.full((10, 12, 14), 2.0)
+    rho3[1:4, 2:5, 3:8] = 0.1    # 3 x 3 x 5 = 45 cells
+    rho3[6:9, 7:11, 9:11] = 0.1  # 3 x 4 x 2 = 24 cells
+    s3 = _sim_with_density(1, rho3)
+    lab3, nb3 = s3.label_field(rho3)
+    st3 = s3.foam_stats(lab3, nb3)
+    d3 = [(6 * 45 / math.pi) ** (1 / 3), (6 * 24 / math.pi) ** (1 / 3)]
+    assert nb3 == 2 and st3["gas_fraction"] == 69 / rho3.size
+    assert abs(st3["mean_diameter"] - sum(d3) / 2) < 1e-14
+    empty = s.foam_stats(np.zeros((40, 50), np.int32), 0)
+    assert empty["gas_fraction"] == 0 and empty["mean_diameter"] == 0
