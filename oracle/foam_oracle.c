@@ -21,6 +21,7 @@
  *   6. BGK collision  f* = f - (f - f^eq(rho, u_eq)) / tau       (Sec. 2.1.1, collision equation; f^eq equation)
  *   6b. bubble growth (optional) the gas-release law dp/dt = A (dn/dt) / N at
  *                     each of the N domain gas points             (Sec. 2.1.3, Fig. Mainflowchart "Bubble growth")
+ *   6c. body force (optional) the forcing term F_i of gravity     (Sec. 2.1.1, forcing equation)
  *   7. streaming      f_i(x + e_i) = f*_i(x), periodic           (Sec. 2.1.1, streaming equation)
  *   8. rupture test   d2 p0 / dn2 >= 0 on barrier links          (Sec. 2.1.5, eta_m equation; Sec. 4)
  *
@@ -89,6 +90,8 @@ typedef struct {
   int32_t growth_on;      /* 1: gas release at the domain gas points (Sec. 2.1.3) */
   double gas_A;           /* A of the gas-release law (lattice units) */
   double gas_dndt;        /* dn/dt of the gas-release law (lattice units, per step) */
+  double gx, gy, gz;      /* gravity (lattice units); all zero: no body force */
+  double g_rho_ref;       /* the body force is (rho - g_rho_ref) g per cell */
 } or_params;
 
 typedef struct {
@@ -573,6 +576,29 @@ static void one_step(or_sim* s) {
       double feq = s->w[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
       double fi = s->f[(long)i * N + c];
       s->fpost[(long)i * N + c] = fi - (fi - feq) / p->tau;
+    }
+  }
+
+  /* 6c: body force (Sec. 2.1.1, the forcing equation for gravity, read as  */
+  /* He's term: F_i = w_i rho' [(e_i - u).g / c_s^2 + (e_i.u)(e_i.g) / c_s^4] */
+  /* with rho' = rho - g_rho_ref and u the velocity of the equilibrium (R29)). */
+  /* It adds rho' g of momentum and no mass per cell.                       */
+  if (p->gx != 0.0 || p->gy != 0.0 || p->gz != 0.0) {
+    const double g[3] = {p->gx, p->gy, p->gz};
+#pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
+    for (long c = 0; c < N; c++) {
+      double rho = s->rho[c];
+      double u[3];
+      u[0] = (jx[c] + p->tau * s->force[3 * c + 0]) / rho;
+      u[1] = (jy[c] + p->tau * s->force[3 * c + 1]) / rho;
+      u[2] = (jz[c] + p->tau * s->force[3 * c + 2]) / rho;
+      double rb = rho - p->g_rho_ref;
+      double ug = u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
+      for (int i = 0; i < Q; i++) {
+        double eg = s->e[i][0] * g[0] + s->e[i][1] * g[1] + s->e[i][2] * g[2];
+        double eu = s->e[i][0] * u[0] + s->e[i][1] * u[1] + s->e[i][2] * u[2];
+        s->fpost[(long)i * N + c] += s->w[i] * rb * (3.0 * (eg - ug) + 9.0 * eu * eg);
+      }
     }
   }
 

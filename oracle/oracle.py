@@ -27,6 +27,7 @@ class _Params(C.Structure):
         ("on_rupture", C.c_int32), ("velocity_mode", C.c_int32),
         ("refresh_src", C.c_int32), ("growth_on", C.c_int32),
         ("gas_A", C.c_double), ("gas_dndt", C.c_double),
+        ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double), ("g_rho_ref", C.c_double),
     ]
 
 
@@ -34,7 +35,8 @@ DEFAULTS = dict(lattice=0, nx=16, ny=16, nz=1, tau=1.0, G=-5.0, rho0=1.0,
                 rho_liquid=2.0, rho_gas=0.15, noise_amp=0.01, seed=1,
                 film_on=0, k_own=10, zone_width=6, rho_th=math.log(2.0),
                 psi_bar_mode=0, rupture_warmup=200, on_rupture=0, velocity_mode=0,
-                refresh_src=0, growth_on=0, gas_A=0.0, gas_dndt=0.0)
+                refresh_src=0, growth_on=0, gas_A=0.0, gas_dndt=0.0,
+                gx=0.0, gy=0.0, gz=0.0, g_rho_ref=0.0)
 
 _P = C.c_void_p
 _D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")

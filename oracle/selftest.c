@@ -36,6 +36,9 @@ static int run(int lattice, int nx, int ny, int nz, int refresh_src, int growth)
   p.growth_on = growth;
   p.gas_A = 1.0;
   p.gas_dndt = 0.01;
+  p.gy = growth ? 1e-5 : 0.0;
+  p.gx = refresh_src ? -2e-5 : 0.0;
+  p.g_rho_ref = 1.0;
   or_sim* s = or_create(&p);
   if (!s) return 1;
   const long N = or_N(s);
