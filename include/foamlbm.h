@@ -16,7 +16,8 @@
  *   f_i(x + e_i, n + 1) = f*_i(x)                        (streaming equation)
  * optionally the gas release of Sec. 2.1.3 (dp/dt = A (dn/dt) / N at each of
  * the N domain gas points, added as the density 3 A (dn/dt) / N after the
- * collision), and, on active barrier links from step rupture_warmup on, the FP64 test
+ * collision), optionally a body force (the forcing term of Sec. 2.1.1 for
+ * gravity), and, on active barrier links from step rupture_warmup on, the FP64 test
  * p0(rho(x+e_i)) - 2 p0(rho(x)) + p0(rho(x-e_i)) >= 0 with
  * p0 = rho/3 + (G/6) psi^2 (Eq. Pequ; eta_m equation), which removes the
  * barrier between that pair of bubbles from step n+1 on.
@@ -120,12 +121,19 @@ typedef struct {
                             2^-12 |rho - f16_rho_ref| / rho of f_i at density rho, so a value
                             between the phase densities (their harmonic mean balances the
                             relative error of both phases) suits two-phase runs; >= 0 */
+  double gx, gy, gz;     /* gravity, lattice units (gz == 0 on D2Q9); all zero: no body force.
+                            Added after the collision as the forcing term of Sec. 2.1.1:
+                            F_i = w_i (rho - g_rho_ref) [(e_i - u).g / c_s^2 +
+                            (e_i.u)(e_i.g) / c_s^4], u the velocity of the equilibrium;
+                            it adds (rho - g_rho_ref) g of momentum and no mass per cell */
+  double g_rho_ref;      /* reference density of the body force (the mean density gives
+                            the buoyancy form, no net force on a periodic lattice) */
 } flb_params;
 
 /* Fills p with defaults: D2Q9 F32 64x64x1, tau 1, G -5, rho0 1, rho_liquid 2,
  * rho_gas 0.15, noise 0.01, seed 1, film off, k_own 10, zone_width 6,
  * rho_th ln 2, psi_bar_mode 0, rupture_warmup 200, on_rupture 0, velocity 0,
- * rupture_filter 1, refresh_src 0, growth off (A = dn/dt = 0), f16_rho_ref 1. */
+ * rupture_filter 1, refresh_src 0, growth off (A = dn/dt = 0), f16_rho_ref 1, no gravity. */
 void flb_default_params(flb_params* p);
 
 /* A gas nucleus: centre (cell centres at integer coordinates) and radius. */

@@ -14,23 +14,23 @@
 
 namespace flb_rt {
 
-// grow: some member has the gas-release source (the members without it skip
-// the source inside that variant)
+// ext: some member has a source term, the gas release or the body force (the
+// members without them skip them inside that variant)
 using BatchStepFn = void (*)(const StepArgs*, const int*, int, int, bool, bool, hipStream_t);
 
-template <class L, class S, int TX, int TM, bool GROW>
+template <class L, class S, int TX, int TM, bool EXT>
 void launch_step_batch_g(const StepArgs* tab, const int* first, int nmem, int nblk, bool buf, hipStream_t s) {
   if (buf)
-    hipLaunchKernelGGL((k_step_batch<L, S, TX, TM, true, GROW>), dim3(nblk),
-                       dim3(StepBlock<L, S, TX, TM, true, GROW>::NT), 0, s, tab, first, nmem);
+    hipLaunchKernelGGL((k_step_batch<L, S, TX, TM, true, EXT>), dim3(nblk),
+                       dim3(StepBlock<L, S, TX, TM, true, EXT>::NT), 0, s, tab, first, nmem);
   else
-    hipLaunchKernelGGL((k_step_batch<L, S, TX, TM, false, GROW>), dim3(nblk),
-                       dim3(StepBlock<L, S, TX, TM, false, GROW>::NT), 0, s, tab, first, nmem);
+    hipLaunchKernelGGL((k_step_batch<L, S, TX, TM, false, EXT>), dim3(nblk),
+                       dim3(StepBlock<L, S, TX, TM, false, EXT>::NT), 0, s, tab, first, nmem);
 }
 template <class L, class S, int TX, int TM>
-void launch_step_batch(const StepArgs* tab, const int* first, int nmem, int nblk, bool buf, bool grow,
+void launch_step_batch(const StepArgs* tab, const int* first, int nmem, int nblk, bool buf, bool ext,
                        hipStream_t s) {
-  if (grow) launch_step_batch_g<L, S, TX, TM, true>(tab, first, nmem, nblk, buf, s);
+  if (ext) launch_step_batch_g<L, S, TX, TM, true>(tab, first, nmem, nblk, buf, s);
   else launch_step_batch_g<L, S, TX, TM, false>(tab, first, nmem, nblk, buf, s);
 }
 
@@ -85,7 +85,7 @@ struct flb_batch {
   flb_rt::MapSet fms;  // film refresh of the film members, one launch per map kernel
   flb_rt::Fork fork;   // side stream of the refresh
   bool dirty = true;
-  bool grow = false;  // some member has the gas-release source
+  bool ext = false;  // some member has a source term (gas release, body force)
   // graphs
   int graph_steps = 16;
   hipGraphExec_t gexec = nullptr;
@@ -145,10 +145,10 @@ inline int rebuild(flb_batch* b) {
     if (b->m[k]->fbytes >= kBufPathLimit) b->buf = false;
   }
   b->film.clear();
-  b->grow = false;
+  b->ext = false;
   for (int k = 0; k < n; k++) {
     if (b->m[k]->p.film_on) b->film.push_back(k);
-    if (b->m[k]->p.growth_on) b->grow = true;
+    if (tab[k].srcw || tab[k].force_on) b->ext = true;
   }
   const int nf = (int)b->film.size();
   std::vector<StepArgs> ftab(nf);
@@ -207,7 +207,7 @@ int batch_one_step(flb_batch* b) {
     if (rc) return rc;
   }
   const int n = (int)b->m.size();
-  b->step_fn()(b->tab, b->first, n, b->nblk, b->buf, b->grow, b->st);
+  b->step_fn()(b->tab, b->first, n, b->nblk, b->buf, b->ext, b->st);
   const int nf = (int)b->film.size();
   if (nf) {
     hipLaunchKernelGGL((k_rupture_batch<L, typename S::ct>), dim3(b->fblk), dim3(MAP_NT), 0, b->st, b->ftab,
@@ -318,9 +318,9 @@ inline int time_trial(flb_batch* b, int reps, void* const* scratch, Ctl* sctl, f
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  b->step_fn()(b->tab, b->first, n, b->nblk, b->buf, b->grow, b->st);  // warm-up launch
+  b->step_fn()(b->tab, b->first, n, b->nblk, b->buf, b->ext, b->st);  // warm-up launch
   hipError_t e = hipEventRecord(e0, b->st);
-  for (int r = 0; r < reps && e == hipSuccess; r++) b->step_fn()(b->tab, b->first, n, b->nblk, b->buf, b->grow, b->st);
+  for (int r = 0; r < reps && e == hipSuccess; r++) b->step_fn()(b->tab, b->first, n, b->nblk, b->buf, b->ext, b->st);
   if (e == hipSuccess) e = hipEventRecord(e1, b->st);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);

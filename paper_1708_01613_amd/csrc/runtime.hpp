@@ -46,19 +46,19 @@ inline int fail(int code, const char* fmt, ...) {
 using StepFn = void (*)(const StepArgs&, int, hipStream_t);
 
 // buffers below 2 GiB use buffer-resource loads with 32-bit offsets; the
-// gas-release source has a variant of its own
-template <class L, class S, int TX, int TM, bool GROW>
+// source terms (gas release, body force) have a variant of their own
+template <class L, class S, int TX, int TM, bool EXT>
 void launch_step_g(const StepArgs& a, int nblk, hipStream_t s) {
   if (a.buf_bytes < kBufPathLimit)
-    hipLaunchKernelGGL((k_step<L, S, TX, TM, true, GROW>), dim3(nblk), dim3(StepBlock<L, S, TX, TM, true, GROW>::NT),
+    hipLaunchKernelGGL((k_step<L, S, TX, TM, true, EXT>), dim3(nblk), dim3(StepBlock<L, S, TX, TM, true, EXT>::NT),
                        0, s, a);
   else
-    hipLaunchKernelGGL((k_step<L, S, TX, TM, false, GROW>), dim3(nblk),
-                       dim3(StepBlock<L, S, TX, TM, false, GROW>::NT), 0, s, a);
+    hipLaunchKernelGGL((k_step<L, S, TX, TM, false, EXT>), dim3(nblk),
+                       dim3(StepBlock<L, S, TX, TM, false, EXT>::NT), 0, s, a);
 }
 template <class L, class S, int TX, int TM>
 void launch_step(const StepArgs& a, int nblk, hipStream_t s) {
-  if (a.srcw) launch_step_g<L, S, TX, TM, true>(a, nblk, s);
+  if (a.srcw || a.force_on) launch_step_g<L, S, TX, TM, true>(a, nblk, s);
   else launch_step_g<L, S, TX, TM, false>(a, nblk, s);
 }
 
@@ -334,6 +334,14 @@ inline StepArgs step_args(flb_ctx* c) {
   if (c->p.growth_on) {
     a.srcw = c->srcw;  // the kernels read N from the run control
     a.src_rate = c->p.gas_A * c->p.gas_dndt;
+  }
+  if (c->p.gx != 0.0 || c->p.gy != 0.0 || c->p.gz != 0.0) {
+    // gravity in kernel coordinates: D2Q9 (x, y) -> (x, z)
+    a.force_on = 1;
+    a.gk[0] = c->p.gx;
+    a.gk[1] = c->D == 3 ? c->p.gy : 0.0;
+    a.gk[2] = c->D == 3 ? c->p.gz : c->p.gy;
+    a.g_rho_ref = c->p.g_rho_ref;
   }
   a.flag = c->flag;
   a.mask = c->mask;
@@ -654,6 +662,9 @@ inline int validate(const flb_params* p) {
   if (p->growth_on != 0 && p->growth_on != 1) return fail(FLB_EINVAL, "growth_on must be 0 or 1");
   if (!isfinite(p->gas_A) || !isfinite(p->gas_dndt)) return fail(FLB_EINVAL, "non-finite gas-release parameter");
   if (!(p->f16_rho_ref >= 0.0) || !(p->f16_rho_ref <= 1e4)) return fail(FLB_EINVAL, "f16_rho_ref must be in 0..1e4");
+  if (!isfinite(p->gx) || !isfinite(p->gy) || !isfinite(p->gz) || !isfinite(p->g_rho_ref))
+    return fail(FLB_EINVAL, "non-finite body-force parameter");
+  if (p->lattice == FLB_D2Q9 && p->gz != 0.0) return fail(FLB_EINVAL, "D2Q9 requires gz == 0");
   return FLB_OK;
 }
 

@@ -42,6 +42,9 @@ struct StepArgs {
                                    // one word per 64-cell row block (population block order); null: off
   double src_rate;       // A (dn/dt) of the gas-release law; a step adds the density 3 A (dn/dt) / N
                          // at each of the ctl->n_src = N domain gas points
+  int force_on;          // 1: body force of gravity gk (kernel coordinates) on rho - g_rho_ref
+  double gk[3];
+  double g_rho_ref;
   int* alias;            // union-find parents over labels
   unsigned long long buf_bytes;  // bytes of one population buffer
   long long* events;     // rupture log, 4 x int64 per event: step, k, k2, 0
@@ -137,6 +140,12 @@ __device__ __forceinline__ unsigned active_links(const StepArgs& a, int x, int m
   }
   return act;
 }
+
+// a + b rounded on its own: never fused with the arithmetic that produced a,
+// so adding the source terms (zero when they are off) leaves a's rounding
+// exactly as in the kernels that do not add them
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
 
 template <class T>
 __device__ __forceinline__ T psi_of(T rho, T rho0) {
@@ -399,7 +408,7 @@ static __global__ __launch_bounds__(FIN_NT) void k_step_finish_batch(const StepA
 // z0-1+j; a collide at iteration k reads slots k-3..k-1, and the slot written
 // at iteration k was last read before the barrier of iteration k-1.  The three
 // register sets rotate by unrolling the loop three times.
-template <class L, class S, int TX, int TM, bool BUF, bool GROW>
+template <class L, class S, int TX, int TM, bool BUF, bool EXT>
 struct StepBlock {
   using T = typename S::ct;
   static constexpr int Q = L::Q;
@@ -426,8 +435,8 @@ struct StepBlock {
   Ctl* ctl;
   long long step;
   int nx, nm, nz, x0, m0, z0, L_, TXe, TMe, lx, lm, x, m, xc, mc, gx, gm, hx, hm;
-  bool act, has_halo, film, grow, test_rupture, tau_one, rho_all;
-  T G, rho0, tau, omega, psi_bar, drho;
+  bool act, has_halo, film, grow, force, test_rupture, tau_one, rho_all;
+  T G, rho0, tau, omega, psi_bar, drho, gkx, gkm, gkz, grho;
   double acc_m = 0.0, acc_x = 0.0, acc_y = 0.0, acc_z = 0.0;
 
   __device__ __forceinline__ StepBlock(const StepArgs& a_, Smem& sm_) : a(a_), sm(sm_) {}
@@ -495,6 +504,10 @@ struct StepBlock {
   }
 
   __device__ __forceinline__ void collide(int k, const T (&f)[Q], unsigned flag) {
+    // every operation rounds on its own (no contraction into fused
+    // multiply-adds): the kernel variants and the two-pass path then give
+    // the same values bit for bit whatever other code the compiler sees
+#pragma clang fp contract(off)
     const int zc = z0 + k - 3;
     const int sl[3] = {(k - 3) & 3, (k - 2) & 3, (k - 1) & 3};
     // lanes outside the lattice compute on clamped data and store to an
@@ -545,10 +558,19 @@ struct StepBlock {
     // one per 64-cell row block: with tiles a whole number of rows wide a
     // wavefront reads one word, through the scalar cache
     T ds = T(0);
-    if (GROW && grow) {
+    if (EXT && grow) {
       unsigned widx = (unsigned)(xc >> 6) + (unsigned)a.geo.nxb * (unsigned)(mc + nm * zc);
       if constexpr (TX % 64 == 0) widx = __builtin_amdgcn_readfirstlane(widx);
       if ((a.srcw[widx] >> (xc & 63)) & 1ull) ds = drho;
+    }
+    // body force (Sec. 2.1.1, forcing equation): F_i = w_i rho' [3 (e_i.g -
+    // u.g) + 9 (e_i.u)(e_i.g)], rho' = rho - g_rho_ref, u the equilibrium's
+    // velocity; per opposite pair its even part w rho' (9 (e.u)(e.g) - 3 u.g)
+    // and its odd part w rho' 3 e.g
+    T rbg = T(0), ug = T(0);
+    if (EXT && force) {
+      rbg = rho - grho;
+      ug = ux * gkx + um * gkm + uz * gkz;
     }
     // equilibria in opposite pairs: common part w rho (base + 4.5 (e.u)^2),
     // odd part w rho 3 e.u; the rest equilibrium is rho minus the moving ones
@@ -566,12 +588,26 @@ struct StepBlock {
       const T odd = wr * (T(3) * eu);
       const T fp = even + odd, fq = even - odd;
       feq_moving += fp + fq;
-      const T wd = (T)L::w[i] * ds;
-      io.store_at(i, vo, (tau_one ? fp : f[i] - (f[i] - fp) * omega) + wd);
-      io.store_at(i + 1, vo, (tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega) + wd);
+      T se = (T)L::w[i] * ds, so = T(0);  // source terms of this pair: even and odd parts
+      if (EXT && force) {
+        T eg = T(0);
+        if (L::ex[i]) eg += L::ex[i] > 0 ? gkx : -gkx;
+        if (L::em[i]) eg += L::em[i] > 0 ? gkm : -gkm;
+        if (L::ez[i]) eg += L::ez[i] > 0 ? gkz : -gkz;
+        const T wb = (T)L::w[i] * rbg;
+        se += wb * (T(9) * eu * eg - T(3) * ug);
+        so = wb * (T(3) * eg);
+      }
+      const T yp = tau_one ? fp : f[i] - (f[i] - fp) * omega;
+      const T yq = tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega;
+      io.store_at(i, vo, EXT ? add_rn(yp, se + so) : yp);
+      io.store_at(i + 1, vo, EXT ? add_rn(yq, se - so) : yq);
     }
     const T feq0 = rho - feq_moving;
-    io.store_at(0, vo0, (tau_one ? feq0 : f[0] - (f[0] - feq0) * omega) + (T)L::w[0] * ds);
+    T s0 = (T)L::w[0] * ds;
+    if (EXT && force) s0 += (T)L::w[0] * rbg * (T(-3) * ug);
+    const T y0 = tau_one ? feq0 : f[0] - (f[0] - feq0) * omega;
+    io.store_at(0, vo0, EXT ? add_rn(y0, s0) : y0);
     // the rupture test runs in its own kernel after this one, on the
     // densities of the state entering the step
     if (act && (rho_all || (test_rupture && (flag & kRhoBit)))) ((T*)a.rho)[c] = rho;
@@ -637,7 +673,12 @@ struct StepBlock {
     omega = T(1) / (T)a.tau;
     tau_one = a.tau == 1.0;
     film = a.film_on != 0;
-    grow = GROW && a.srcw != nullptr && ctl->n_src > 0;
+    grow = EXT && a.srcw != nullptr && ctl->n_src > 0;
+    force = EXT && a.force_on;
+    gkx = (T)a.gk[0];
+    gkm = (T)a.gk[1];
+    gkz = (T)a.gk[2];
+    grho = (T)a.g_rho_ref;
     drho = grow ? (T)(3.0 * (a.src_rate / (double)ctl->n_src)) : T(0);
     test_rupture = film && step >= a.rupture_warmup;
     rho_all = a.gas_k > 0 && (step + 1) % a.gas_k == 0;
@@ -662,21 +703,22 @@ struct StepBlock {
   }
 };
 
-// GROW: the variant with the gas-release source (its code costs registers,
-// so lattices without the source run the variant without it)
-template <class L, class S, int TX, int TM, bool BUF, bool GROW>
-__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF, GROW>::NT)) void k_step(StepArgs a) {
-  using SB = StepBlock<L, S, TX, TM, BUF, GROW>;
+// EXT: the variant with the source terms after the collision, the gas release
+// and the body force (their code costs registers, so lattices without them
+// run the variant without it)
+template <class L, class S, int TX, int TM, bool BUF, bool EXT>
+__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF, EXT>::NT)) void k_step(StepArgs a) {
+  using SB = StepBlock<L, S, TX, TM, BUF, EXT>;
   __shared__ typename SB::Smem sm;
   if (a.ctl->stopped) return;
   SB blk(a, sm);
   blk.run(blockIdx.x, gridDim.x);
 }
 
-template <class L, class S, int TX, int TM, bool BUF, bool GROW>
-__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF, GROW>::NT)) void k_step_batch(
+template <class L, class S, int TX, int TM, bool BUF, bool EXT>
+__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF, EXT>::NT)) void k_step_batch(
     const StepArgs* __restrict__ tab, const int* __restrict__ first, int nmem) {
-  using SB = StepBlock<L, S, TX, TM, BUF, GROW>;
+  using SB = StepBlock<L, S, TX, TM, BUF, EXT>;
   __shared__ typename SB::Smem sm;
   const int k = batch_member(first, nmem, blockIdx.x);
   const StepArgs& a = tab[k];  // read in place: a local copy would live in scratch

@@ -74,6 +74,8 @@ __global__ __launch_bounds__(TP_NT) void k_psi(StepArgs a) {
 
 template <class L, class S, bool BUF>
 __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
+  // the same uncontracted arithmetic as the fused kernel's collide
+#pragma clang fp contract(off)
   using T = typename S::ct;
   constexpr int Q = L::Q;
   __shared__ double red[TP_NT / 64][4];
@@ -149,6 +151,11 @@ __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
   const long long nsrc = a.srcw ? a.ctl->n_src : 0;
   const bool src = nsrc > 0 && ((a.srcw[(xc >> 6) + a.geo.nxb * row] >> (xc & 63)) & 1ull);
   const T ds = src ? (T)(3.0 * (a.src_rate / (double)nsrc)) : T(0);
+  // body force (Sec. 2.1.1, forcing equation), as in the fused kernel
+  const bool force = a.force_on != 0;
+  const T gkx = (T)a.gk[0], gkm = (T)a.gk[1], gkz = (T)a.gk[2];
+  const T rbg = force ? rho - (T)a.g_rho_ref : T(0);
+  const T ug = force ? ux * gkx + um * gkm + uz * gkz : T(0);
   // paired equilibria; the rest equilibrium is rho minus the moving ones
   T feq_moving = T(0);
 #pragma unroll
@@ -162,12 +169,25 @@ __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
     const T odd = wr * (T(3) * eu);
     const T fp = even + odd, fq = even - odd;
     feq_moving += fp + fq;
-    const T wd = (T)L::w[i] * ds;
-    io.store_at(i, vo, (tau_one ? fp : f[i] - (f[i] - fp) * omega) + wd);
-    io.store_at(i + 1, vo, (tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega) + wd);
+    T se = (T)L::w[i] * ds, so = T(0);  // source terms (gas release, body force): even and odd parts
+    if (force) {
+      T eg = T(0);
+      if (L::ex[i]) eg += L::ex[i] > 0 ? gkx : -gkx;
+      if (L::em[i]) eg += L::em[i] > 0 ? gkm : -gkm;
+      if (L::ez[i]) eg += L::ez[i] > 0 ? gkz : -gkz;
+      const T wb = (T)L::w[i] * rbg;
+      se += wb * (T(9) * eu * eg - T(3) * ug);
+      so = wb * (T(3) * eg);
+    }
+    // the source terms are added on their own (zero when off: the fused
+    // kernel's values exactly)
+    io.store_at(i, vo, add_rn(tau_one ? fp : f[i] - (f[i] - fp) * omega, se + so));
+    io.store_at(i + 1, vo, add_rn(tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega, se - so));
   }
   const T feq0 = rho - feq_moving;
-  io.store_at(0, vo0, (tau_one ? feq0 : f[0] - (f[0] - feq0) * omega) + (T)L::w[0] * ds);
+  T s0 = (T)L::w[0] * ds;
+  if (force) s0 += (T)L::w[0] * rbg * (T(-3) * ug);
+  io.store_at(0, vo0, add_rn(tau_one ? feq0 : f[0] - (f[0] - feq0) * omega, s0));
 
   // the rupture test runs in its own kernel, on the rho array of k_psi
   const double keep = act ? 1.0 : 0.0;

@@ -45,6 +45,7 @@ class flb_params(C.Structure):
         ("refresh_src", C.c_int32), ("growth_on", C.c_int32),
         ("gas_A", C.c_double), ("gas_dndt", C.c_double),
         ("f16_rho_ref", C.c_double),
+        ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double), ("g_rho_ref", C.c_double),
     ]
 
 

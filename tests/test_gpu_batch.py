@@ -132,7 +132,9 @@ def test_batch_with_gas_release_matches_solo(flb):
     for k, (p, _) in enumerate(members):
         if k % 3 != 1:
             p.update(growth_on=1, gas_A=1.0 + k, gas_dndt=0.01)
-    _say("batch of 6 D2Q9 f32, gas release in 4 members")
+        if k % 2 == 1:
+            p.update(gx=1e-5 * k, gy=-2e-5, g_rho_ref=1.5)
+    _say("batch of 6 D2Q9 f32, gas release in 4 members, gravity in 3")
     b = flb.Batch([p for p, _ in members])
     for k, (_, nuc) in enumerate(members):
         b.members[k].set_nuclei(nuc)

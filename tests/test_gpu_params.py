@@ -29,7 +29,8 @@ def flb():
     return foamlbm
 
 
-def _case(kind, storage, tau=1.0, rho0=1.0, psi_bar_mode=0, refresh_src=0, growth=0, velocity_mode=1, **kw):
+def _case(kind, storage, tau=1.0, rho0=1.0, psi_bar_mode=0, refresh_src=0, growth=0, velocity_mode=1, gravity=None,
+          g_rho_ref=0.0, **kw):
     # the rho0-scaled problem: psi = rho0 phi(rho / rho0) with G rho0 and the
     # densities / rho0 held fixed is the same physics at another scale
     p = dict(lattice=kind, storage=storage, tau=tau, rho0=rho0, G=-5.5 / rho0, rho_liquid=2.3 * rho0,
@@ -38,6 +39,8 @@ def _case(kind, storage, tau=1.0, rho0=1.0, psi_bar_mode=0, refresh_src=0, growt
              velocity_mode=velocity_mode, seed=5)
     if growth:
         p.update(growth_on=1, gas_A=1.5 * rho0, gas_dndt=0.01)
+    if gravity is not None:
+        p.update(gx=gravity[0], gy=gravity[1], gz=gravity[2] if kind == 1 else 0.0, g_rho_ref=g_rho_ref)
     if kind == 0:
         p.update(nx=72, ny=44, nz=1)
         nuc = [[20.0, 22.0, 0, 9.0], [40.5, 22.0, 0, 9.0], [60.0, 8.0, 0, 5.0]]
@@ -96,6 +99,8 @@ CASES = [
     dict(tau=1.3, rho0=0.5, refresh_src=1),
     dict(tau=1.0, rho0=1.5, growth=1, refresh_src=0),
     dict(tau=0.75, growth=1, psi_bar_mode=1, refresh_src=1),
+    dict(tau=0.9, gravity=(2e-5, -3e-5, 1e-5), g_rho_ref=1.8),
+    dict(tau=1.0, gravity=(-1e-5, 2e-5, -2e-5), growth=1, refresh_src=1),
 ]
 
 
@@ -116,7 +121,8 @@ def test_parameter_paths(flb, kind, storage, case):
 
 @pytest.mark.parametrize("kind", [0, 1])
 def test_two_pass_variant_parameter_paths(flb, kind):
-    p, nuc, steps = _case(kind, "f64", tau=0.8, growth=1, psi_bar_mode=1)
+    p, nuc, steps = _case(kind, "f64", tau=0.8, growth=1, psi_bar_mode=1, gravity=(1e-5, -2e-5, 1.5e-5),
+                          g_rho_ref=1.0)
     ntiles = flb.Sim(**p).tuning()["n_tiles"]
     g, o = _run(flb, p, nuc, steps, tile=ntiles - 1)  # the two-pass variant is the last
     _check(flb, kind, "f64", g, o)
