@@ -8,9 +8,10 @@
       HBM bytes per dispatch of the kernels whose name starts with NAME, from
       two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of a program
       that also copies a buffer of --copy-bytes bytes device to device
-      (bench.py's copy-ceiling measurement does, 1 GiB).  Each counter is
-      scaled by the factor that makes it read the known size for that copy
-      (the largest-grid __amd_rocclr_copyBuffer dispatches).
+      (bench.py's copy-ceiling measurement does, 1 GiB, with the library's
+      k_copy16).  Each counter is scaled by the factor that makes it read the
+      known size for that copy (every k_copy16 dispatch, or else the
+      largest-grid __amd_rocclr_copyBuffer dispatches).
 """
 import argparse
 import csv
@@ -50,11 +51,13 @@ def _per_dispatch(rows, counter):
 
 def _scaled(d, counter, kernel, copy_bytes):
     disp = _per_dispatch(_csv(d, "counter_collection.csv"), counter)
-    copies = [(g, v) for n, g, v in disp.values() if n.startswith("__amd_rocclr_copyBuffer")]
-    if not copies:
-        sys.exit(f"{d}: no copy dispatches to calibrate {counter}")
-    gmax = max(g for g, _ in copies)
-    cal = [v for g, v in copies if g == gmax]
+    cal = [v for n, _, v in disp.values() if "k_copy16" in n]
+    if not cal:
+        copies = [(g, v) for n, g, v in disp.values() if n.startswith("__amd_rocclr_copyBuffer")]
+        if not copies:
+            sys.exit(f"{d}: no copy dispatches to calibrate {counter}")
+        gmax = max(g for g, _ in copies)
+        cal = [v for g, v in copies if g == gmax]
     factor = copy_bytes / (sum(cal) / len(cal) * 1024.0)
     vals = [v for n, _, v in disp.values() if n.startswith(kernel)]
     if not vals:

@@ -48,3 +48,27 @@ def test_stats_table_orders_by_total_time(tmp_path):
         w.writerow(["big", 2, 9000, 4500, 4000, 5000, 90.0])
     lines = profsum.stats(str(tmp_path), 5).splitlines()
     assert lines[2].startswith("| `big` | 2 | 4.5 |") and lines[3].startswith("| `small` | 10 | 0.1 |")
+
+
+def test_traffic_calibrates_on_the_library_copy_kernel(tmp_path):
+    # with k_copy16 dispatches present they calibrate (every one copies the
+    # full size), whatever other copies the program made
+    fd, wd = tmp_path / "f", tmp_path / "w"
+    fd.mkdir()
+    wd.mkdir()
+    gib = 1 << 30
+    name = "void flb::k_copy16<4>(float __vector(4) const*, float __vector(4)*, long long)"
+    _counters(fd / "run_counter_collection.csv", [
+        (1, name, 8192 * 256, "FETCH_SIZE", gib / 1024),
+        (2, name, 32768 * 256, "FETCH_SIZE", gib / 1024),
+        (3, "__amd_rocclr_copyBuffer", 131072, "FETCH_SIZE", 7.0),
+        (4, "void flb::k_step<X>(args)", 4096, "FETCH_SIZE", 6.0),
+    ])
+    _counters(wd / "run_counter_collection.csv", [
+        (1, name, 8192 * 256, "WRITE_SIZE", gib / 2 / 1024),
+        (4, "void flb::k_step<X>(args)", 4096, "WRITE_SIZE", 2.0),
+    ])
+    out = profsum.traffic(str(fd), str(wd), "void flb::k_step<X>", gib, 0)
+    vals = dict(line[2:].split(": ", 1) for line in out.splitlines() if line.startswith("- "))
+    assert float(vals["hbm_read_bytes_per_launch"]) == 6 * 1024
+    assert float(vals["hbm_write_bytes_per_launch"]) == 2 * 2 * 1024
