@@ -115,16 +115,22 @@ int flb_batch_autotune(flb_batch* b, int32_t reps, double* best_ms) {
   if (reps < 1 || reps > 1000) return fail(FLB_EINVAL, "reps must be in 1..1000");
   HIPCHK(hipStreamSynchronize(b->st));
   const int n = (int)b->m.size();
+  // one allocation: per member its populations, then its densities (trials
+  // keep the member's own), each part 256-byte aligned; the run-control
+  // copies at the end
   std::vector<void*> scratch(n, nullptr);
-  bool ok = true;
-  // per member: populations, then densities (trials keep the member's own)
-  for (int k = 0; k < n && ok; k++) {
+  std::vector<size_t> ofs(n + 1, 0);
+  for (int k = 0; k < n; k++) {
     const flb_ctx* c = b->m[k];
     const size_t tsz = c->p.storage == FLB_F64 ? 8 : 4;
-    ok = (scratch[k] = b->dalloc(c->fbytes + tsz * (size_t)c->N)) != nullptr;
+    ofs[k + 1] = ofs[k] + ((c->fbytes + tsz * (size_t)c->N + 255) & ~(size_t)255);
   }
-  Ctl* sctl = ok ? (Ctl*)b->dalloc(sizeof(Ctl) * n) : nullptr;
-  int rc = (ok && sctl) ? FLB_OK : fail(FLB_ENOMEM, "autotune scratch allocation failed");
+  const size_t total = ofs[n] + sizeof(Ctl) * n;
+  char* base = (char*)b->dalloc(total);
+  Ctl* sctl = base ? (Ctl*)(base + ofs[n]) : nullptr;
+  for (int k = 0; k < n && base; k++) scratch[k] = base + ofs[k];
+  int rc = base ? FLB_OK
+                : fail(FLB_ENOMEM, "autotune scratch allocation of %zu bytes (%d members) failed", total, n);
   const long long targets[] = {256, 512, 1024, 2048, 4096, 8192};
   const int xcds[] = {0, 8};
   float best = 1e30f;
@@ -147,8 +153,7 @@ int flb_batch_autotune(flb_batch* b, int32_t reps, double* best_ms) {
         }
       }
   (void)hipStreamSynchronize(b->st);
-  for (void* p : scratch) b->dfree(p);
-  b->dfree(sctl);
+  b->dfree(base);
   b->tile = bt;
   b->target = bg;
   b->xcd = bx;
