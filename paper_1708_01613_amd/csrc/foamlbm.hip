@@ -157,6 +157,7 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     ok = ok && (c->rep = (int*)c->dalloc(sizeof(int) * (size_t)(c->N + 1)));
     ok = ok && (c->events = (long long*)c->dalloc(sizeof(long long) * 4 * (size_t)c->ev_cap));
     ok = ok && (c->bits = (unsigned long long*)c->dalloc(sizeof(unsigned long long) * (size_t)c->nwords));
+    ok = ok && (c->bfw = (unsigned long long*)c->dalloc(3 * sizeof(unsigned long long) * (size_t)c->nwords));
   }
   if (ok && p->growth_on)
     ok = ok && (c->srcw = (unsigned long long*)c->dalloc(sizeof(unsigned long long) * (size_t)c->nwords));
@@ -448,14 +449,14 @@ int flb_get_maps(flb_ctx* c, int32_t* label, int32_t* owner, int32_t* owner2, in
     own.resize(n);
     HIPCHK(hipMemcpyAsync(own.data(), c->own, sizeof(int2) * n, hipMemcpyDeviceToHost, c->st));
   }
-  if (dist) {
+  if (owner || owner2 || dist) {  // unreached cells (dist 255) have no owners
     d8.resize(n);
     HIPCHK(hipMemcpyAsync(d8.data(), c->dist, n, hipMemcpyDeviceToHost, c->st));
   }
   HIPCHK(hipStreamSynchronize(c->st));
   for (size_t k = 0; k < n; k++) {
-    if (owner) owner[k] = own[k].x;
-    if (owner2) owner2[k] = own[k].y;
+    if (owner) owner[k] = d8[k] == 255 ? 0 : own[k].x;
+    if (owner2) owner2[k] = d8[k] == 255 ? 0 : own[k].y;
     if (dist) dist[k] = d8[k] == 255 ? -1 : d8[k];
     if (mask) mask[k] &= kLinkBits;  // link bits only
   }

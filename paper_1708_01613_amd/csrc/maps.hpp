@@ -28,6 +28,33 @@
 
 namespace flb {
 
+// Pointers of the map tables are plain (generic) pointers, and accesses
+// through them compile to flat memory instructions; these casts name the
+// address space, so the accesses become global (or, for data a kernel only
+// reads, scalar-capable constant) memory instructions.
+#define FLB_AS_GLOBAL __attribute__((address_space(1)))
+#define FLB_AS_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ FLB_AS_GLOBAL T* as_global(T* p) {
+  return (FLB_AS_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const FLB_AS_GLOBAL T* as_global(const T* p) {
+  return (const FLB_AS_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const FLB_AS_CONST T* as_const(const T* p) {
+  return (const FLB_AS_CONST T*)p;
+}
+// owner pairs (int2) through the global address space, as 64-bit words
+__device__ __forceinline__ int2 ld_pair(const int2* p, unsigned i) {
+  const long long v = as_global((const long long*)p)[i];
+  return make_int2((int)v, (int)(v >> 32));
+}
+__device__ __forceinline__ void st_pair(int2* p, unsigned i, int2 v) {
+  as_global((long long*)p)[i] = (long long)((unsigned long long)(unsigned)v.x | ((unsigned long long)(unsigned)v.y << 32));
+}
+
 struct MapDims {
   int nx, nm, nz;  // kernel coordinates
   long long N;
@@ -143,6 +170,7 @@ struct MapArgs {
   uint32_t* mask;
   int* flist;
   unsigned long long* fwords;  // flag words: bit l of word s = cell 64 xs + l of its row has links
+  unsigned long long* bfw;     // BFS frontier words, 3 slots of one bit per cell (layer L in slot L % 3)
 };
 
 __device__ __forceinline__ bool map_due(const MapArgs& m) {
@@ -151,7 +179,7 @@ __device__ __forceinline__ bool map_due(const MapArgs& m) {
 }
 
 // decompositions of a map launch (workgroups per lattice)
-enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_BFST, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_COUNT };
+enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_BFST, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_BFSB, SH_FEW, SH_COUNT };
 
 #define MAP_KERNEL_PARAMS const MapArgs *__restrict__ tab, const int *__restrict__ first, int nmem
 #define MAP_MEMBER                                                           \
@@ -174,53 +202,36 @@ __device__ __forceinline__ bool run_head(int a, int b) {
 // grid-stride over [0, n) within a lattice's share
 #define FOR_SHARE(i, n) for (long long i = bid * (long long)blockDim.x + threadIdx.x; i < (n); i += (long long)nbk * blockDim.x)
 
-// ---- gas flags: par[c] = c for gas cells, -1 otherwise ----
-template <class L, class S, int SRC>
-__global__ __launch_bounds__(MAP_NT) void k_gas(MAP_KERNEL_PARAMS) {
-  MAP_MEMBER
-  if (!map_due(m)) return;
-  if (SRC == GAS_AUTO && m.sctl->steps > 0 && m.sctl->rho_step == m.sctl->steps - 1) {
-    // the densities the previous step stored for this refresh (cell-linear)
-    const typename S::ct* __restrict__ rho = (const typename S::ct*)m.src;
-    FOR_SHARE(c, m.d.N) m.par[c] = (double)rho[c] < m.rho_th ? (int)c : -1;
-  } else if constexpr (SRC == GAS_POP || SRC == GAS_AUTO) {
-    // density of the stored state, summed in FP64
-    const void* src = (m.sctl->steps & 1) ? m.b1 : m.b0;
-    for_cells<false>(
-        m.d,
-        [&](const SegCell& q) {
-          typename S::ct f[L::Q];
-          load_pulled<L, S>(src, m.geo, q.x, q.m, q.z, f);
-          double r = 0.0;
-#pragma unroll
-          for (int i = 0; i < L::Q; i++) r += (double)f[i];
-          m.par[q.c] = r < m.rho_th ? (int)q.c : -1;
-        },
-        bid, nbk);
-  } else {
-    FOR_SHARE(c, m.d.N) {
-      const double r = ((const double*)m.src)[c];  // GAS_FIELD: an FP64 field
-      m.par[c] = r < m.rho_th ? (int)c : -1;
-    }
-  }
-}
-
-// ---- connected components in two phases ----
-// Phase 1 (k_cc_local): a workgroup labels the gas components of one tile of
-// CC_TX x CC_TM x CC_TZ cells with a union-find in LDS over the links that
-// stay inside the tile, then points every gas cell at its tile-local root
-// (the local order is the global order, so that root is the component's
-// smallest cell index within the tile).  Phase 2 (k_cc_cross): the links that
-// leave a tile (including the periodic wrap) unite the local roots in the
-// global union-find; a wavefront first merges duplicate root pairs, which are
-// the common case, so few global atomics remain.
-constexpr int CC_NT = 256;
-constexpr int CC_CELLS = 2048;
+// ---- gas cells and connected components in two phases ----
+// Phase 1 (k_cc_local): a workgroup decides which cells of its tile of
+// TX x TM x TZ cells are gas (rho < rho_th, from the source the refresh
+// reads), labels the gas components of the tile with a union-find in LDS over
+// the links that stay inside the tile, and writes every cell's parent: -1
+// for liquid, the tile-local root for gas (the local order is the global
+// order, so that root is the component's smallest cell index within the
+// tile).  Phase 2 (k_cc_cross): the links that leave a tile (including the
+// periodic wrap) unite the local roots in the global union-find; a wavefront
+// first merges duplicate root pairs, which are the common case, so few global
+// atomics remain.  Large tiles keep the share of cells on tile faces, and so
+// the global unions, small.
+#ifndef FLB_CC_TM3
+#define FLB_CC_TM3 8
+#endif
+#ifndef FLB_CC_TZ3
+#define FLB_CC_TZ3 16
+#endif
+#ifndef FLB_CC_TZ2
+#define FLB_CC_TZ2 64
+#endif
 template <class L>
 struct CCTile {
   static constexpr int TX = 64;
-  static constexpr int TM = L::HAS_M ? 8 : 1;
-  static constexpr int TZ = CC_CELLS / (TX * TM);
+  static constexpr int TM = L::HAS_M ? FLB_CC_TM3 : 1;
+  static constexpr int TZ = L::HAS_M ? FLB_CC_TZ3 : FLB_CC_TZ2;
+  static constexpr int CELLS = TX * TM * TZ;
+  static constexpr int NT = CELLS / 16 > 1024 ? 1024 : (CELLS / 16 < 64 ? 64 : CELLS / 16);
+  static constexpr int PER = CELLS / NT;
+  static_assert(CELLS % NT == 0 && NT % 64 == 0 && PER <= 32, "CC tile shape");
 };
 
 __host__ inline int cc_tiles(const MapDims& d, int tm, int tz) {
@@ -252,56 +263,89 @@ __device__ __forceinline__ void lds_unite(int* lp, int a, int b) {
   }
 }
 
-template <class L>
-__global__ __launch_bounds__(CC_NT) void k_cc_local(MAP_KERNEL_PARAMS) {
+// Gas sources of a refresh or a labels query (SRC):
+//  GAS_POP   the density of the stored state, from its populations summed in
+//            FP64;
+//  GAS_AUTO  the densities the previous step stored for this refresh (the
+//            rho array, cell-linear) when it holds the step before this one,
+//            else as GAS_POP;
+//  GAS_FIELD a cell-linear FP64 density field given by the caller.
+template <class L, class S, int SRC>
+__global__ __launch_bounds__(CCTile<L>::NT) void k_cc_local(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m)) return;
   using TT = CCTile<L>;
-  __shared__ int lp[CC_CELLS];
+  constexpr int NT = TT::NT, PER = TT::PER;
+  __shared__ int lp[TT::CELLS];
   const MapDims d = m.d;
   const int ntx = (d.nx + 63) / 64, ntm = (d.nm + TT::TM - 1) / TT::TM;
   const int b = (int)bid;
   const int tx = b % ntx, tm = (b / ntx) % ntm, tz = b / (ntx * ntm);
   const int x0 = tx * 64, m0 = tm * TT::TM, z0 = tz * TT::TZ;
-  constexpr int PER = CC_CELLS / CC_NT;
-  auto gcell = [&](int l, int& x, int& mm_, int& z) -> bool {
-    x = x0 + (l & 63);
-    mm_ = m0 + (l >> 6) % TT::TM;
-    z = z0 + (l >> 6) / TT::TM;
-    return x < d.nx && mm_ < d.nm && z < d.nz;
-  };
-  // a wavefront's k-th row is one tile row (lanes = x): the gas runs along x
-  // are components already, so every gas cell starts at its run's first cell
   const int lane = threadIdx.x & 63;
-  bool gas[PER];
-#pragma unroll
+  const int x = x0 + lane;
+  // row of the tile (wave-uniform) handled by this thread's k-th cell
+  auto rowk = [&](int k, int& mm_, int& z) -> bool {
+    const int r = (int)(threadIdx.x >> 6) + k * (NT / 64);
+    mm_ = m0 + r % TT::TM;
+    z = z0 + r / TT::TM;
+    return mm_ < d.nm && z < d.nz;
+  };
+  const bool xin = x < d.nx;
+  const bool from_rho = SRC == GAS_AUTO && m.sctl->steps > 0 && m.sctl->rho_step == m.sctl->steps - 1;
+  const void* pops = (m.sctl->steps & 1) ? m.b1 : m.b0;
+  unsigned gas = 0;  // bit k: the k-th cell is gas
+#pragma unroll 2
   for (int k = 0; k < PER; k++) {
-    const int l = threadIdx.x + k * CC_NT;
-    int x, mm_, z;
-    gas[k] = false;
-    if (gcell(l, x, mm_, z)) gas[k] = m.par[x + (unsigned)d.nx * (mm_ + (unsigned)d.nm * z)] >= 0;
+    int mm_, z;
+    if (!rowk(k, mm_, z) || !xin) continue;
+    const unsigned c = (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z);
+    double r;
+    if constexpr (SRC == GAS_FIELD) {
+      r = ((const double*)m.src)[c];
+    } else {
+      if (from_rho) {
+        r = (double)((const typename S::ct*)m.src)[c];
+      } else {
+        typename S::ct f[L::Q];
+        load_pulled<L, S>(pops, m.geo, x, mm_, z, f);
+        r = 0.0;
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) r += (double)f[i];
+      }
+    }
+    if (r < m.rho_th) gas |= 1u << k;
   }
+  // a wavefront's k-th row is one tile row (lanes = x): the gas runs along x
+  // are components already, so every gas cell starts at its run's first cell.
+  // On a film refresh the row's gas word is also the BFS frontier of layer 0.
+  const int nxs = (d.nx + 63) >> 6;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    const int l = threadIdx.x + k * CC_NT;
-    const unsigned long long g = __ballot(gas[k]);
-    const unsigned long long starts = g & ~(g << 1);
+    const int l = threadIdx.x + k * NT;
+    const bool g = (gas >> k) & 1u;
+    const unsigned long long bg = __ballot(g);
+    int mm_, z;
+    if (m.refresh && lane == 0 && rowk(k, mm_, z))
+      m.bfw[(unsigned)tx + (unsigned)nxs * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z)] = bg;
+    const unsigned long long starts = bg & ~(bg << 1);
     const unsigned long long upto = starts & ((2ull << lane) - 1ull);  // lane 63: all bits
-    lp[l] = gas[k] ? (l & ~63) + (63 - __clzll((long long)upto)) : -1;
+    lp[l] = g ? (l & ~63) + (63 - __clzll((long long)upto)) : -1;
   }
   __syncthreads();
   // links leaving the row: one union per run of equal (run, run) pairs, the
   // runs' unions concurrently
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    const int l = threadIdx.x + k * CC_NT;
+    const int l = threadIdx.x + k * NT;
     const int lx = l & 63, lm = (l >> 6) % TT::TM, lz = (l >> 6) / TT::TM;
+    const bool g = (gas >> k) & 1u;
 #pragma unroll
     for (int i = 1; i < L::Q; i += 2) {  // one direction of each opposite pair
       if (L::em[i] == 0 && L::ez[i] == 0) continue;  // along x: inside the runs
       const int nx_ = lx + L::ex[i], nm_ = lm + L::em[i], nz_ = lz + L::ez[i];
       int a = -1, bn = -1;
-      if (gas[k] && nx_ >= 0 && nx_ < 64 && nm_ >= 0 && nm_ < TT::TM && nz_ >= 0 && nz_ < TT::TZ &&
+      if (g && nx_ >= 0 && nx_ < 64 && nm_ >= 0 && nm_ < TT::TM && nz_ >= 0 && nz_ < TT::TZ &&
           x0 + nx_ < d.nx && m0 + nm_ < d.nm && z0 + nz_ < d.nz) {
         bn = lp[nx_ + 64 * (nm_ + TT::TM * nz_)];
         if (bn >= 0) a = lp[l];
@@ -311,15 +355,20 @@ __global__ __launch_bounds__(CC_NT) void k_cc_local(MAP_KERNEL_PARAMS) {
     }
   }
   __syncthreads();
+  // every cell's parent: its tile-local root, or -1
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    const int l = threadIdx.x + k * CC_NT;
-    if (lp[l] < 0) continue;
-    const int r = lds_find(lp, l);
-    int x, mm_, z, rx, rm, rz;
-    gcell(l, x, mm_, z);
-    gcell(r, rx, rm, rz);
-    m.par[x + (unsigned)d.nx * (mm_ + (unsigned)d.nm * z)] = (int)(rx + (unsigned)d.nx * (rm + (unsigned)d.nm * rz));
+    const int l = threadIdx.x + k * NT;
+    int mm_, z;
+    if (!rowk(k, mm_, z) || !xin) continue;
+    const unsigned c = (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z);
+    int v = -1;
+    if ((gas >> k) & 1u) {
+      const int r = lds_find(lp, l);
+      const int rx = x0 + (r & 63), rm = m0 + (r >> 6) % TT::TM, rz = z0 + (r >> 6) / TT::TM;
+      v = (int)((unsigned)rx + (unsigned)d.nx * ((unsigned)rm + (unsigned)d.nm * (unsigned)rz));
+    }
+    m.par[c] = v;
   }
 }
 
@@ -330,6 +379,7 @@ __global__ __launch_bounds__(MAP_NT) void k_cc_cross(MAP_KERNEL_PARAMS) {
   using TT = CCTile<L>;
   const MapDims d = m.d;
   int* par = m.par;
+  FLB_AS_GLOBAL int* gpar = as_global(m.par);
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nxs = (d.nx + 63) >> 6;
@@ -341,7 +391,7 @@ __global__ __launch_bounds__(MAP_NT) void k_cc_cross(MAP_KERNEL_PARAMS) {
     const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
     const bool in = x < d.nx;
     const unsigned c = (unsigned)min(x, d.nx - 1) + (unsigned)d.nx * row;
-    const int pc = in ? par[c] : -1;
+    const int pc = in ? gpar[c] : -1;
     if (!__ballot(pc >= 0)) continue;  // no gas in this segment
     // the neighbours across tile edges, all loaded before any union
     constexpr int NP = (L::Q - 1) / 2;
@@ -356,7 +406,7 @@ __global__ __launch_bounds__(MAP_NT) void k_cc_cross(MAP_KERNEL_PARAMS) {
       if (pc >= 0 && !local) {
         const unsigned y = (unsigned)wrap_any(xu, d.nx) +
                            (unsigned)d.nx * ((unsigned)wrap_any(mu, d.nm) + (unsigned)d.nm * wrap_any(zu, d.nz));
-        py[p] = __atomic_load_n(&par[y], __ATOMIC_RELAXED);
+        py[p] = __atomic_load_n(&gpar[y], __ATOMIC_RELAXED);
       }
     }
     // one union per run of equal root pairs, the runs' unions concurrently
@@ -454,12 +504,22 @@ static __global__ __launch_bounds__(RANK_BLOCK) void k_write_rank(MAP_KERNEL_PAR
   }
 }
 
+// Labels; on a film refresh also the start of the owner BFS: gas cells are
+// their own owners at distance 0, every other cell is unreached (dist 255;
+// its owner pair is left as it was and is never read: every reader of the
+// owners reads them at cells with a distance).
 static __global__ __launch_bounds__(MAP_NT) void k_write_labels(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m)) return;
+  const bool film = m.refresh;
   FOR_SHARE(c, m.d.N) {
     const int p = m.par[c];
-    m.label[c] = p < 0 ? 0 : m.rank[p];
+    const int l = p < 0 ? 0 : m.rank[p];
+    m.label[c] = l;
+    if (film) {
+      m.dist[c] = l > 0 ? 0 : 255;
+      if (l > 0) m.own[c] = make_int2(l, l);
+    }
   }
 }
 
@@ -476,19 +536,6 @@ static __global__ __launch_bounds__(MAP_NT) void k_keep_old(MAP_KERNEL_PARAMS) {
   }
 }
 
-// ---- owner / dist ----
-// Gas cells are their own owners at distance 0; every other cell starts
-// unreached (dist 255).
-static __global__ __launch_bounds__(MAP_NT) void k_owner_init(MAP_KERNEL_PARAMS) {
-  MAP_MEMBER
-  if (!map_due(m)) return;
-  FOR_SHARE(c, m.d.N) {
-    const int l = m.label[c];
-    m.own[c] = make_int2(l, l);
-    m.dist[c] = l > 0 ? 0 : 255;
-  }
-}
-
 // Layers a barrier can depend on.  A barrier link joins two owned cells with
 // dist(x) + dist(y) + 1 <= zone_width, and BFS distances of neighbours differ
 // by at most one, so both ends lie within zone_width / 2 hops of a bubble.
@@ -496,13 +543,6 @@ static __global__ __launch_bounds__(MAP_NT) void k_owner_init(MAP_KERNEL_PARAMS)
 // fill in the exported maps when they are read.
 __host__ __device__ constexpr int bfs_hot_layers(int zone_width) { return zone_width / 2; }
 
-// One BFS layer over tiles of 64 x TM x TZ cells: the workgroup stages the
-// distances of its tile and a one-cell halo in LDS (a tile whose cells are
-// all reached stops after reading its own), then every unreached cell with a
-// neighbour at distance layer - 1 is reached now and takes the smallest owner
-// and the largest owner2 over those neighbours.  Cells reached in this layer
-// get dist = layer, which no cell of this layer compares with, so the update
-// in place is free of races.
 __device__ __forceinline__ int wrap_mod(int a, int n) {
   if (a >= 0 && a < n) return a;
   const int r = a % n;
@@ -554,106 +594,182 @@ struct AxisStep {
   __device__ __forceinline__ int of(int e) const { return e < 0 ? dn : (e > 0 ? up : 0); }
 };
 
+// ---- owner / dist by layers over frontier bitsets ----
+// The frontier of layer L (the cells at distance L) is a bitset in row
+// words: bit l of word xs + nxs * row is cell 64 xs + l of that row.  Layer 0
+// is the gas (written by k_cc_local).  A workgroup takes a block of CW words
+// along x by TM x TZ rows and
+//  1. stages the frontier words of layer L - 1 of the block and a one-word,
+//     one-row halo in LDS, and forms, one thread per word, the word of cells
+//     reached in layer L:
+//       new = (union over directions e of F_{L-1} shifted by e) & ~F_{L-1} & ~F_{L-2}
+//     (a neighbour of a cell at distance L - 1 is at distance L - 2, L - 1 or
+//     L), together with, for each new cell, the directions that lead to the
+//     frontier;
+//  2. lists the new cells of the block in LDS (a block-wide scan of the word
+//     counts gives each word its place);
+//  3. spreads the list over all threads, which gather the owners of each
+//     listed cell's frontier neighbours (all loads of a cell in flight
+//     together) and keep the smallest owner and the largest owner2.
+// The bit arithmetic touches no memory beyond the staged words, and the
+// gathers cover only the new cells.
+#ifndef FLB_BFS_U
+#define FLB_BFS_U 1
+#endif
 template <class L>
-__global__ __launch_bounds__(BFS_NT) void k_bfs_layer(MAP_KERNEL_PARAMS, int layer, int deferred) {
+struct BfsBlock {
+  static constexpr int CW = 4;                    // words along x
+  static constexpr int TM = L::HAS_M ? 8 : 1;     // rows along m
+  static constexpr int TZ = L::HAS_M ? 8 : 64;    // rows along z
+  static constexpr int HM = L::HAS_M ? 1 : 0;
+  static constexpr int LW = CW + 2, LM = TM + 2 * HM, LZ = TZ + 2;
+  static constexpr int NT = CW * TM * TZ;         // one thread per word
+  static constexpr int LIST = 2048;               // listed cells per round
+  static_assert(NT == 256, "one word per thread");
+};
+
+__host__ inline int bfs_blocks(const MapDims& d, int cw, int tm, int tz) {
+  return ((d.nx + 64 * cw - 1) / (64 * cw)) * ((d.nm + tm - 1) / tm) * ((d.nz + tz - 1) / tz);
+}
+
+template <class L>
+__global__ __launch_bounds__(256) void k_bfs_blk(MAP_KERNEL_PARAMS, int layer, int deferred) {
   MAP_MEMBER
   if (layer > m.zone_width - 1) return;
   if (deferred ? (!m.ctl->maps_partial || layer <= bfs_hot_layers(m.zone_width))
                : (!map_due(m) || layer > bfs_hot_layers(m.zone_width)))
     return;
-  using T = BfsTile<L>;
-  using H = HaloRows<T>;
-  constexpr int PER = T::CELLS / BFS_NT;
-  __shared__ unsigned long long fm[H::NR];
-  __shared__ unsigned long long om[H::NR];
-  __shared__ unsigned fe[H::NR];
+  using T = BfsBlock<L>;
+  __shared__ unsigned long long fw[T::LW * T::LM * T::LZ];
+  __shared__ uint2 list[T::LIST];
+  __shared__ int wsum[T::NT / 64];
   const MapDims d = m.d;
-  const int ntx = (d.nx + 63) / 64, ntm = (d.nm + T::TM - 1) / T::TM;
+  const int nxs = (d.nx + 63) >> 6;
+  const unsigned nrows = (unsigned)d.nm * (unsigned)d.nz;
+  const size_t nw = (size_t)nxs * nrows;
+  const FLB_AS_GLOBAL unsigned long long* Fp = as_global((const unsigned long long*)m.bfw + (size_t)((layer - 1) % 3) * nw);
+  const FLB_AS_GLOBAL unsigned long long* Fq = as_global((const unsigned long long*)m.bfw + (size_t)((layer + 1) % 3) * nw);
+  FLB_AS_GLOBAL unsigned long long* Fn = as_global(m.bfw + (size_t)(layer % 3) * nw);
+  const int nbx = (nxs + T::CW - 1) / T::CW, nbm = (d.nm + T::TM - 1) / T::TM;
   const int b = (int)bid;
-  const int x0 = (b % ntx) * 64, m0 = ((b / ntx) % ntm) * T::TM, z0 = (b / (ntx * ntm)) * T::TZ;
-  const int lx = threadIdx.x & 63;
-  const int x = x0 + lx;
-  const H hr(d, x0);
-  const uint8_t prev = (uint8_t)(layer - 1);
-  uint8_t va[H::RPW], ve[H::RPW];
-#pragma unroll
-  for (int j = 0; j < H::RPW; j++) {
-    va[j] = ve[j] = 0;
-    if (hr.row(j) < H::NR) {
-      const unsigned base = hr.base(d, m0, z0, hr.row(j));
-      va[j] = m.dist[base + (unsigned)hr.xa];
-      if (hr.lane < 2) ve[j] = m.dist[base + (unsigned)hr.xe];
-    }
+  const int xs0 = (b % nbx) * T::CW, m0 = ((b / nbx) % nbm) * T::TM, z0 = (b / (nbx * nbm)) * T::TZ;
+  // 1. stage the frontier words of the block and its halo (wrapped)
+  for (int i = threadIdx.x; i < T::LW * T::LM * T::LZ; i += T::NT) {
+    const int wx = i % T::LW, r = i / T::LW;
+    const int gx = wrap_mod(xs0 - 1 + wx, nxs);
+    const int gm = T::HM ? wrap_mod(m0 - 1 + r % T::LM, d.nm) : 0;
+    const int gz = wrap_mod(z0 - 1 + r / T::LM, d.nz);
+    fw[i] = Fp[(unsigned)gx + (unsigned)nxs * ((unsigned)gm + (unsigned)d.nm * (unsigned)gz)];
   }
-  // frontier bits of the halo rows: bit l of fm[row] is the cell x0 + l,
-  // bits 0 and 1 of fe[row] the cells x0 - 1 and x0 + 64; bit l of om[row]:
-  // cell x0 + l is not reached yet (the tile's own rows are halo rows too,
-  // so one round of loads serves both)
-#pragma unroll
-  for (int j = 0; j < H::RPW; j++) {
-    if (hr.row(j) >= H::NR) continue;  // wave-uniform
-    const unsigned long long bm = __ballot(va[j] == prev);
-    const unsigned long long be = __ballot(hr.lane < 2 && ve[j] == prev);
-    const unsigned long long bo = __ballot(va[j] == 255);
-    if (hr.lane == 0) {
-      fm[hr.row(j)] = bm;
-      fe[hr.row(j)] = (unsigned)be;
-      om[hr.row(j)] = bo;
-    }
-  }
+  const int wx = threadIdx.x % T::CW, tr = threadIdx.x / T::CW;
+  const int lm = tr % T::TM, lz = tr / T::TM;
+  const int xs = xs0 + wx, mm_ = m0 + lm, z = z0 + lz;
+  const bool own_word = xs < nxs && mm_ < d.nm && z < d.nz;
+  const unsigned wi = own_word ? (unsigned)xs + (unsigned)nxs * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z) : 0u;
+  const unsigned long long prev = (own_word && layer >= 2) ? Fq[wi] : 0ull;
   __syncthreads();
-  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  unsigned cidx[PER];
-  bool open[PER];
-  bool any = false;
+  unsigned long long S[L::Q];
+  unsigned long long nwd = 0;
+  if (own_word) {
+    const int x0 = xs * 64;
+    const int nval = min(64, d.nx - x0);
+    const unsigned long long valid = nval == 64 ? ~0ull : (1ull << nval) - 1ull;
+    unsigned long long reach = 0;
 #pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int r = wv + k * (BFS_NT / 64);
-    const int mm_ = m0 + r % T::TM, z = z0 + r / T::TM;
-    const bool in = x < d.nx && mm_ < d.nm && z < d.nz;
-    cidx[k] = in ? (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z) : 0u;
-    const int row = (r % T::TM + T::HM) + T::LM * (r / T::TM + 1);
-    open[k] = in && ((om[row] >> lx) & 1ull);
-    any |= open[k];
+    for (int i = 1; i < L::Q; i++) {
+      const int at = (wx + 1) + T::LW * ((lm + T::HM + L::em[i]) + T::LM * (lz + 1 + L::ez[i]));
+      const unsigned long long w = fw[at];
+      unsigned long long sh;
+      if (L::ex[i] == 0) {
+        sh = w;
+      } else if (L::ex[i] > 0) {  // the cell right of the word: bit 0 of the next word, or cell 0 of the row
+        const unsigned long long cr = fw[at + 1] & 1ull;
+        sh = (w >> 1) | (cr << (nval - 1));
+      } else {  // the cell left of the word: bit 63 of the previous word, or the row's last cell
+        const unsigned long long cl = (fw[at - 1] >> (xs == 0 ? ((d.nx - 1) & 63) : 63)) & 1ull;
+        sh = ((w << 1) | cl) & valid;
+      }
+      S[i] = sh;
+      reach |= sh;
+    }
+    const unsigned long long self = fw[(wx + 1) + T::LW * ((lm + T::HM) + T::LM * (lz + 1))];
+    nwd = reach & ~self & ~prev & valid;
+    Fn[wi] = nwd;
   }
-  if (!__syncthreads_or(any)) return;  // block-uniform
-  const AxisStep sx(x < d.nx ? x : 0, d.nx, 1);
+  // 2. places of the new cells: block-wide exclusive scan of the word counts
+  const int cnt = __popcll(nwd);
+  int incl = cnt;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int r = wv + k * (BFS_NT / 64);
-    const int lm = r % T::TM, lz = r / T::TM;
-    // the frontier words of the 18 neighbour directions, wave-uniform:
-    // bit l of s[i] is the cell reached from lane l's cell along e_i
-    unsigned long long s[L::Q], reach = 0;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  int base = incl - cnt, total = 0;
 #pragma unroll
-    for (int i = 1; i < L::Q; i++) {
-      const int row = (lm + T::HM + L::em[i]) + T::LM * (lz + 1 + L::ez[i]);
-      const unsigned long long w = fm[row];
-      const unsigned e = fe[row];
-      s[i] = L::ex[i] == 0 ? w
-           : L::ex[i] > 0 ? (w >> 1) | ((unsigned long long)((e >> 1) & 1u) << 63)
-                          : (w << 1) | (unsigned long long)(e & 1u);
-      reach |= s[i];
+  for (int k = 0; k < T::NT / 64; k++) {
+    if (k < wv) base += wsum[k];
+    total += wsum[k];
+  }
+  const unsigned c_row = own_word ? (unsigned)(xs * 64) + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z) : 0u;
+  for (int r0 = 0; r0 < total; r0 += T::LIST) {  // block-uniform rounds
+    // 2. this round's part of the list: (cell, frontier directions)
+    if (cnt && base < r0 + T::LIST && base + cnt > r0) {
+      unsigned long long bits = nwd;
+      int rank = base;
+      while (bits) {
+        const int l = __builtin_ctzll(bits);
+        bits &= bits - 1ull;
+        if (rank >= r0 && rank < r0 + T::LIST) {
+          unsigned hit = 0;
+#pragma unroll
+          for (int i = 1; i < L::Q; i++) hit |= (unsigned)((S[i] >> l) & 1ull) << i;
+          list[rank - r0] = make_uint2(c_row + (unsigned)l, hit);
+        }
+        rank++;
+      }
     }
-    if (!open[k] || !((reach >> lx) & 1ull)) continue;
-    unsigned hit = 0;
+    __syncthreads();
+    // 3. owners of the listed cells, U cells per thread at a time
+    const int n = min(T::LIST, total - r0);
+    constexpr int U = FLB_BFS_U;
+    for (int e = threadIdx.x; e < n; e += U * T::NT) {
+      int2 o[U][L::Q];
+      unsigned cc[U];
+      bool act[U];
 #pragma unroll
-    for (int i = 1; i < L::Q; i++) hit |= (unsigned)((s[i] >> lx) & 1ull) << i;
-    const AxisStep sm(m0 + lm, d.nm, d.nx), sz(z0 + lz, d.nz, d.nx * d.nm);
-    int2 o[L::Q];
+      for (int u = 0; u < U; u++) {
+        const int ee = e + u * T::NT;
+        act[u] = ee < n;
+        const uint2 ent = act[u] ? list[ee] : make_uint2(0u, 0u);
+        cc[u] = ent.x;
+        const unsigned r = ent.x / (unsigned)d.nx;
+        const int x = (int)(ent.x - r * (unsigned)d.nx);
+        const AxisStep sx(x, d.nx, 1), sm((int)(r % (unsigned)d.nm), d.nm, d.nx),
+            sz((int)(r / (unsigned)d.nm), d.nz, d.nx * d.nm);
 #pragma unroll
-    for (int i = 1; i < L::Q; i++) {  // the owners of all frontier neighbours in flight at once
-      o[i] = make_int2(0x7fffffff, 0);
-      if (hit & (1u << i)) o[i] = m.own[(int)cidx[k] + sx.of(L::ex[i]) + sm.of(L::em[i]) + sz.of(L::ez[i])];
+        for (int i = 1; i < L::Q; i++) {
+          o[u][i] = make_int2(0x7fffffff, 0);
+          if (ent.y & (1u << i))
+            o[u][i] = ld_pair(m.own, (unsigned)((int)ent.x + sx.of(L::ex[i]) + sm.of(L::em[i]) + sz.of(L::ez[i])));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        if (!act[u]) continue;
+        int lo = 0x7fffffff, hi = 0;
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) {
+          lo = min(lo, o[u][i].x);
+          hi = max(hi, o[u][i].y);
+        }
+        st_pair(m.own, cc[u], make_int2(lo, hi));
+        as_global(m.dist)[cc[u]] = (uint8_t)layer;
+      }
     }
-    int lo = 0x7fffffff, hi = 0;
-#pragma unroll
-    for (int i = 1; i < L::Q; i++) {
-      lo = min(lo, o[i].x);
-      hi = max(hi, o[i].y);
-    }
-    m.own[cidx[k]] = make_int2(lo, hi);
-    m.dist[cidx[k]] = (uint8_t)layer;
+    __syncthreads();
   }
 }
 
@@ -737,6 +853,7 @@ __global__ __launch_bounds__(BFS_NT) void k_masks(MAP_KERNEL_PARAMS) {
   __shared__ int2 lo[T::HALO];
   const MapDims d = m.d;
   const int zone_width = m.zone_width;
+  const FLB_AS_GLOBAL uint8_t* dist = as_global((const uint8_t*)m.dist);
   const int ntx = (d.nx + 63) / 64, ntm = (d.nm + T::TM - 1) / T::TM;
   const int b = (int)bid;
   const int x0 = (b % ntx) * 64, m0 = ((b / ntx) % ntm) * T::TM, z0 = (b / (ntx * ntm)) * T::TZ;
@@ -744,7 +861,6 @@ __global__ __launch_bounds__(BFS_NT) void k_masks(MAP_KERNEL_PARAMS) {
   const int x = x0 + lane;
   unsigned cidx[PER];
   bool in[PER], rowin[PER];
-  bool any = false;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int r = (int)(threadIdx.x >> 6) + k * (BFS_NT / 64);
@@ -752,30 +868,34 @@ __global__ __launch_bounds__(BFS_NT) void k_masks(MAP_KERNEL_PARAMS) {
     rowin[k] = mm_ < d.nm && z < d.nz;
     in[k] = rowin[k] && x < d.nx;
     cidx[k] = in[k] ? (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z) : 0u;
-    any |= in[k] && m.dist[cidx[k]] != 255;
+  }
+  // distances of the tile and its halo; a tile whose halo holds no owned
+  // cell has no barrier links and stages nothing more
+  const H hr(d, x0);
+  unsigned ga[H::RPW], ge[H::RPW];
+  uint8_t da[H::RPW], de[H::RPW];
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < H::RPW; j++) {
+    da[j] = de[j] = 255;
+    ga[j] = ge[j] = 0;
+    if (hr.row(j) < H::NR) {
+      const unsigned base = hr.base(d, m0, z0, hr.row(j));
+      ga[j] = base + (unsigned)hr.xa;
+      ge[j] = base + (unsigned)hr.xe;
+      da[j] = dist[ga[j]];
+      if (hr.lane < 2) de[j] = dist[ge[j]];
+    }
+    any |= da[j] != 255 || de[j] != 255;
   }
   const bool owned = __syncthreads_or(any);  // block-uniform
   if (owned) {
-    const H hr(d, x0);
-    unsigned ga[H::RPW], ge[H::RPW];
-    uint8_t da[H::RPW], de[H::RPW];
-#pragma unroll
-    for (int j = 0; j < H::RPW; j++) {  // distances, then the owners of owned cells
-      da[j] = de[j] = 255;
-      ga[j] = ge[j] = 0;
-      if (hr.row(j) < H::NR) {
-        const unsigned base = hr.base(d, m0, z0, hr.row(j));
-        ga[j] = base + (unsigned)hr.xa;
-        ge[j] = base + (unsigned)hr.xe;
-        da[j] = m.dist[ga[j]];
-        if (hr.lane < 2) de[j] = m.dist[ge[j]];
-      }
-    }
     int2 oa[H::RPW], oe[H::RPW];
 #pragma unroll
-    for (int j = 0; j < H::RPW; j++) {
-      oa[j] = da[j] != 255 ? m.own[ga[j]] : make_int2(0, 0);
-      oe[j] = de[j] != 255 ? m.own[ge[j]] : make_int2(0, 0);
+    for (int j = 0; j < H::RPW; j++) {  // the owners of owned cells
+      oa[j] = oe[j] = make_int2(0, 0);
+      if (da[j] != 255) oa[j] = ld_pair(m.own, ga[j]);
+      if (de[j] != 255) oe[j] = ld_pair(m.own, ge[j]);
     }
 #pragma unroll
     for (int j = 0; j < H::RPW; j++) {
@@ -792,7 +912,7 @@ __global__ __launch_bounds__(BFS_NT) void k_masks(MAP_KERNEL_PARAMS) {
     __syncthreads();
   }
   const int nxs = (d.nx + 63) >> 6;
-  const int* __restrict__ alias = m.alias;
+  const FLB_AS_GLOBAL int* alias = as_global((const int*)m.alias);
   auto root_pair = [&](int2 o) {
     const int ra = alias[o.x], rb = alias[o.y];
     return make_int2(min(ra, rb), max(ra, rb));
@@ -829,13 +949,13 @@ __global__ __launch_bounds__(BFS_NT) void k_masks(MAP_KERNEL_PARAMS) {
       }
     }
     if (in[k]) {
-      m.flag[cidx[k]] = mk ? 1 : 0;
-      m.mask[cidx[k]] = mk;
+      as_global(m.flag)[cidx[k]] = mk ? 1 : 0;
+      as_global(m.mask)[cidx[k]] = mk;
     }
     const unsigned long long bal = __ballot(mk != 0);
     if (rowin[k] && lane == 0) {
       const unsigned row = (unsigned)(m0 + lm) + (unsigned)d.nm * (unsigned)(z0 + lz);
-      m.fwords[(unsigned)(x0 >> 6) + (unsigned)nxs * row] = bal;
+      as_global(m.fwords)[(unsigned)(x0 >> 6) + (unsigned)nxs * row] = bal;
     }
   }
 }
@@ -980,8 +1100,12 @@ __host__ inline int map_share(int shape, const MapDims& d) {
     case SH_BFST: g = cc_tiles(d, BfsTile<L>::TM, BfsTile<L>::TZ); break;
     case SH_RANK: g = (N + RANK_BLOCK - 1) / RANK_BLOCK; break;
     case SH_ONE: g = 1; break;
+    // passes over per-bubble tables (as long as the bubble count, which only
+    // the device knows): a few workgroups, grid-stride
+    case SH_FEW: g = std::min<long long>((N + 1 + MAP_NT - 1) / MAP_NT, 32); break;
     case SH_LIST: g = list_grid(N); break;
     case SH_FW: g = (nseg + FW_BLOCK - 1) / FW_BLOCK; break;
+    case SH_BFSB: g = bfs_blocks(d, BfsBlock<L>::CW, BfsBlock<L>::TM, BfsBlock<L>::TZ); break;
   }
   return (int)std::max<long long>(g, 1);
 }

@@ -129,7 +129,7 @@ inline size_t ctx_footprint(const flb_params* p) {
   const size_t nwords = nxb * nm * nz;
   if (p->film_on)
     t += 2 * r(N) + r(4 * N) + r(8 * N) + 2 * r(4 * N) + 3 * r(4 * (N + 1)) + r(32 * 65536) +
-         r(4 * N) + r(8 * nwords);
+         r(4 * N) + r(8 * nwords) + r(3 * 8 * nwords);
   if (p->growth_on) t += r(8 * nwords);
   return t;
 }
@@ -213,6 +213,7 @@ struct flb_ctx {
   int* rank = nullptr;
   int* counts = nullptr;
   unsigned long long* bits = nullptr;  // flag words: one bit per cell, set where the cell has barrier links
+  unsigned long long* bfw = nullptr;   // BFS frontier words (three bitsets)
   long long nwords = 0;                // 64-bit words per bitset
   unsigned long long* srcw = nullptr;  // gas-release source: bits of the domain gas points (growth_on);
                                        // their number is ctl->n_src
@@ -431,6 +432,7 @@ inline MapArgs map_args(flb_ctx* c, bool query, int src) {
     a.mask = c->mask;
     a.flist = c->flist;
     a.fwords = c->bits;
+    a.bfw = c->bfw;
   }
   return a;
 }
@@ -458,10 +460,10 @@ int map_masks(const MapSet& s, hipStream_t st) {
 template <class L, class S>
 int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh, const Fork* fk = nullptr) {
   if (refresh) MAPL(k_keep_old, SH_CELLS, MAP_NT);
-  if (src == GAS_POP) MAPL((k_gas<L, S, GAS_POP>), SH_SEG, MAP_NT);
-  else if (src == GAS_AUTO) MAPL((k_gas<L, S, GAS_AUTO>), SH_SEG, MAP_NT);  // either path: segments
-  else MAPL((k_gas<L, S, GAS_FIELD>), SH_CELLS, MAP_NT);
-  MAPL((k_cc_local<L>), SH_CCT, CC_NT);
+  constexpr int CNT = CCTile<L>::NT;
+  if (src == GAS_POP) MAPL((k_cc_local<L, S, GAS_POP>), SH_CCT, CNT);
+  else if (src == GAS_AUTO) MAPL((k_cc_local<L, S, GAS_AUTO>), SH_CCT, CNT);
+  else MAPL((k_cc_local<L, S, GAS_FIELD>), SH_CCT, CNT);
   MAPL((k_cc_cross<L>), SH_SEG, MAP_NT);
   MAPL(k_cc_compress, SH_RANK, RANK_BLOCK);
   MAPL(k_scan_counts, SH_ONE, 1024, 0);
@@ -476,15 +478,14 @@ int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh, const F
     {
       hipStream_t st_main = st;
       hipStream_t st = fork ? fk->side : st_main;  // the alias carry, beside the BFS
-      MAPL(k_alias_reset, SH_CELLS, MAP_NT);
+      MAPL(k_alias_reset, SH_FEW, MAP_NT);
       MAPL(k_alias_carry1, SH_CELLS, MAP_NT);
       MAPL(k_alias_carry2, SH_CELLS, MAP_NT);
-      MAPL(k_alias_compress, SH_CELLS, MAP_NT);
+      MAPL(k_alias_compress, SH_FEW, MAP_NT);
       if (fork) HIPCHK(hipEventRecord(fk->b, st));
     }
-    MAPL(k_owner_init, SH_CELLS, MAP_NT);
     for (int layer = 1; layer <= std::min(s.max_zone - 1, bfs_hot_layers(s.max_zone)); layer++)
-      MAPL((k_bfs_layer<L>), SH_BFST, BFS_NT, layer, 0);
+      MAPL((k_bfs_blk<L>), SH_BFSB, 256, layer, 0);
     if (fork) HIPCHK(hipStreamWaitEvent(st, fk->b, 0));
   }
   if (refresh) return map_masks<L>(s, st);
@@ -497,7 +498,7 @@ template <class L>
 int map_deferred(const MapSet& s, hipStream_t st, bool run) {
   if (run)
     for (int layer = bfs_hot_layers(s.max_zone) + 1; layer <= s.max_zone - 1; layer++)
-      MAPL((k_bfs_layer<L>), SH_BFST, BFS_NT, layer, 1);
+      MAPL((k_bfs_blk<L>), SH_BFSB, 256, layer, 1);
   MAPL(k_maps_whole, SH_ONE, 64);
   HIPCHK(hipGetLastError());
   return FLB_OK;
