@@ -25,6 +25,13 @@
  *   7. streaming      f_i(x + e_i) = f*_i(x), periodic           (Sec. 2.1.1, streaming equation)
  *   8. rupture test   d2 p0 / dn2 >= 0 on barrier links          (Sec. 2.1.5, eta_m equation; Sec. 4)
  *
+ * With model = 1 the step is the paper's two-lattice form (Sec. 2.1.5, the
+ * two separate lattices for melt and gas, coupled at the end of every step;
+ * Fig. Mainflowchart "Domain coupling"): one population set per component,
+ * a common velocity, a Shan-Chen force on each component from both
+ * components, and the per-bubble selection taken as the nearest-bubble
+ * substitution on barrier links.  It is one_step_tl below, step by step.
+ *
  * Readings of passages the paper leaves silent or garbled are named where
  * they are used (R-numbers match the table of readings kept with the design
  * notes).  No part of this file is tuned for speed beyond an OpenMP pragma on
@@ -92,6 +99,12 @@ typedef struct {
   double gas_dndt;        /* dn/dt of the gas-release law (lattice units, per step) */
   double gx, gy, gz;      /* gravity (lattice units); all zero: no body force */
   double g_rho_ref;       /* the body force is (rho - g_rho_ref) g per cell */
+  int32_t model;          /* 0: single component; 1: two lattices, melt and gas (Sec. 2.1.5) */
+  double G_mg;            /* model 1: melt-gas coupling (G is the melt's own) */
+  double G_gg;            /* model 1: the gas's own coupling */
+  double tau_g;           /* model 1: relaxation time of the gas lattice */
+  double rho_g_bubble;    /* model 1: gas density inside the nuclei */
+  double rho_g_liquid;    /* model 1: gas density in the melt */
 } or_params;
 
 typedef struct {
@@ -128,6 +141,12 @@ typedef struct {
   /* domain gas points: the cells of the nuclei (Sec. 2.1.3), set at nucleation */
   unsigned char* src;
   long n_src;
+  /* model 1: the gas lattice (populations g[i*N + c]), its moments and force */
+  double* g;
+  double* gpost;
+  double* rho_g;
+  double* psi_g;
+  double* force_g;
 } or_sim;
 
 /* ------------------------------------------------------------------ */
@@ -213,6 +232,11 @@ or_sim* or_create(const or_params* p) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
   if (p->lattice == 0 && p->nz != 1) return NULL;
   if (!(p->tau > 0.5)) return NULL;
+  if (p->model != 0 && p->model != 1) return NULL;
+  /* the two-lattice model carries no growth source or body force */
+  if (p->model == 1 && (!(p->tau_g > 0.5) || p->growth_on || p->gx != 0.0 || p->gy != 0.0 || p->gz != 0.0 ||
+                        !(p->rho_g_bubble > 0.0) || !(p->rho_g_liquid > 0.0)))
+    return NULL;
   or_sim* s = (or_sim*)calloc(1, sizeof(or_sim));
   s->p = *p;
   if (s->p.k_own < 1) s->p.k_own = 1;
@@ -250,6 +274,17 @@ or_sim* or_create(const or_params* p) {
     return NULL;
   }
   for (long c = 0; c < N; c++) s->dist[c] = -1;
+  if (p->model == 1) {
+    s->g = (double*)calloc((size_t)s->Q * N, sizeof(double));
+    s->gpost = (double*)calloc((size_t)s->Q * N, sizeof(double));
+    s->rho_g = (double*)calloc(N, sizeof(double));
+    s->psi_g = (double*)calloc(N, sizeof(double));
+    s->force_g = (double*)calloc(3 * (size_t)N, sizeof(double));
+    if (!s->g || !s->gpost || !s->rho_g || !s->psi_g || !s->force_g) {
+      or_destroy(s);
+      return NULL;
+    }
+  }
   return s;
 }
 
@@ -258,6 +293,7 @@ void or_destroy(or_sim* s) {
   free(s->f); free(s->fpost); free(s->rho); free(s->rho_prev); free(s->psi); free(s->force);
   free(s->label); free(s->label_old); free(s->owner); free(s->owner2); free(s->dist); free(s->mask);
   free(s->alias); free(s->alias_old); free(s->src); free(s->ev);
+  free(s->g); free(s->gpost); free(s->rho_g); free(s->psi_g); free(s->force_g);
   free(s);
 }
 
@@ -326,6 +362,12 @@ int or_set_nuclei(or_sim* s, const double* nuc, int32_t n) {
     double rho = inside[c] ? p->rho_gas : p->rho_liquid;
     rho += p->noise_amp * (2.0 * or_uniform(p->seed, (uint64_t)c) - 1.0);
     for (int i = 0; i < s->Q; i++) s->f[(long)i * N + c] = s->w[i] * rho;
+    /* model 1: the gas lattice holds rho_g_bubble in the nuclei and the */
+    /* dissolved rho_g_liquid in the melt, at rest, without noise        */
+    if (p->model == 1) {
+      double rg = inside[c] ? p->rho_g_bubble : p->rho_g_liquid;
+      for (int i = 0; i < s->Q; i++) s->g[(long)i * N + c] = s->w[i] * rg;
+    }
   }
   /* the nucleus cells are the domain gas points that release gas (Sec. 2.1.3) */
   s->n_src = 0;
@@ -347,12 +389,15 @@ int or_set_nuclei(or_sim* s, const double* nuc, int32_t n) {
   return 0;
 }
 
+/* populations [i*N + c]; with model 1 the melt's, then the gas's (2 Q N) */
 void or_set_populations(or_sim* s, const double* f) {
   memcpy(s->f, f, (size_t)s->Q * s->N * sizeof(double));
+  if (s->p.model == 1) memcpy(s->g, f + (size_t)s->Q * s->N, (size_t)s->Q * s->N * sizeof(double));
   s->have_prev = 0;
 }
 void or_get_populations(const or_sim* s, double* f) {
   memcpy(f, s->f, (size_t)s->Q * s->N * sizeof(double));
+  if (s->p.model == 1) memcpy(f + (size_t)s->Q * s->N, s->g, (size_t)s->Q * s->N * sizeof(double));
 }
 
 /* ------------------------------------------------------------------ */
@@ -661,12 +706,170 @@ static void one_step(or_sim* s) {
   if (any_rupture && p->on_rupture == 1) s->stopped = 1;
 }
 
+/* ------------------------------------------------------------------ */
+/* model 1: the two-lattice step (Sec. 2.1.5, two separate lattices for */
+/* melt and gas, coupled at the end of each step; Fig. Mainflowchart    */
+/* "Domain coupling").  Readings R30-R34 of the design notes.           */
+/* ------------------------------------------------------------------ */
+
+/* moments and pseudopotential of the gas lattice (steps 1-2 for the gas) */
+static void compute_moments_gas(or_sim* s, double* jx, double* jy, double* jz) {
+  long N = s->N;
+#pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
+  for (long c = 0; c < N; c++) {
+    double r = 0, a = 0, b = 0, d = 0;
+    for (int i = 0; i < s->Q; i++) {
+      double gi = s->g[(long)i * N + c];
+      r += gi;
+      a += s->e[i][0] * gi;
+      b += s->e[i][1] * gi;
+      d += s->e[i][2] * gi;
+    }
+    s->rho_g[c] = r;
+    s->psi_g[c] = psi_of(&s->p, r);
+    if (jx) { jx[c] = a; jy[c] = b; jz[c] = d; }
+  }
+}
+
+/* Bulk pressure of the two components (R33): the multicomponent Shan-Chen */
+/* equation of state, p = (rho_m + rho_g)/3 + (G psi_m^2 + 2 G_mg psi_m    */
+/* psi_g + G_gg psi_g^2)/6; each lattice's own part is the xi of Sec. 2.1.5. */
+double or_p_tl(double rm, double rg, double G, double G_mg, double G_gg, double rho0) {
+  double a = rho0 * (1.0 - exp(-rm / rho0)), b = rho0 * (1.0 - exp(-rg / rho0));
+  return (rm + rg) / 3.0 + (G * a * a + 2.0 * G_mg * a * b + G_gg * b * b) / 6.0;
+}
+
+/* Forces on both lattices (R31, R32):                                      */
+/*   F_m(x) = -psi_m(x) sum_i w_i e_i [G psi~_m(x+e_i) + G_mg psi~_g(x+e_i)] */
+/*   F_g(x) = -psi_g(x) sum_i w_i e_i [G_mg psi~_m(x+e_i) + G_gg psi~_g(x+e_i)] */
+/* summed over opposite pairs.  On an active barrier link the neighbour's   */
+/* state is replaced in every sum by that of the bulk melt (psi_bar_mode 0: */
+/* psi(rho_liquid), psi(rho_g_liquid); mode 1: x's own): only the nearest   */
+/* bubble's gas acts at x, the per-bubble selection of Sec. 2.1.5.          */
+static void compute_force_tl(or_sim* s, int with_film) {
+  long N = s->N;
+  const or_params* p = &s->p;
+  double lm = psi_of(p, p->rho_liquid), lg = psi_of(p, p->rho_g_liquid);
+#pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
+  for (long c = 0; c < N; c++) {
+    double am[3] = {0, 0, 0}, ag[3] = {0, 0, 0};
+    for (int i = 1; i < s->Q; i++) {
+      int o = s->opp[i];
+      if (o < i) continue;
+      long yp = nbr(s, c, i, +1), ym = nbr(s, c, i, -1);
+      double pm = s->psi[yp], mm = s->psi[ym], pg = s->psi_g[yp], mg = s->psi_g[ym];
+      if (with_film) {
+        double bm = p->psi_bar_mode == 0 ? lm : s->psi[c];
+        double bg = p->psi_bar_mode == 0 ? lg : s->psi_g[c];
+        if (link_active(s, c, i)) { pm = bm; pg = bg; }
+        if (link_active(s, c, o)) { mm = bm; mg = bg; }
+      }
+      for (int k = 0; k < 3; k++) {
+        am[k] += s->w[i] * s->e[i][k] * (pm - mm);
+        ag[k] += s->w[i] * s->e[i][k] * (pg - mg);
+      }
+    }
+    for (int k = 0; k < 3; k++) {
+      s->force[3 * c + k] = -s->psi[c] * (p->G * am[k] + p->G_mg * ag[k]);
+      s->force_g[3 * c + k] = -s->psi_g[c] * (p->G_mg * am[k] + p->G_gg * ag[k]);
+    }
+  }
+}
+
+static void one_step_tl(or_sim* s) {
+  long N = s->N;
+  const or_params* p = &s->p;
+  int Q = s->Q;
+  double* jm = (double*)malloc(6 * N * sizeof(double));
+  double* jg = jm + 3 * N;
+
+  compute_moments(s, jm, jm + N, jm + 2 * N);           /* 1, 2: melt */
+  compute_moments_gas(s, jg, jg + N, jg + 2 * N);       /* 1, 2: gas */
+  /* 3: maps from the melt density, as in the single-lattice step (R34) */
+  if (p->film_on && s->step % p->k_own == 0)
+    refresh_maps(s, (p->refresh_src == 1 && s->have_prev) ? s->rho_prev : s->rho);
+  compute_force_tl(s, p->film_on);                      /* 4 */
+
+#pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
+  for (long c = 0; c < N; c++) {
+    double rm = s->rho[c], rg = s->rho_g[c];
+    /* 5: the common velocity of the coupling (R30), then each lattice's */
+    /* equilibrium velocity shifted by its own force                      */
+    double den = rm / p->tau + rg / p->tau_g;
+    double uc[3], um[3], ug[3];
+    for (int k = 0; k < 3; k++) {
+      uc[k] = (jm[k * N + c] / p->tau + jg[k * N + c] / p->tau_g) / den;
+      um[k] = uc[k] + p->tau * s->force[3 * c + k] / rm;
+      ug[k] = uc[k] + p->tau_g * s->force_g[3 * c + k] / rg;
+    }
+    double uum = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
+    double uug = ug[0] * ug[0] + ug[1] * ug[1] + ug[2] * ug[2];
+    for (int i = 0; i < Q; i++) {                       /* 6: BGK on both lattices */
+      double eum = s->e[i][0] * um[0] + s->e[i][1] * um[1] + s->e[i][2] * um[2];
+      double eug = s->e[i][0] * ug[0] + s->e[i][1] * ug[1] + s->e[i][2] * ug[2];
+      double fem = s->w[i] * rm * (1.0 + 3.0 * eum + 4.5 * eum * eum - 1.5 * uum);
+      double feg = s->w[i] * rg * (1.0 + 3.0 * eug + 4.5 * eug * eug - 1.5 * uug);
+      double fi = s->f[(long)i * N + c], gi = s->g[(long)i * N + c];
+      s->fpost[(long)i * N + c] = fi - (fi - fem) / p->tau;
+      s->gpost[(long)i * N + c] = gi - (gi - feg) / p->tau_g;
+    }
+  }
+
+  /* 8: rupture test, on the two-component pressure (R33) */
+  int any_rupture = 0;
+  if (p->film_on && s->maps_valid && s->step >= p->rupture_warmup) {
+    long first_ev = s->nev;
+    for (long c = 0; c < N; c++) {
+      if (!s->mask[c]) continue;
+      for (int i = 1; i < Q; i++) {
+        if (!link_active(s, c, i)) continue;
+        long yp = nbr(s, c, i, +1), ym = nbr(s, c, i, -1);
+        double d2 = or_p_tl(s->rho[yp], s->rho_g[yp], p->G, p->G_mg, p->G_gg, p->rho0) -
+                    2.0 * or_p_tl(s->rho[c], s->rho_g[c], p->G, p->G_mg, p->G_gg, p->rho0) +
+                    or_p_tl(s->rho[ym], s->rho_g[ym], p->G, p->G_mg, p->G_gg, p->rho0);
+        if (d2 >= 0.0) {
+          int32_t k = s->owner[c] < s->owner[yp] ? s->owner[c] : s->owner[yp];
+          int32_t k2 = s->owner2[c] > s->owner2[yp] ? s->owner2[c] : s->owner2[yp];
+          if (s->nev == s->evcap) {
+            s->evcap *= 2;
+            s->ev = (int64_t*)realloc(s->ev, 3 * (size_t)s->evcap * sizeof(int64_t));
+          }
+          s->ev[3 * s->nev + 0] = s->step;
+          s->ev[3 * s->nev + 1] = k;
+          s->ev[3 * s->nev + 2] = k2;
+          s->nev++;
+        }
+      }
+    }
+    for (long e = first_ev; e < s->nev; e++) {
+      any_rupture = 1;
+      s->n_ruptures += uf_union(s->alias, (int32_t)s->ev[3 * e + 1], (int32_t)s->ev[3 * e + 2]);
+    }
+  }
+
+  /* 7: streaming of both lattices */
+#pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
+  for (long c = 0; c < N; c++)
+    for (int i = 0; i < Q; i++) {
+      long from = nbr(s, c, i, -1);
+      s->f[(long)i * N + c] = s->fpost[(long)i * N + from];
+      s->g[(long)i * N + c] = s->gpost[(long)i * N + from];
+    }
+
+  free(jm);
+  memcpy(s->rho_prev, s->rho, N * sizeof(double));
+  s->have_prev = 1;
+  s->step++;
+  if (any_rupture && p->on_rupture == 1) s->stopped = 1;
+}
+
 /* Runs up to nsteps steps; returns 1 if the run stopped on a rupture      */
 /* (on_rupture == 1, the flowchart's termination), 0 otherwise.           */
 int or_step(or_sim* s, int64_t nsteps) {
   for (int64_t k = 0; k < nsteps; k++) {
     if (s->stopped) return 1;
-    one_step(s);
+    if (s->p.model == 1) one_step_tl(s);
+    else one_step(s);
   }
   return s->stopped;
 }
@@ -682,24 +885,50 @@ void or_density(or_sim* s, double* out) {
 /* velocity, structure of arrays by component (D components).  Mode 0:     */
 /* u = j/rho (Sec. 2.1.1, Eq. vel_dens); mode 1: (j + F/2)/rho with the    */
 /* force of the current state under the current film maps.                 */
+/* With model 1 the velocity of the mixture: (j_m + j_g [+ (F_m + F_g)/2]) */
+/* / (rho_m + rho_g), the printed common velocity read with momenta.       */
 void or_velocity(or_sim* s, double* out) {
   long N = s->N;
-  double* j = (double*)malloc(3 * N * sizeof(double));
+  double* j = (double*)malloc(6 * N * sizeof(double));
   compute_moments(s, j, j + N, j + 2 * N);
-  if (s->p.velocity_mode == 1) compute_force(s, s->p.film_on);
+  if (s->p.model == 1) compute_moments_gas(s, j + 3 * N, j + 4 * N, j + 5 * N);
+  if (s->p.velocity_mode == 1) {
+    if (s->p.model == 1) compute_force_tl(s, s->p.film_on);
+    else compute_force(s, s->p.film_on);
+  }
   for (int k = 0; k < s->D; k++)
     for (long c = 0; c < N; c++) {
-      double jk = j[k * N + c];
-      if (s->p.velocity_mode == 1) jk += 0.5 * s->force[3 * c + k];
-      out[k * N + c] = jk / s->rho[c];
+      double jk = j[k * N + c], r = s->rho[c];
+      if (s->p.model == 1) {
+        jk += j[(3 + k) * N + c];
+        r += s->rho_g[c];
+      }
+      if (s->p.velocity_mode == 1) {
+        jk += 0.5 * s->force[3 * c + k];
+        if (s->p.model == 1) jk += 0.5 * s->force_g[3 * c + k];
+      }
+      out[k * N + c] = jk / r;
     }
   free(j);
 }
 
+/* model 1: density of the gas lattice */
+void or_density_gas(or_sim* s, double* out) {
+  if (s->p.model != 1) return;
+  compute_moments_gas(s, NULL, NULL, NULL);
+  memcpy(out, s->rho_g, s->N * sizeof(double));
+}
+
 /* force field of the current state (3*N, component-major), for tests */
+/* (model 1: the force on the melt lattice) */
 void or_force(or_sim* s, int with_film, double* out) {
   compute_moments(s, NULL, NULL, NULL);
-  compute_force(s, with_film);
+  if (s->p.model == 1) {
+    compute_moments_gas(s, NULL, NULL, NULL);
+    compute_force_tl(s, with_film);
+  } else {
+    compute_force(s, with_film);
+  }
   for (int k = 0; k < 3; k++)
     for (long c = 0; c < s->N; c++) out[k * s->N + c] = s->force[3 * c + k];
 }
@@ -733,12 +962,14 @@ int32_t or_maps(const or_sim* s, int32_t* label, int32_t* owner, int32_t* owner2
 }
 
 /* FP64 totals of the current state: mass and momentum, serial sums */
+/* (model 1: of both lattices together) */
 void or_stats(or_sim* s, double* mass, double* mom) {
   long N = s->N;
   double m = 0, px = 0, py = 0, pz = 0;
   for (long c = 0; c < N; c++)
     for (int i = 0; i < s->Q; i++) {
       double fi = s->f[(long)i * N + c];
+      if (s->p.model == 1) fi += s->g[(long)i * N + c];
       m += fi;
       px += s->e[i][0] * fi;
       py += s->e[i][1] * fi;
@@ -787,8 +1018,15 @@ long or_gas_points(const or_sim* s, unsigned char* out) {
 
 /* bulk pressure p0 = rho/3 + (G/6) psi^2 of the current state (Sec. 2.1.2, */
 /* Eq. Pequ), the quantity plotted across a film (Sec. 4, Fig. plot)        */
+/* (model 1: the two-component pressure, R33)                                */
 void or_pressure(or_sim* s, double* out) {
   compute_moments(s, NULL, NULL, NULL);
+  if (s->p.model == 1) {
+    compute_moments_gas(s, NULL, NULL, NULL);
+    for (long c = 0; c < s->N; c++)
+      out[c] = or_p_tl(s->rho[c], s->rho_g[c], s->p.G, s->p.G_mg, s->p.G_gg, s->p.rho0);
+    return;
+  }
   for (long c = 0; c < s->N; c++) out[c] = or_p0(s->rho[c], s->p.G, s->p.rho0);
 }
 

@@ -28,6 +28,8 @@ class _Params(C.Structure):
         ("refresh_src", C.c_int32), ("growth_on", C.c_int32),
         ("gas_A", C.c_double), ("gas_dndt", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double), ("g_rho_ref", C.c_double),
+        ("model", C.c_int32), ("G_mg", C.c_double), ("G_gg", C.c_double), ("tau_g", C.c_double),
+        ("rho_g_bubble", C.c_double), ("rho_g_liquid", C.c_double),
     ]
 
 
@@ -36,7 +38,8 @@ DEFAULTS = dict(lattice=0, nx=16, ny=16, nz=1, tau=1.0, G=-5.0, rho0=1.0,
                 film_on=0, k_own=10, zone_width=6, rho_th=math.log(2.0),
                 psi_bar_mode=0, rupture_warmup=200, on_rupture=0, velocity_mode=0,
                 refresh_src=0, growth_on=0, gas_A=0.0, gas_dndt=0.0,
-                gx=0.0, gy=0.0, gz=0.0, g_rho_ref=0.0)
+                gx=0.0, gy=0.0, gz=0.0, g_rho_ref=0.0,
+                model=0, G_mg=0.0, G_gg=0.0, tau_g=1.0, rho_g_bubble=1.0, rho_g_liquid=0.05)
 
 _P = C.c_void_p
 _D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -77,6 +80,8 @@ def _load():
         "or_events": (C.c_long, [_P, _L, C.c_long]),
         "or_histogram": (None, [_P, _I, C.c_int32, C.c_int32, C.c_double, _L, _L]),
         "or_p0": (C.c_double, [C.c_double, C.c_double, C.c_double]),
+        "or_p_tl": (C.c_double, [C.c_double] * 6),
+        "or_density_gas": (None, [_P, _D]),
         "or_gas_points": (C.c_long, [_P, C.c_void_p]),
         "or_pressure": (None, [_P, _D]),
         "or_alias_unite": (C.c_int, [_P, C.c_int32, C.c_int32]),
@@ -96,6 +101,11 @@ def _load():
 
 def p0(rho, G, rho0=1.0):
     return _load().or_p0(float(rho), float(G), float(rho0))
+
+
+def p_tl(rho_m, rho_g, G, G_mg, G_gg, rho0=1.0):
+    """Two-component bulk pressure of the two-lattice model."""
+    return _load().or_p_tl(float(rho_m), float(rho_g), float(G), float(G_mg), float(G_gg), float(rho0))
 
 
 def splitmix64(x):
@@ -149,6 +159,7 @@ class OracleSim:
             raise ValueError(f"oracle rejected parameters {p}")
         self.Q = self._lib.or_Q(self._h)
         self.N = self._lib.or_N(self._h)
+        self.ncomp = 2 if p["model"] == 1 else 1  # population sets (melt, then gas)
         self.D = 2 if p["lattice"] == 0 else 3
         self.shape = (p["nz"], p["ny"], p["nx"]) if self.D == 3 else (p["ny"], p["nx"])
 
@@ -172,13 +183,15 @@ class OracleSim:
 
     def set_populations(self, f):
         f = np.ascontiguousarray(np.asarray(f, np.float64).reshape(-1))
-        assert f.size == self.Q * self.N
+        assert f.size == self.ncomp * self.Q * self.N
         self._lib.or_set_populations(self._h, f)
 
     def populations(self):
-        out = np.zeros(self.Q * self.N, np.float64)
+        """(Q, *shape); with the two-lattice model (2 Q, *shape), the melt's
+        populations first."""
+        out = np.zeros(self.ncomp * self.Q * self.N, np.float64)
         self._lib.or_get_populations(self._h, out)
-        return out.reshape((self.Q,) + self.shape)
+        return out.reshape((self.ncomp * self.Q,) + self.shape)
 
     def step(self, n=1):
         return self._lib.or_step(self._h, int(n))
@@ -195,6 +208,13 @@ class OracleSim:
     def density(self):
         out = np.zeros(self.N, np.float64)
         self._lib.or_density(self._h, out)
+        return out.reshape(self.shape)
+
+    def density_gas(self):
+        """Two-lattice model: density of the gas lattice."""
+        assert self.ncomp == 2
+        out = np.zeros(self.N, np.float64)
+        self._lib.or_density_gas(self._h, out)
         return out.reshape(self.shape)
 
     def velocity(self):

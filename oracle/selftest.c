@@ -1,7 +1,7 @@
 /*
  * selftest.c -- a driver that runs every entry point of the FP64 oracle on
  * small 2-D and 3-D lattices (film model, rupture test, refresh readings,
- * gas release, queries), so that a build with the address and
+ * gas release, the two-lattice model, queries), so that a build with the address and
  * undefined-behaviour sanitizers checks the oracle's memory accesses and
  * arithmetic.  TEST INFRASTRUCTURE ONLY: built and run by the CPU tests.
  * It includes the oracle source so that it sees its types.
@@ -10,7 +10,7 @@
 
 #include "foam_oracle.c"
 
-static int run(int lattice, int nx, int ny, int nz, int refresh_src, int growth) {
+static int run(int lattice, int nx, int ny, int nz, int refresh_src, int growth, int model) {
   or_params p;
   memset(&p, 0, sizeof p);
   p.lattice = lattice;
@@ -39,6 +39,15 @@ static int run(int lattice, int nx, int ny, int nz, int refresh_src, int growth)
   p.gy = growth ? 1e-5 : 0.0;
   p.gx = refresh_src ? -2e-5 : 0.0;
   p.g_rho_ref = 1.0;
+  if (model == 1) {  /* two lattices: no sources */
+    p.model = 1;
+    p.G_mg = 0.5;
+    p.tau_g = 0.8;
+    p.rho_g_bubble = 0.5;
+    p.rho_g_liquid = 0.05;
+    p.growth_on = 0;
+    p.gx = p.gy = 0.0;
+  }
   or_sim* s = or_create(&p);
   if (!s) return 1;
   const long N = or_N(s);
@@ -48,7 +57,7 @@ static int run(int lattice, int nx, int ny, int nz, int refresh_src, int growth)
   if (lattice == 0) nuc[2] = nuc[6] = nuc[10] = 0.0;
   if (or_set_nuclei(s, nuc, 3)) return 2;
   double* d = (double*)malloc(sizeof(double) * 3 * (size_t)N);
-  double* f = (double*)malloc(sizeof(double) * (size_t)Q * N);
+  double* f = (double*)malloc(sizeof(double) * 2 * (size_t)Q * N);
   int32_t* lab = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
   int32_t* o1 = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
   int32_t* o2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
@@ -76,6 +85,7 @@ static int run(int lattice, int nx, int ny, int nz, int refresh_src, int growth)
   double m, mom[3];
   or_stats(s, &m, mom);
   or_label_field(s, d, lab);
+  if (model == 1) or_density_gas(s, d);
   free(d); free(f); free(lab); free(o1); free(o2); free(di); free(mk); free(al); free(pts);
   or_destroy(s);
   return isfinite(m) ? 0 : 3;
@@ -83,10 +93,12 @@ static int run(int lattice, int nx, int ny, int nz, int refresh_src, int growth)
 
 int main(void) {
   int rc = 0;
-  rc |= run(0, 40, 28, 1, 0, 1);
-  rc |= run(0, 33, 17, 1, 1, 0);
-  rc |= run(1, 14, 12, 10, 0, 1);
-  rc |= run(1, 11, 9, 13, 1, 1);
+  rc |= run(0, 40, 28, 1, 0, 1, 0);
+  rc |= run(0, 33, 17, 1, 1, 0, 0);
+  rc |= run(1, 14, 12, 10, 0, 1, 0);
+  rc |= run(1, 11, 9, 13, 1, 1, 0);
+  rc |= run(0, 31, 22, 1, 0, 0, 1);
+  rc |= run(1, 12, 10, 9, 1, 0, 1);
   printf("oracle selftest %s\n", rc ? "FAILED" : "ok");
   return rc;
 }
