@@ -128,12 +128,32 @@ typedef struct {
                             it adds (rho - g_rho_ref) g of momentum and no mass per cell */
   double g_rho_ref;      /* reference density of the body force (the mean density gives
                             the buoyancy form, no net force on a periodic lattice) */
+  int32_t model;         /* 0 (default): one lattice.  1: the two lattices of Sec. 2.1.5, melt
+                            and gas, coupled every step: the fields above describe the melt
+                            (its populations, tau, its own coupling G, rho_liquid / rho_gas
+                            outside / inside the nuclei, the labels from its density); the
+                            gas lattice has tau_g, its own coupling G_gg, the coupling G_mg to
+                            the melt, and rho_g_liquid / rho_g_bubble outside / inside the
+                            nuclei.  Each lattice feels F_s = -psi_s(x) sum_i w_i e_i sum_s'
+                            G_ss' psi~_s'(x + e_i), with the bulk melt's values (psi_bar_mode 0)
+                            or x's own (mode 1) across active barrier links, and relaxes to
+                            the equilibrium at u' + tau_s F_s / rho_s, u' = (j_m / tau + j_g /
+                            tau_g) / (rho_m / tau + rho_g / tau_g).  The rupture test uses the
+                            pressure (rho_m + rho_g)/3 + (G psi_m^2 + 2 G_mg psi_m psi_g +
+                            G_gg psi_g^2)/6.  Storage FLB_F64 or FLB_F32; no gas release or
+                            body force; single lattices only (not in batches or the server). */
+  double G_mg;           /* model 1: melt-gas coupling (> 0 repels) */
+  double G_gg;           /* model 1: the gas lattice's own coupling */
+  double tau_g;          /* model 1: relaxation time of the gas lattice, > 0.5 */
+  double rho_g_bubble;   /* model 1: initial gas density inside the nuclei, > 0 */
+  double rho_g_liquid;   /* model 1: initial gas density in the melt, > 0 */
 } flb_params;
 
 /* Fills p with defaults: D2Q9 F32 64x64x1, tau 1, G -5, rho0 1, rho_liquid 2,
  * rho_gas 0.15, noise 0.01, seed 1, film off, k_own 10, zone_width 6,
  * rho_th ln 2, psi_bar_mode 0, rupture_warmup 200, on_rupture 0, velocity 0,
- * rupture_filter 1, refresh_src 0, growth off (A = dn/dt = 0), f16_rho_ref 1, no gravity. */
+ * rupture_filter 1, refresh_src 0, growth off (A = dn/dt = 0), f16_rho_ref 1, no gravity,
+ * model 0 (two-lattice fields: G_mg 0.5, G_gg 0, tau_g 1, rho_g_bubble 0.5, rho_g_liquid 0.05). */
 void flb_default_params(flb_params* p);
 
 /* A gas nucleus: centre (cell centres at integer coordinates) and radius. */
@@ -190,12 +210,21 @@ int flb_get_pressure(flb_ctx* ctx, double* host_out, size_t n);
 int flb_get_gas_points(flb_ctx* ctx, uint8_t* out, size_t n, int64_t* n_points);
 
 /* Populations of the current state, host_out[n], n == Q*nx*ny*nz, population
- * planes in the order listed above (FP64 values of the stored precision). */
+ * planes in the order listed above (FP64 values of the stored precision).
+ * With model 1, n == 2*Q*nx*ny*nz: the melt lattice's planes, then the gas's. */
 int flb_get_populations(flb_ctx* ctx, double* host_out, size_t n);
 
 /* Replace the current state by host populations (same layout); rounds to the
  * storage precision.  Does not touch the step counter or the film maps. */
 int flb_set_populations(flb_ctx* ctx, const double* host_in, size_t n);
+
+/* Model 1 (the two lattices of Sec. 2.1.5, the "Domain coupling" box of
+ * Fig. Mainflowchart): density of the gas lattice, host_out[n], n ==
+ * nx*ny*nz, FP64 sums of its stored populations.  flb_get_density gives the
+ * melt lattice's, flb_get_velocity the mixture's (j_m + j_g [+ (F_m + F_g)/2])
+ * / (rho_m + rho_g), flb_get_pressure the two-component pressure and
+ * flb_get_stats the totals of both lattices.  FLB_EINVAL with model 0. */
+int flb_get_gas_density(flb_ctx* ctx, double* host_out, size_t n);
 
 /* FP64 totals of the current state and the run counters. */
 int flb_get_stats(flb_ctx* ctx, flb_stats* out);

@@ -78,6 +78,12 @@ void flb_default_params(flb_params* p) {
   p->gas_A = 0.0;
   p->gas_dndt = 0.0;
   p->f16_rho_ref = 1.0;
+  p->model = 0;
+  p->G_mg = 0.5;
+  p->G_gg = 0.0;
+  p->tau_g = 1.0;
+  p->rho_g_bubble = 0.5;
+  p->rho_g_liquid = 0.05;
 }
 
 const char* flb_last_error(void) { return g_err.c_str(); }
@@ -111,7 +117,9 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
                        : p->storage == FLB_F32 ? block_bytes<SF32>(c->Q)
                                                : block_bytes<SF16S>(c->Q);
   c->geo.href = (float)p->f16_rho_ref;
-  c->fbytes = (size_t)c->geo.nxb * c->md.nm * c->md.nz * c->geo.block_bytes;
+  c->fcomp = (size_t)c->geo.nxb * c->md.nm * c->md.nz * c->geo.block_bytes;
+  c->ncomp = p->model == 1 ? 2 : 1;
+  c->fbytes = c->fcomp * (size_t)c->ncomp;  // with model 1 the gas lattice follows the melt's
   c->nwords = (long long)c->geo.nxb * c->md.nm * c->md.nz;
   default_tuning(c);
   // the largest block count any tile variant can produce (one plane per
@@ -127,6 +135,7 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     c->tile = save_tile;
     c->lz = save_lz;
   }
+  if (p->model == 1) c->tile = two_pass_tile(c->D);  // the two-lattice kernels use its decomposition
   bool ok = true;
   for (int b = 0; b < 2; b++) ok = ok && (c->f[b] = c->dalloc(c->fbytes));
   ok = ok && (c->ctl = (Ctl*)c->dalloc(sizeof(Ctl)));
@@ -136,6 +145,10 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     const size_t tsz = p->storage == FLB_F64 ? 8 : 4;
     ok = ok && (c->psi = c->dalloc(tsz * (size_t)c->N));
     ok = ok && (c->rho = c->dalloc(tsz * (size_t)c->N));
+    if (p->model == 1) {
+      ok = ok && (c->psi_g = c->dalloc(tsz * (size_t)c->N));
+      ok = ok && (c->rho_g = c->dalloc(tsz * (size_t)c->N));
+    }
   }
   ok = ok && (c->qd = (double*)c->dalloc(sizeof(double) * 4 * (size_t)c->N));
   ok = ok && (c->qtot = (double*)c->dalloc(sizeof(double) * 4 * 4096));
@@ -230,6 +243,14 @@ int flb_set_nuclei(flb_ctx* c, const flb_nucleus* nuc, int32_t n) {
     HIPCHK(hipMemcpyAsync(&c->ctl->n_src, nsrc, sizeof(long long), hipMemcpyDeviceToDevice, c->st));
   int rc = FLB_DISPATCH(c, do_pack, c, c->qd, 0, 0);
   if (rc) return rc;
+  if (c->p.model == 1) {  // the gas lattice: rho_g_bubble in the nuclei, rho_g_liquid elsewhere, no noise
+    hipLaunchKernelGGL(k_init_density, dim3(g), dim3(B), 0, c->st, c->qd, c->p.nx, c->p.ny, c->p.nz, c->N, dn, n,
+                       c->p.rho_g_liquid, c->p.rho_g_bubble, 0.0, (unsigned long long)c->p.seed, nullptr,
+                       c->geo.nxb, nullptr);
+    HIPCHK(hipGetLastError());
+    rc = FLB_DISPATCH(c, do_pack, c, c->qd, 0, 0, 1);
+    if (rc) return rc;
+  }
   HIPCHK(hipStreamSynchronize(c->st));
   c->dfree(dn);
   c->launched = 0;
@@ -301,6 +322,8 @@ int flb_set_tuning(flb_ctx* c, int32_t tile, int32_t lz, int32_t xcd) {
   if (tile < -1 || tile >= nt) return fail(FLB_EINVAL, "tile must be in -1..%d", nt - 1);
   if (lz < 0) return fail(FLB_EINVAL, "lz must be >= 0");
   if (xcd < -1 || xcd > 64) return fail(FLB_EINVAL, "xcd must be in -1..64");
+  if (c->p.model == 1 && tile >= 0 && tile != two_pass_tile(c->D))
+    return fail(FLB_EINVAL, "model 1 runs on the two-pass decomposition (tile %d)", two_pass_tile(c->D));
   HIPCHK(hipStreamSynchronize(c->st));
   if (tile >= 0) c->tile = tile;
   if (lz > 0) c->lz = std::min(lz, c->md.nz);
@@ -312,6 +335,10 @@ int flb_set_tuning(flb_ctx* c, int32_t tile, int32_t lz, int32_t xcd) {
 int flb_autotune(flb_ctx* c, int32_t reps, double* best_ms) {
   if (!c) return fail(FLB_EINVAL, "ctx is NULL");
   if (reps < 1 || reps > 1000) return fail(FLB_EINVAL, "reps must be in 1..1000");
+  if (c->p.model == 1) {  // one decomposition: nothing to choose
+    if (best_ms) *best_ms = 0.0;
+    return FLB_OK;
+  }
   Ctl h;
   int rc = read_ctl(c, &h);
   if (rc) return rc;
@@ -635,9 +662,51 @@ int flb_get_density(flb_ctx* c, double* out, size_t n) {
   return FLB_OK;
 }
 
+int flb_get_gas_density(flb_ctx* c, double* out, size_t n) {
+  if (!c || !out) return fail(FLB_EINVAL, "NULL argument");
+  if (c->p.model != 1) return fail(FLB_EINVAL, "the gas lattice exists only with model 1");
+  if (n != (size_t)c->N) return fail(FLB_EINVAL, "n must be nx*ny*nz = %lld", c->N);
+  int rc = FLB_DISPATCH(c, do_moments, c, false, 1);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(out, c->qd, sizeof(double) * n, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return FLB_OK;
+}
+
+// model 1: the mixture's velocity (what 1) or the two-component pressure
+// (what 0) from the FP64 moments of both lattices
+static int tl_query(flb_ctx* c, int what, double* out, size_t n) {
+  const size_t planes = 1 + (size_t)c->D;
+  double* gm = (double*)c->dalloc(sizeof(double) * (planes * (size_t)c->N + n));
+  if (!gm) return fail(FLB_ENOMEM, "query scratch allocation failed");
+  double* res = gm + planes * (size_t)c->N;
+  int rc = FLB_DISPATCH(c, do_moments, c, true, 0);
+  if (!rc) rc = FLB_DISPATCH(c, do_moments, c, true, 1, gm);
+  hipError_t e = hipSuccess;
+  if (!rc) {
+    const int B = 256, g = grid_for(c->N, B);
+    StepArgs a = step_args(c);
+    TLArgs t = tl_args(c);
+    if (c->D == 2)
+      hipLaunchKernelGGL((k_tl_query<D2Q9K>), dim3(g), dim3(B), 0, c->st, a, t, c->md, c->qd, gm, what,
+                         c->p.velocity_mode, res);
+    else
+      hipLaunchKernelGGL((k_tl_query<D3Q19K>), dim3(g), dim3(B), 0, c->st, a, t, c->md, c->qd, gm, what,
+                         c->p.velocity_mode, res);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out, res, sizeof(double) * n, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  }
+  c->dfree(gm);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(FLB_EHIP, "two-lattice query: %s", hipGetErrorString(e));
+  return FLB_OK;
+}
+
 int flb_get_velocity(flb_ctx* c, double* out, size_t n) {
   if (!c || !out) return fail(FLB_EINVAL, "NULL argument");
   if (n != (size_t)c->D * c->N) return fail(FLB_EINVAL, "n must be D*nx*ny*nz = %lld", c->D * c->N);
+  if (c->p.model == 1) return tl_query(c, 1, out, n);
   int rc = FLB_DISPATCH(c, do_moments, c, true);
   if (rc) return rc;
   double* vel = (double*)c->dalloc(sizeof(double) * n);
@@ -713,6 +782,7 @@ int flb_copy_bandwidth(const flb_allocator* alloc, void* hip_stream, int64_t byt
 int flb_get_pressure(flb_ctx* c, double* out, size_t n) {
   if (!c || !out) return fail(FLB_EINVAL, "NULL argument");
   if (n != (size_t)c->N) return fail(FLB_EINVAL, "n must be nx*ny*nz = %lld", c->N);
+  if (c->p.model == 1) return tl_query(c, 0, out, n);
   int rc = FLB_DISPATCH(c, do_moments, c, false);
   if (rc) return rc;
   const int B = 256, g = grid_for(c->N, B);
@@ -749,10 +819,13 @@ int flb_get_gas_points(flb_ctx* c, uint8_t* out, size_t n, int64_t* n_points) {
 
 int flb_get_populations(flb_ctx* c, double* out, size_t n) {
   if (!c || !out) return fail(FLB_EINVAL, "NULL argument");
-  if (n != (size_t)c->Q * c->N) return fail(FLB_EINVAL, "n must be Q*nx*ny*nz = %lld", c->Q * c->N);
+  const long long qn = (long long)c->ncomp * c->Q * c->N;
+  if (n != (size_t)qn) return fail(FLB_EINVAL, "n must be %s*nx*ny*nz = %lld", c->ncomp == 2 ? "2*Q" : "Q", qn);
   double* tmp = (double*)c->dalloc(sizeof(double) * n);
   if (!tmp) return fail(FLB_ENOMEM, "population scratch allocation failed");
-  int rc = FLB_DISPATCH(c, do_unpack, c, tmp);
+  int rc = FLB_OK;
+  for (int lat = 0; lat < c->ncomp && !rc; lat++)
+    rc = FLB_DISPATCH(c, do_unpack, c, tmp + (size_t)lat * c->Q * c->N, lat);
   hipError_t e = hipSuccess;
   if (!rc) e = hipMemcpyAsync(out, tmp, sizeof(double) * n, hipMemcpyDeviceToHost, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
@@ -764,14 +837,16 @@ int flb_get_populations(flb_ctx* c, double* out, size_t n) {
 
 int flb_set_populations(flb_ctx* c, const double* in, size_t n) {
   if (!c || !in) return fail(FLB_EINVAL, "NULL argument");
-  if (n != (size_t)c->Q * c->N) return fail(FLB_EINVAL, "n must be Q*nx*ny*nz = %lld", c->Q * c->N);
+  const long long qn = (long long)c->ncomp * c->Q * c->N;
+  if (n != (size_t)qn) return fail(FLB_EINVAL, "n must be %s*nx*ny*nz = %lld", c->ncomp == 2 ? "2*Q" : "Q", qn);
   Ctl h;
   int rc = read_ctl(c, &h);
   if (rc) return rc;
   double* tmp = (double*)c->dalloc(sizeof(double) * n);
   if (!tmp) return fail(FLB_ENOMEM, "population scratch allocation failed");
   hipError_t e = hipMemcpyAsync(tmp, in, sizeof(double) * n, hipMemcpyHostToDevice, c->st);
-  if (e == hipSuccess) rc = FLB_DISPATCH(c, do_pack, c, tmp, 1, (int)(h.steps & 1));
+  for (int lat = 0; lat < c->ncomp && e == hipSuccess && !rc; lat++)
+    rc = FLB_DISPATCH(c, do_pack, c, tmp + (size_t)lat * c->Q * c->N, 1, (int)(h.steps & 1), lat);
   if (e == hipSuccess && !rc) rc = forget_rho(c);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   c->dfree(tmp);
@@ -781,14 +856,20 @@ int flb_set_populations(flb_ctx* c, const double* in, size_t n) {
 
 int flb_get_stats(flb_ctx* c, flb_stats* out) {
   if (!c || !out) return fail(FLB_EINVAL, "NULL argument");
-  int rc = FLB_DISPATCH(c, do_moments, c, true);
-  if (rc) return rc;
-  const int nb = 1024;
-  hipLaunchKernelGGL(k_reduce_partial, dim3(nb), dim3(RED_BLOCK), 0, c->st, c->qd, 1 + c->D, c->N, c->qtot + 4);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, c->st, c->qtot + 4, nb, c->qtot);
-  HIPCHK(hipGetLastError());
-  double tot[4];
-  HIPCHK(hipMemcpyAsync(tot, c->qtot, sizeof tot, hipMemcpyDeviceToHost, c->st));
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int lat = 0; lat < c->ncomp; lat++) {  // with model 1, both lattices together
+    int rc = FLB_DISPATCH(c, do_moments, c, true, lat);
+    if (rc) return rc;
+    const int nb = 1024;
+    hipLaunchKernelGGL(k_reduce_partial, dim3(nb), dim3(RED_BLOCK), 0, c->st, c->qd, 1 + c->D, c->N, c->qtot + 4);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, c->st, c->qtot + 4, nb, c->qtot);
+    HIPCHK(hipGetLastError());
+    double part[4];
+    HIPCHK(hipMemcpyAsync(part, c->qtot, sizeof part, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int k = 0; k < 4; k++) tot[k] += part[k];
+  }
+  int rc;
   Ctl h;
   rc = read_ctl(c, &h);
   if (rc) return rc;
@@ -872,7 +953,7 @@ int flb_save(flb_ctx* c, const char* path) {
   CkptHeader hd;
   memset(&hd, 0, sizeof hd);
   memcpy(hd.magic, kCkptMagic, 8);
-  hd.version = 3;
+  hd.version = 4;
   hd.params_size = sizeof(flb_params);
   hd.p = c->p;
   hd.ctl = h;
@@ -897,7 +978,7 @@ int flb_load(flb_ctx* c, const char* path) {
   if (!fp) return fail(FLB_EINVAL, "cannot open %s", path);
   CkptHeader hd;
   int rc = fread(&hd, sizeof hd, 1, fp) == 1 ? FLB_OK : fail(FLB_EINVAL, "not a checkpoint");
-  if (!rc && (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 3 || hd.params_size != sizeof(flb_params)))
+  if (!rc && (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 4 || hd.params_size != sizeof(flb_params)))
     rc = fail(FLB_EINVAL, "not a checkpoint of this library version");
   if (!rc && (memcmp(&hd.p, &c->p, sizeof(flb_params)) != 0 || hd.fbytes != c->fbytes || hd.N != (uint64_t)c->N))
     rc = fail(FLB_EINVAL, "checkpoint parameters differ from the context's");

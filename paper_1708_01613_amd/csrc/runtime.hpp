@@ -16,6 +16,7 @@
 #include "../../include/foamlbm.h"
 #include "ops.hpp"
 #include "rupture.hpp"
+#include "twolattice.hpp"
 #include "twopass.hpp"
 
 using namespace flb;
@@ -97,6 +98,18 @@ constexpr TileCfg make_two_pass() {
                  {&launch_collide<L, SF64>, &launch_collide<L, SF32>, &launch_collide<L, SF16S>}};
 }
 
+// the two-lattice step: k_psi_tl then k_collide_tl, on the two-pass decomposition
+template <class L, class S>
+void launch_tl(const StepArgs& a, const TLArgs& t, int nblk, hipStream_t s) {
+  if (a.buf_bytes < kBufPathLimit) {
+    hipLaunchKernelGGL((k_psi_tl<L, S, true>), dim3(nblk), dim3(TP_NT), 0, s, a, t);
+    hipLaunchKernelGGL((k_collide_tl<L, S, true>), dim3(nblk), dim3(TP_NT), 0, s, a, t);
+  } else {
+    hipLaunchKernelGGL((k_psi_tl<L, S, false>), dim3(nblk), dim3(TP_NT), 0, s, a, t);
+    hipLaunchKernelGGL((k_collide_tl<L, S, false>), dim3(nblk), dim3(TP_NT), 0, s, a, t);
+  }
+}
+
 const TileCfg kTiles2[] = {make_tile<D2Q9K, 64, 1>(), make_tile<D2Q9K, 128, 1>(), make_tile<D2Q9K, 256, 1>(),
                            make_two_pass<D2Q9K>()};
 const TileCfg kTiles3[] = {make_tile<D3Q19K, 64, 4>(), make_tile<D3Q19K, 64, 8>(), make_tile<D3Q19K, 32, 8>(),
@@ -131,6 +144,7 @@ inline size_t ctx_footprint(const flb_params* p) {
     t += 2 * r(N) + r(4 * N) + r(8 * N) + 2 * r(4 * N) + 3 * r(4 * (N + 1)) + r(32 * 65536) +
          r(4 * N) + r(8 * nwords) + r(3 * 8 * nwords);
   if (p->growth_on) t += r(8 * nwords);
+  if (p->model == 1) t += 2 * r(fbytes) + 2 * r(tsz * N);  // the gas lattice's populations and arrays
   return t;
 }
 
@@ -188,7 +202,9 @@ struct flb_ctx {
   MapDims md;              // kernel-coordinate extents
   long long N = 0;         // cells
   Geo geo;                 // population block layout
-  size_t fbytes = 0;       // bytes of one population buffer
+  size_t fbytes = 0;       // bytes of one population buffer (with model 1: the melt's lattice, then the gas's)
+  size_t fcomp = 0;        // bytes of one lattice's populations in it
+  int ncomp = 1;           // lattices: 1, or 2 with model 1
   void* f[2] = {nullptr, nullptr};
   Ctl* ctl = nullptr;      // run control of the step kernel
   Ctl* qctl = nullptr;     // always-zero control for query pipelines
@@ -196,6 +212,8 @@ struct flb_ctx {
   int max_blk = 0;
   void* psi = nullptr;     // two-pass path: psi and rho arrays (compute type)
   void* rho = nullptr;
+  void* psi_g = nullptr;   // model 1: psi and rho of the gas lattice (compute type)
+  void* rho_g = nullptr;
   // tuning
   int tile = -1, lz = 0, xcd = 0;
   // film maps
@@ -353,10 +371,33 @@ inline StepArgs step_args(flb_ctx* c) {
   a.ev_cap = c->ev_cap;
   a.ctl = c->ctl;
   a.partials = c->partials;
-  a.buf_bytes = c->fbytes;
+  a.buf_bytes = c->fcomp;
   a.psi = c->psi;
   a.rho = c->rho;
   return a;
+}
+
+// model 1: the gas lattice, in the second half of each population buffer
+inline TLArgs tl_args(flb_ctx* c) {
+  TLArgs t;
+  memset(&t, 0, sizeof t);
+  for (int k = 0; k < 2; k++) t.gbuf[k] = (char*)c->f[k] + c->fcomp;
+  t.gbytes = c->fcomp;
+  t.rho_g = c->rho_g;
+  t.psi_g = c->psi_g;
+  t.G_mg = c->p.G_mg;
+  t.G_gg = c->p.G_gg;
+  t.tau_g = c->p.tau_g;
+  t.psi_bar_g = c->p.rho0 * (1.0 - exp(-c->p.rho_g_liquid / c->p.rho0));
+  return t;
+}
+
+// the two-pass tile index of a lattice (the decomposition model 1 runs on)
+inline int two_pass_tile(int D) {
+  const int n = D == 2 ? kNTiles2 : kNTiles3;
+  for (int t = 0; t < n; t++)
+    if ((D == 2 ? kTiles2[t] : kTiles3[t]).tx == 0) return t;
+  return -1;
 }
 
 inline PruneArgs prune_args(flb_ctx* c) {
@@ -577,6 +618,8 @@ int do_steps(flb_ctx* c, int64_t nsteps, bool refresh, hipEvent_t* ev = nullptr)
   const int nblk = c->nblocks();
   const StepFn fn = c->tcfg().fn[c->p.storage];
   const StepFn coll = c->tcfg().coll[c->p.storage];
+  const bool tl = c->p.model == 1;
+  const TLArgs t = tl ? tl_args(c) : TLArgs{};
   for (int64_t s = 0; s < nsteps; s++) {
     hipEvent_t* e = ev ? ev + kPhaseEv * s : nullptr;
     const bool due = refresh && c->p.film_on && c->launched % c->p.k_own == 0;
@@ -586,13 +629,20 @@ int do_steps(flb_ctx* c, int64_t nsteps, bool refresh, hipEvent_t* ev = nullptr)
       if (rc) return rc;
     }
     if (e) HIPCHK(hipEventRecord(e[1], c->st));
-    fn(a, nblk, c->st);              // fused step, or rho / psi of the two-pass variant
-    if (coll) coll(a, nblk, c->st);  // the two-pass collide
+    if (tl) {
+      launch_tl<L, S>(a, t, nblk, c->st);  // both lattices: k_psi_tl, k_collide_tl
+    } else {
+      fn(a, nblk, c->st);              // fused step, or rho / psi of the two-pass variant
+      if (coll) coll(a, nblk, c->st);  // the two-pass collide
+    }
     if (e) HIPCHK(hipEventRecord(e[2], c->st));
     // rupture test (applies its unions), pruning of united pairs' links,
     // then the finisher, which closes the step
     if (c->p.film_on && c->launched >= c->p.rupture_warmup) {
-      hipLaunchKernelGGL((k_rupture<L, typename S::ct>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, a);
+      if (tl)
+        hipLaunchKernelGGL((k_rupture_tl<L, typename S::ct>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, a, t);
+      else
+        hipLaunchKernelGGL((k_rupture<L, typename S::ct>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, a);
       hipLaunchKernelGGL((k_mask_prune<L>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, prune_args(c));
     }
     if (e) HIPCHK(hipEventRecord(e[3], c->st));
@@ -604,28 +654,35 @@ int do_steps(flb_ctx* c, int64_t nsteps, bool refresh, hipEvent_t* ev = nullptr)
   return FLB_OK;
 }
 
+// `lat` selects the lattice of a model-1 context (0 melt, 1 gas): its
+// populations start lat * fcomp bytes into each buffer
+inline void* lat_buf(const flb_ctx* c, int which, int lat) { return (char*)c->f[which] + (size_t)lat * c->fcomp; }
+
 template <class L, class S>
-int do_pack(flb_ctx* c, const double* field_dev, int mode, int which) {
+int do_pack(flb_ctx* c, const double* field_dev, int mode, int which, int lat = 0) {
   const int B = 256, g = grid_for(c->N, B);
-  hipLaunchKernelGGL((k_pack<L, S>), dim3(g), dim3(B), 0, c->st, c->f[which], c->geo, c->md, field_dev, mode);
+  hipLaunchKernelGGL((k_pack<L, S>), dim3(g), dim3(B), 0, c->st, lat_buf(c, which, lat), c->geo, c->md, field_dev,
+                     mode);
+  HIPCHK(hipGetLastError());
+  return FLB_OK;
+}
+
+// FP64 moments into rho (N) and, with_j, the D momentum planes after it
+template <class L, class S>
+int do_moments(flb_ctx* c, bool with_j, int lat = 0, double* out = nullptr) {
+  const int B = 256, g = grid_for(c->N, B);
+  double* rho = out ? out : c->qd;
+  hipLaunchKernelGGL((k_moments<L, S>), dim3(g), dim3(B), 0, c->st, lat_buf(c, 0, lat), lat_buf(c, 1, lat), c->ctl,
+                     c->geo, c->md, rho, with_j ? rho + c->N : nullptr);
   HIPCHK(hipGetLastError());
   return FLB_OK;
 }
 
 template <class L, class S>
-int do_moments(flb_ctx* c, bool with_j) {
+int do_unpack(flb_ctx* c, double* out_dev, int lat = 0) {
   const int B = 256, g = grid_for(c->N, B);
-  hipLaunchKernelGGL((k_moments<L, S>), dim3(g), dim3(B), 0, c->st, c->f[0], c->f[1], c->ctl, c->geo, c->md, c->qd,
-                     with_j ? c->qd + c->N : nullptr);
-  HIPCHK(hipGetLastError());
-  return FLB_OK;
-}
-
-template <class L, class S>
-int do_unpack(flb_ctx* c, double* out_dev) {
-  const int B = 256, g = grid_for(c->N, B);
-  hipLaunchKernelGGL((k_unpack<L, S>), dim3(g), dim3(B), 0, c->st, c->f[0], c->f[1], c->ctl, c->geo, c->md,
-                     out_dev);
+  hipLaunchKernelGGL((k_unpack<L, S>), dim3(g), dim3(B), 0, c->st, lat_buf(c, 0, lat), lat_buf(c, 1, lat), c->ctl,
+                     c->geo, c->md, out_dev);
   HIPCHK(hipGetLastError());
   return FLB_OK;
 }
@@ -666,6 +723,17 @@ inline int validate(const flb_params* p) {
   if (!isfinite(p->gx) || !isfinite(p->gy) || !isfinite(p->gz) || !isfinite(p->g_rho_ref))
     return fail(FLB_EINVAL, "non-finite body-force parameter");
   if (p->lattice == FLB_D2Q9 && p->gz != 0.0) return fail(FLB_EINVAL, "D2Q9 requires gz == 0");
+  if (p->model != 0 && p->model != 1) return fail(FLB_EINVAL, "model must be 0 or 1");
+  if (p->model == 1) {
+    if (p->storage == FLB_F16S) return fail(FLB_EINVAL, "model 1 needs FLB_F64 or FLB_F32 storage");
+    if (p->growth_on || p->gx != 0.0 || p->gy != 0.0 || p->gz != 0.0)
+      return fail(FLB_EINVAL, "model 1 has no gas release or body force");
+    if (!(p->tau_g > 0.5) || !isfinite(p->tau_g)) return fail(FLB_EINVAL, "tau_g must be > 0.5");
+    if (!isfinite(p->G_mg) || !isfinite(p->G_gg)) return fail(FLB_EINVAL, "non-finite coupling");
+    if (!(p->rho_g_bubble > 0.0) || !(p->rho_g_liquid > 0.0) || !isfinite(p->rho_g_bubble) ||
+        !isfinite(p->rho_g_liquid))
+      return fail(FLB_EINVAL, "rho_g_bubble and rho_g_liquid must be > 0");
+  }
   return FLB_OK;
 }
 

@@ -16,6 +16,25 @@
 
 namespace flb {
 
+// Arguments of the two-lattice model beyond those of the melt lattice (which
+// the StepArgs describe): the gas lattice of Sec. 2.1.5, coupled to the melt
+// at the end of every step.
+struct TLArgs {
+  void* gbuf[2];             // the gas lattice's A/B population buffers (the melt's layout)
+  unsigned long long gbytes; // bytes of one of them
+  void* rho_g;               // gas density and pseudopotential, cell-linear, compute type
+  void* psi_g;
+  double G_mg, G_gg, tau_g;  // couplings melt-gas and gas-gas; the gas relaxation time
+  double psi_bar_g;          // psi of the gas density in the bulk melt
+};
+
+// bulk pressure of the two lattices together: (rho_m + rho_g)/3 + (G psi_m^2
+// + 2 G_mg psi_m psi_g + G_gg psi_g^2)/6, FP64
+__device__ __forceinline__ double p_tl_of(double rm, double rg, double G, double G_mg, double G_gg, double rho0) {
+  const double a = rho0 * (1.0 - exp(-rm / rho0)), b = rho0 * (1.0 - exp(-rg / rho0));
+  return (rm + rg) / 3.0 + (G * a * a + 2.0 * G_mg * a * b + G_gg * b * b) / 6.0;
+}
+
 // A hit on link (x, i) unites the pair (k, k2) = (smaller owner, larger
 // owner2 of the two ends) in the alias union-find at once.  No test of this
 // step reads the aliases (the links to test are the mask, pruned before the
@@ -25,8 +44,11 @@ namespace flb {
 // the unions land.  A wavefront merges its lanes' identical pairs first, and
 // the log keeps one record per distinct (step, k, k2) of a wavefront until it
 // is full.
-template <class L, class T>
-__device__ __forceinline__ void rupture_cells(const StepArgs& a, unsigned bid, unsigned nb) {
+// TWO: the two-lattice model, whose pressure takes both densities (the gas
+// densities from tl->rho_g); always FP64, no FP32 pre-check.
+template <class L, class T, bool TWO = false>
+__device__ __forceinline__ void rupture_cells(const StepArgs& a, unsigned bid, unsigned nb,
+                                              const TLArgs* tl = nullptr) {
   Ctl* ctl = a.ctl;
   if (ctl->stopped) return;
   const long long step = ctl->steps;
@@ -44,7 +66,7 @@ __device__ __forceinline__ void rupture_cells(const StepArgs& a, unsigned bid, u
         const ListCell q(d, c);
         const T rc = mk ? rho[c] : T(1);
         T psc = T(0);
-        if constexpr (sizeof(T) == 4) psc = psi_of(rc, r0f);
+        if constexpr (sizeof(T) == 4 && !TWO) psc = psi_of(rc, r0f);
         double pc = 0.0;
         bool have_pc = false;
         int2 oc = make_int2(0, 0);
@@ -55,9 +77,19 @@ __device__ __forceinline__ void rupture_cells(const StepArgs& a, unsigned bid, u
           const unsigned ym = q.nb(d, -L::ex[i], -L::em[i], -L::ez[i]);
           const T rp = rho[yp], rm = rho[ym];
           bool hit = false;
-          if (sizeof(T) != 4 || !a.rupture_filter ||
-              d2_may_be_nonneg((float)rp, (float)rc, (float)rm, psi_of((float)rp, r0f), (float)psc,
-                               psi_of((float)rm, r0f), g6, r0f)) {
+          if constexpr (TWO) {
+            const T* rg = (const T*)tl->rho_g;
+            if (!have_pc) {
+              pc = p_tl_of((double)rc, (double)rg[c], G64, tl->G_mg, tl->G_gg, r064);
+              oc = a.own[c];
+              have_pc = true;
+            }
+            hit = p_tl_of((double)rp, (double)rg[yp], G64, tl->G_mg, tl->G_gg, r064) - 2.0 * pc +
+                      p_tl_of((double)rm, (double)rg[ym], G64, tl->G_mg, tl->G_gg, r064) >=
+                  0.0;
+          } else if (sizeof(T) != 4 || !a.rupture_filter ||
+                     d2_may_be_nonneg((float)rp, (float)rc, (float)rm, psi_of((float)rp, r0f), (float)psc,
+                                      psi_of((float)rm, r0f), g6, r0f)) {
             if (!have_pc) {
               pc = p0_of((double)rc, G64, r064);
               oc = a.own[c];
@@ -120,6 +152,11 @@ __device__ __forceinline__ void rupture_cells(const StepArgs& a, unsigned bid, u
 template <class L, class T>
 __global__ __launch_bounds__(MAP_NT) void k_rupture(StepArgs a) {
   rupture_cells<L, T>(a, blockIdx.x, gridDim.x);
+}
+
+template <class L, class T>
+__global__ __launch_bounds__(MAP_NT) void k_rupture_tl(StepArgs a, TLArgs t) {
+  rupture_cells<L, T, true>(a, blockIdx.x, gridDim.x, &t);
 }
 
 // batched: workgroups [first[k], first[k+1]) test member k

@@ -46,6 +46,8 @@ class flb_params(C.Structure):
         ("gas_A", C.c_double), ("gas_dndt", C.c_double),
         ("f16_rho_ref", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double), ("g_rho_ref", C.c_double),
+        ("model", C.c_int32), ("G_mg", C.c_double), ("G_gg", C.c_double), ("tau_g", C.c_double),
+        ("rho_g_bubble", C.c_double), ("rho_g_liquid", C.c_double),
     ]
 
 
@@ -110,6 +112,7 @@ _SIGS = {
     "flb_set_nuclei": (C.c_int, [_CTX, C.POINTER(flb_nucleus), C.c_int32]),
     "flb_step": (C.c_int, [_CTX, C.c_int64]),
     "flb_get_density": (C.c_int, [_CTX, _D, C.c_size_t]),
+    "flb_get_gas_density": (C.c_int, [_CTX, _D, C.c_size_t]),
     "flb_get_velocity": (C.c_int, [_CTX, _D, C.c_size_t]),
     "flb_get_populations": (C.c_int, [_CTX, _D, C.c_size_t]),
     "flb_set_populations": (C.c_int, [_CTX, _D, C.c_size_t]),
@@ -227,6 +230,7 @@ class Sim:
         self.Q = 9 if self.D == 2 else 19
         self.N = p.nx * p.ny * p.nz
         self.shape = (p.ny, p.nx) if self.D == 2 else (p.nz, p.ny, p.nx)
+        self.ncomp = 2 if p.model == 1 else 1  # population sets: the melt's, then the gas's
         dev = torch.cuda.current_device()
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         self._keep = None
@@ -249,6 +253,7 @@ class Sim:
         self.Q = 9 if self.D == 2 else 19
         self.N = p.nx * p.ny * p.nz
         self.shape = (p.ny, p.nx) if self.D == 2 else (p.nz, p.ny, p.nx)
+        self.ncomp = 1
         self.stream = owner.stream
         self._owner = owner
         self.h = handle
@@ -290,10 +295,16 @@ class Sim:
         check(flb_get_velocity(self.h, out, out.size), "flb_get_velocity")
         return out.reshape((self.D,) + self.shape)
 
+    def gas_density(self):
+        """Two-lattice model: density of the gas lattice."""
+        out = np.empty(self.N, np.float64)
+        check(flb_get_gas_density(self.h, out, out.size), "flb_get_gas_density")
+        return out.reshape(self.shape)
+
     def populations(self):
-        out = np.empty(self.Q * self.N, np.float64)
+        out = np.empty(self.ncomp * self.Q * self.N, np.float64)
         check(flb_get_populations(self.h, out, out.size), "flb_get_populations")
-        return out.reshape((self.Q,) + self.shape)
+        return out.reshape((self.ncomp * self.Q,) + self.shape)
 
     def set_populations(self, f):
         f = np.ascontiguousarray(np.asarray(f, np.float64).reshape(-1))

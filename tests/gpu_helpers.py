@@ -15,7 +15,8 @@ def oracle_for(params, nuclei):
     """An oracle run with the same problem definition as a GPU run."""
     keys = ("lattice", "nx", "ny", "nz", "tau", "G", "rho0", "rho_liquid", "rho_gas", "noise_amp", "seed",
             "film_on", "k_own", "zone_width", "rho_th", "psi_bar_mode", "rupture_warmup", "on_rupture",
-            "velocity_mode", "refresh_src", "growth_on", "gas_A", "gas_dndt", "gx", "gy", "gz", "g_rho_ref")
+            "velocity_mode", "refresh_src", "growth_on", "gas_A", "gas_dndt", "gx", "gy", "gz", "g_rho_ref",
+            "model", "G_mg", "G_gg", "tau_g", "rho_g_bubble", "rho_g_liquid")
     kw = {k: params[k] for k in keys if k in params}
     s = OracleSim(**kw)
     s.set_nuclei(nuclei)
