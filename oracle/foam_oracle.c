@@ -22,7 +22,9 @@
  *   6b. bubble growth (optional) the gas-release law dp/dt = A (dn/dt) / N at
  *                     each of the N domain gas points             (Sec. 2.1.3, Fig. Mainflowchart "Bubble growth")
  *   6c. body force (optional) the forcing term F_i of gravity     (Sec. 2.1.1, forcing equation)
- *   7. streaming      f_i(x + e_i) = f*_i(x), periodic           (Sec. 2.1.1, streaming equation)
+ *   7. streaming      f_i(x + e_i) = f*_i(x), periodic; with open_z the
+ *                     last axis is open to a liquid reservoir       (Sec. 2.1.1, streaming equation; Sec. 5, the
+ *                                                                    container open for the liquid)
  *   8. rupture test   d2 p0 / dn2 >= 0 on barrier links          (Sec. 2.1.5, eta_m equation; Sec. 4)
  *
  * With model = 1 the step is the paper's two-lattice form (Sec. 2.1.5, the
@@ -105,6 +107,9 @@ typedef struct {
   double tau_g;           /* model 1: relaxation time of the gas lattice */
   double rho_g_bubble;    /* model 1: gas density inside the nuclei */
   double rho_g_liquid;    /* model 1: gas density in the melt */
+  int32_t open_z;         /* 1: the first and last planes of the last axis (z on D3Q19, y on D2Q9) */
+                          /* are open to a liquid reservoir at rest at density rho_res (R35) */
+  double rho_res;         /* density of that reservoir */
 } or_params;
 
 typedef struct {
@@ -164,6 +169,17 @@ static long nbr(const or_sim* s, long c, int i, int sign) {
   y = wrap(y + sign * s->e[i][1], ny);
   z = wrap(z + sign * s->e[i][2], nz);
   return x + nx * (y + ny * z);
+}
+
+/* With open_z (R35): whether the neighbour of c along sign * e_i lies      */
+/* beyond an open plane (outside the container, in the reservoir).          */
+static int beyond_open(const or_sim* s, long c, int i, int sign) {
+  if (!s->p.open_z) return 0;
+  const int ax = s->D == 2 ? 1 : 2;
+  const long n = ax == 1 ? s->p.ny : s->p.nz;
+  const long k = ax == 1 ? (c / s->p.nx) % s->p.ny : c / ((long)s->p.nx * s->p.ny);
+  const long t = k + sign * s->e[i][ax];
+  return t < 0 || t >= n;
 }
 
 static double psi_of(const or_params* p, double rho) {
@@ -233,8 +249,10 @@ or_sim* or_create(const or_params* p) {
   if (p->lattice == 0 && p->nz != 1) return NULL;
   if (!(p->tau > 0.5)) return NULL;
   if (p->model != 0 && p->model != 1) return NULL;
-  /* the two-lattice model carries no growth source or body force */
-  if (p->model == 1 && (!(p->tau_g > 0.5) || p->growth_on || p->gx != 0.0 || p->gy != 0.0 || p->gz != 0.0 ||
+  if (p->open_z != 0 && p->open_z != 1) return NULL;
+  if (p->open_z && !(p->rho_res > 0.0)) return NULL;
+  /* the two-lattice model carries no body force (its gas release goes to the gas lattice) */
+  if (p->model == 1 && (!(p->tau_g > 0.5) || p->gx != 0.0 || p->gy != 0.0 || p->gz != 0.0 ||
                         !(p->rho_g_bubble > 0.0) || !(p->rho_g_liquid > 0.0)))
     return NULL;
   or_sim* s = (or_sim*)calloc(1, sizeof(or_sim));
@@ -577,6 +595,8 @@ static void compute_force(or_sim* s, int with_film) {
       if (o < i) continue; /* each opposite pair once */
       long yp = nbr(s, c, i, +1), ym = nbr(s, c, i, -1);
       double sp = s->psi[yp], sm = s->psi[ym];
+      if (beyond_open(s, c, i, +1)) sp = psi_of(p, p->rho_res); /* the reservoir (R35) */
+      if (beyond_open(s, c, i, -1)) sm = psi_of(p, p->rho_res);
       if (with_film) {
         double bar = p->psi_bar_mode == 0 ? psi_liq : s->psi[c];
         if (link_active(s, c, i)) sp = bar;
@@ -671,8 +691,10 @@ static void one_step(or_sim* s) {
       for (int i = 1; i < Q; i++) {
         if (!link_active(s, c, i)) continue;
         long yp = nbr(s, c, i, +1), ym = nbr(s, c, i, -1);
-        double d2 = or_p0(s->rho[yp], p->G, p->rho0) - 2.0 * or_p0(s->rho[c], p->G, p->rho0) +
-                    or_p0(s->rho[ym], p->G, p->rho0);
+        /* beyond an open plane the reservoir's density (R35) */
+        double rp = beyond_open(s, c, i, +1) ? p->rho_res : s->rho[yp];
+        double rm = beyond_open(s, c, i, -1) ? p->rho_res : s->rho[ym];
+        double d2 = or_p0(rp, p->G, p->rho0) - 2.0 * or_p0(s->rho[c], p->G, p->rho0) + or_p0(rm, p->G, p->rho0);
         if (d2 >= 0.0) {
           /* the film's pair: smallest and largest nearest-bubble label */
           int32_t k = s->owner[c] < s->owner[yp] ? s->owner[c] : s->owner[yp];
@@ -694,10 +716,13 @@ static void one_step(or_sim* s) {
     }
   }
 
-  /* 7: pull form of f_i(x + e_i) <- f*_i(x) */
+  /* 7: pull form of f_i(x + e_i) <- f*_i(x); across an open plane the    */
+  /* population comes from the reservoir at rest, w_i rho_res (R35), and   */
+  /* what streams out of the container leaves it                           */
 #pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
   for (long c = 0; c < N; c++)
-    for (int i = 0; i < Q; i++) s->f[(long)i * N + c] = s->fpost[(long)i * N + nbr(s, c, i, -1)];
+    for (int i = 0; i < Q; i++)
+      s->f[(long)i * N + c] = beyond_open(s, c, i, -1) ? s->w[i] * p->rho_res : s->fpost[(long)i * N + nbr(s, c, i, -1)];
 
   free(jx);
   memcpy(s->rho_prev, s->rho, N * sizeof(double));
@@ -758,6 +783,8 @@ static void compute_force_tl(or_sim* s, int with_film) {
       if (o < i) continue;
       long yp = nbr(s, c, i, +1), ym = nbr(s, c, i, -1);
       double pm = s->psi[yp], mm = s->psi[ym], pg = s->psi_g[yp], mg = s->psi_g[ym];
+      if (beyond_open(s, c, i, +1)) { pm = psi_of(p, p->rho_res); pg = lg; } /* the reservoir (R35) */
+      if (beyond_open(s, c, i, -1)) { mm = psi_of(p, p->rho_res); mg = lg; }
       if (with_film) {
         double bm = p->psi_bar_mode == 0 ? lm : s->psi[c];
         double bg = p->psi_bar_mode == 0 ? lg : s->psi_g[c];
@@ -815,6 +842,16 @@ static void one_step_tl(or_sim* s) {
     }
   }
 
+  /* 6b: bubble growth (Sec. 2.1.3): the gas release of each domain gas    */
+  /* point goes to the gas lattice, w_i drho with drho = 3 A (dn/dt) / N    */
+  if (p->growth_on && s->n_src > 0) {
+    double drho = 3.0 * p->gas_A * p->gas_dndt / (double)s->n_src;
+    for (long c = 0; c < N; c++) {
+      if (!s->src[c]) continue;
+      for (int i = 0; i < Q; i++) s->gpost[(long)i * N + c] += s->w[i] * drho;
+    }
+  }
+
   /* 8: rupture test, on the two-component pressure (R33) */
   int any_rupture = 0;
   if (p->film_on && s->maps_valid && s->step >= p->rupture_warmup) {
@@ -824,9 +861,12 @@ static void one_step_tl(or_sim* s) {
       for (int i = 1; i < Q; i++) {
         if (!link_active(s, c, i)) continue;
         long yp = nbr(s, c, i, +1), ym = nbr(s, c, i, -1);
-        double d2 = or_p_tl(s->rho[yp], s->rho_g[yp], p->G, p->G_mg, p->G_gg, p->rho0) -
+        int op = beyond_open(s, c, i, +1), om = beyond_open(s, c, i, -1); /* the reservoir (R35) */
+        double d2 = or_p_tl(op ? p->rho_res : s->rho[yp], op ? p->rho_g_liquid : s->rho_g[yp], p->G, p->G_mg,
+                            p->G_gg, p->rho0) -
                     2.0 * or_p_tl(s->rho[c], s->rho_g[c], p->G, p->G_mg, p->G_gg, p->rho0) +
-                    or_p_tl(s->rho[ym], s->rho_g[ym], p->G, p->G_mg, p->G_gg, p->rho0);
+                    or_p_tl(om ? p->rho_res : s->rho[ym], om ? p->rho_g_liquid : s->rho_g[ym], p->G, p->G_mg,
+                            p->G_gg, p->rho0);
         if (d2 >= 0.0) {
           int32_t k = s->owner[c] < s->owner[yp] ? s->owner[c] : s->owner[yp];
           int32_t k2 = s->owner2[c] > s->owner2[yp] ? s->owner2[c] : s->owner2[yp];
@@ -847,13 +887,15 @@ static void one_step_tl(or_sim* s) {
     }
   }
 
-  /* 7: streaming of both lattices */
+  /* 7: streaming of both lattices; across an open plane from the          */
+  /* reservoir at rest: melt rho_res, gas rho_g_liquid (R35)               */
 #pragma omp parallel for schedule(static) if (N >= OR_OMP_MIN_CELLS)
   for (long c = 0; c < N; c++)
     for (int i = 0; i < Q; i++) {
       long from = nbr(s, c, i, -1);
-      s->f[(long)i * N + c] = s->fpost[(long)i * N + from];
-      s->g[(long)i * N + c] = s->gpost[(long)i * N + from];
+      int out = beyond_open(s, c, i, -1);
+      s->f[(long)i * N + c] = out ? s->w[i] * p->rho_res : s->fpost[(long)i * N + from];
+      s->g[(long)i * N + c] = out ? s->w[i] * p->rho_g_liquid : s->gpost[(long)i * N + from];
     }
 
   free(jm);

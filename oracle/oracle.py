@@ -30,6 +30,7 @@ class _Params(C.Structure):
         ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double), ("g_rho_ref", C.c_double),
         ("model", C.c_int32), ("G_mg", C.c_double), ("G_gg", C.c_double), ("tau_g", C.c_double),
         ("rho_g_bubble", C.c_double), ("rho_g_liquid", C.c_double),
+        ("open_z", C.c_int32), ("rho_res", C.c_double),
     ]
 
 
@@ -39,7 +40,8 @@ DEFAULTS = dict(lattice=0, nx=16, ny=16, nz=1, tau=1.0, G=-5.0, rho0=1.0,
                 psi_bar_mode=0, rupture_warmup=200, on_rupture=0, velocity_mode=0,
                 refresh_src=0, growth_on=0, gas_A=0.0, gas_dndt=0.0,
                 gx=0.0, gy=0.0, gz=0.0, g_rho_ref=0.0,
-                model=0, G_mg=0.0, G_gg=0.0, tau_g=1.0, rho_g_bubble=1.0, rho_g_liquid=0.05)
+                model=0, G_mg=0.0, G_gg=0.0, tau_g=1.0, rho_g_bubble=1.0, rho_g_liquid=0.05,
+                open_z=0, rho_res=2.0)
 
 _P = C.c_void_p
 _D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")

@@ -1,7 +1,7 @@
 /*
  * selftest.c -- a driver that runs every entry point of the FP64 oracle on
  * small 2-D and 3-D lattices (film model, rupture test, refresh readings,
- * gas release, the two-lattice model, queries), so that a build with the address and
+ * gas release, the two-lattice model, the open container, queries), so that a build with the address and
  * undefined-behaviour sanitizers checks the oracle's memory accesses and
  * arithmetic.  TEST INFRASTRUCTURE ONLY: built and run by the CPU tests.
  * It includes the oracle source so that it sees its types.
@@ -45,8 +45,11 @@ static int run(int lattice, int nx, int ny, int nz, int refresh_src, int growth,
     p.tau_g = 0.8;
     p.rho_g_bubble = 0.5;
     p.rho_g_liquid = 0.05;
-    p.growth_on = 0;
     p.gx = p.gy = 0.0;
+  }
+  if (refresh_src == 0 && lattice == 1) {  /* a container open across the last axis */
+    p.open_z = 1;
+    p.rho_res = 2.0;
   }
   or_sim* s = or_create(&p);
   if (!s) return 1;
@@ -99,6 +102,7 @@ int main(void) {
   rc |= run(1, 11, 9, 13, 1, 1, 0);
   rc |= run(0, 31, 22, 1, 0, 0, 1);
   rc |= run(1, 12, 10, 9, 1, 0, 1);
+  rc |= run(1, 12, 10, 9, 0, 1, 1);
   printf("oracle selftest %s\n", rc ? "FAILED" : "ok");
   return rc;
 }

@@ -16,7 +16,7 @@ def oracle_for(params, nuclei):
     keys = ("lattice", "nx", "ny", "nz", "tau", "G", "rho0", "rho_liquid", "rho_gas", "noise_amp", "seed",
             "film_on", "k_own", "zone_width", "rho_th", "psi_bar_mode", "rupture_warmup", "on_rupture",
             "velocity_mode", "refresh_src", "growth_on", "gas_A", "gas_dndt", "gx", "gy", "gz", "g_rho_ref",
-            "model", "G_mg", "G_gg", "tau_g", "rho_g_bubble", "rho_g_liquid")
+            "model", "G_mg", "G_gg", "tau_g", "rho_g_bubble", "rho_g_liquid", "open_z", "rho_res")
     kw = {k: params[k] for k in keys if k in params}
     s = OracleSim(**kw)
     s.set_nuclei(nuclei)

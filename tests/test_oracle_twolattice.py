@@ -142,7 +142,8 @@ def test_two_bubble_film_behaves_as_the_single_lattice_reading():
     assert s.n_ruptures == 1 and nbs[-1] == 1
 
 
-def test_rejects_sources_with_two_lattices():
-    for bad in (dict(growth_on=1, gas_A=1.0, gas_dndt=1.0), dict(gx=1e-5), dict(tau_g=0.5), dict(rho_g_liquid=0.0)):
+def test_rejects_bad_two_lattice_parameters():
+    # (the gas release goes to the gas lattice; a body force is not part of the model)
+    for bad in (dict(gx=1e-5), dict(tau_g=0.5), dict(rho_g_liquid=0.0), dict(rho_g_bubble=-1.0)):
         with pytest.raises(ValueError):
             OracleSim(lattice=0, nx=8, ny=8, **dict(TL, **bad))
