@@ -26,7 +26,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 # (the kernel reads a 4-byte barrier mask instead of the flag byte: 156 B)
 DESIGN_BYTES = 156
 BYTES_PER_UPDATE = {("d3q19", "f32"): 153, ("d3q19", "f16s"): 77, ("d3q19", "f64"): 305,
-                    ("d2q9", "f32"): 73, ("d2q9", "f16s"): 37, ("d2q9", "f64"): 145}
+                    ("d2q9", "f32"): 73, ("d2q9", "f16s"): 37, ("d2q9", "f64"): 145,
+                    # two lattices, two passes: 2 x 19 x 4 B read twice and written once,
+                    # 4 arrays x 4 B written, 2 x 4 B read, a 4 B mask
+                    ("d3q19_two_lattice", "f32"): 2 * 76 * 2 + 2 * 76 + 16 + 8 + 4}
 
 
 def log(msg):
@@ -278,6 +281,35 @@ def main():
         torch.cuda.empty_cache()
     except Exception as exc:  # a variant failing must not hide the main line
         variants["d3q19_f16s_kernel"] = {"error": str(exc)}
+    # the two-lattice model (melt and gas lattices, Sec. 2.1.5) on the same
+    # lattice and nuclei: the whole path and its step kernels (k_psi_tl +
+    # k_collide_tl: both lattices read twice and written once, the four
+    # density / pseudopotential arrays written and two of them read, the mask)
+    try:
+        ptl = dict(params, model=1, G_mg=0.3, tau_g=1.0, rho_g_bubble=0.4, rho_g_liquid=0.05)
+        stl = foamlbm.Sim(**ptl)
+        stl.set_nuclei(nuc)
+        stl.step(setup)
+        torch.cuda.synchronize()
+        ntl = max(20, min(100, args.steps))
+        t0 = time.perf_counter()
+        stl.step(ntl)
+        torch.cuda.synchronize()
+        wtl = time.perf_counter() - t0
+        mstl = stl.time_steps(nk, refresh=False, kernel=True)[1] / nk
+        btl = BYTES_PER_UPDATE[("d3q19_two_lattice", "f32")]
+        variants["d3q19_two_lattice"] = {
+            "steps": ntl, "MLUPS": round(N * ntl / wtl / 1e6, 1), "ms_per_step": round(wtl * 1e3 / ntl, 4),
+            "kernel_ms": round(mstl, 4), "bytes_per_update": btl,
+            "GBs_algorithmic": round(btl * N / (mstl * 1e-3) / 1e9, 1),
+            "frac": round(btl * N / (mstl * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel": "k_psi_tl+k_collide_tl<D3Q19K,SF32>", "n_bubbles": stl.stats()["n_bubbles"]}
+        log(f"two-lattice d3q19 256^3: {variants['d3q19_two_lattice']['MLUPS']:.0f} MLUPS whole path, "
+            f"step kernels {mstl:.4f} ms")
+        del stl
+        torch.cuda.empty_cache()
+    except Exception as exc:
+        variants["d3q19_two_lattice"] = {"error": str(exc)}
     # the 2-D foam-growth workload: D2Q9 1024^2 FP32, film on, bubble labels,
     # the size histogram and the overlap with the previous labels read back
     # every 500 steps over its full horizon (whole path, then the step kernel

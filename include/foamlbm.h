@@ -140,20 +140,32 @@ typedef struct {
                             the equilibrium at u' + tau_s F_s / rho_s, u' = (j_m / tau + j_g /
                             tau_g) / (rho_m / tau + rho_g / tau_g).  The rupture test uses the
                             pressure (rho_m + rho_g)/3 + (G psi_m^2 + 2 G_mg psi_m psi_g +
-                            G_gg psi_g^2)/6.  Storage FLB_F64 or FLB_F32; no gas release or
-                            body force; single lattices only (not in batches or the server). */
+                            G_gg psi_g^2)/6.  Storage FLB_F64 or FLB_F32; the gas release
+                            (growth_on) goes to the gas lattice; no body force; single
+                            lattices only (not in batches or the server). */
   double G_mg;           /* model 1: melt-gas coupling (> 0 repels) */
   double G_gg;           /* model 1: the gas lattice's own coupling */
   double tau_g;          /* model 1: relaxation time of the gas lattice, > 0.5 */
   double rho_g_bubble;   /* model 1: initial gas density inside the nuclei, > 0 */
   double rho_g_liquid;   /* model 1: initial gas density in the melt, > 0 */
+  int32_t open_z;        /* 1: the container of Sec. 5, open for the liquid: the first and last
+                            planes across the last axis (z on D3Q19, y on D2Q9) face a reservoir
+                            at rest, melt density rho_res (and, with model 1, gas density
+                            rho_g_liquid).  A population that streams out through such a plane
+                            leaves; one that streams in is the reservoir's w_i rho; neighbours
+                            beyond the planes (force, rupture test, velocity query) are the
+                            reservoir's.  The other axes stay periodic, and so do the film maps
+                            (labels, owners, barriers).  Runs on the two-pass kernels; single
+                            lattices only.  0 (default): periodic. */
+  double rho_res;        /* open_z: reservoir (melt) density, > 0 */
 } flb_params;
 
 /* Fills p with defaults: D2Q9 F32 64x64x1, tau 1, G -5, rho0 1, rho_liquid 2,
  * rho_gas 0.15, noise 0.01, seed 1, film off, k_own 10, zone_width 6,
  * rho_th ln 2, psi_bar_mode 0, rupture_warmup 200, on_rupture 0, velocity 0,
  * rupture_filter 1, refresh_src 0, growth off (A = dn/dt = 0), f16_rho_ref 1, no gravity,
- * model 0 (two-lattice fields: G_mg 0.5, G_gg 0, tau_g 1, rho_g_bubble 0.5, rho_g_liquid 0.05). */
+ * model 0 (two-lattice fields: G_mg 0.5, G_gg 0, tau_g 1, rho_g_bubble 0.5, rho_g_liquid 0.05),
+ * open_z 0 (rho_res 2). */
 void flb_default_params(flb_params* p);
 
 /* A gas nucleus: centre (cell centres at integer coordinates) and radius. */

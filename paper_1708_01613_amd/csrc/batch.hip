@@ -20,7 +20,8 @@ int flb_batch_create(const flb_params* params, int32_t count, const flb_allocato
     }
     if (params[k].lattice != params[0].lattice || params[k].storage != params[0].storage)
       return fail(FLB_EINVAL, "member %d: all members need the same lattice and storage", k);
-    if (params[k].model != 0) return fail(FLB_EINVAL, "member %d: batches hold single-lattice (model 0) members", k);
+    if (params[k].model != 0 || params[k].open_z)
+      return fail(FLB_EINVAL, "member %d: batches hold periodic single-lattice (model 0) members", k);
   }
   if (alloc && (!alloc->alloc || !alloc->free)) return fail(FLB_EINVAL, "allocator needs alloc and free");
   flb_batch* b = new (std::nothrow) flb_batch();

@@ -84,6 +84,8 @@ void flb_default_params(flb_params* p) {
   p->tau_g = 1.0;
   p->rho_g_bubble = 0.5;
   p->rho_g_liquid = 0.05;
+  p->open_z = 0;
+  p->rho_res = 2.0;
 }
 
 const char* flb_last_error(void) { return g_err.c_str(); }
@@ -135,7 +137,8 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
     c->tile = save_tile;
     c->lz = save_lz;
   }
-  if (p->model == 1) c->tile = two_pass_tile(c->D);  // the two-lattice kernels use its decomposition
+  // the two-lattice kernels and the open container run on the two-pass decomposition
+  if (p->model == 1 || p->open_z) c->tile = two_pass_tile(c->D);
   bool ok = true;
   for (int b = 0; b < 2; b++) ok = ok && (c->f[b] = c->dalloc(c->fbytes));
   ok = ok && (c->ctl = (Ctl*)c->dalloc(sizeof(Ctl)));
@@ -322,8 +325,8 @@ int flb_set_tuning(flb_ctx* c, int32_t tile, int32_t lz, int32_t xcd) {
   if (tile < -1 || tile >= nt) return fail(FLB_EINVAL, "tile must be in -1..%d", nt - 1);
   if (lz < 0) return fail(FLB_EINVAL, "lz must be >= 0");
   if (xcd < -1 || xcd > 64) return fail(FLB_EINVAL, "xcd must be in -1..64");
-  if (c->p.model == 1 && tile >= 0 && tile != two_pass_tile(c->D))
-    return fail(FLB_EINVAL, "model 1 runs on the two-pass decomposition (tile %d)", two_pass_tile(c->D));
+  if ((c->p.model == 1 || c->p.open_z) && tile >= 0 && tile != two_pass_tile(c->D))
+    return fail(FLB_EINVAL, "model 1 and the open container run on the two-pass path (tile %d)", two_pass_tile(c->D));
   HIPCHK(hipStreamSynchronize(c->st));
   if (tile >= 0) c->tile = tile;
   if (lz > 0) c->lz = std::min(lz, c->md.nz);
@@ -335,7 +338,7 @@ int flb_set_tuning(flb_ctx* c, int32_t tile, int32_t lz, int32_t xcd) {
 int flb_autotune(flb_ctx* c, int32_t reps, double* best_ms) {
   if (!c) return fail(FLB_EINVAL, "ctx is NULL");
   if (reps < 1 || reps > 1000) return fail(FLB_EINVAL, "reps must be in 1..1000");
-  if (c->p.model == 1) {  // one decomposition: nothing to choose
+  if (c->p.model == 1 || c->p.open_z) {  // one decomposition: nothing to choose
     if (best_ms) *best_ms = 0.0;
     return FLB_OK;
   }

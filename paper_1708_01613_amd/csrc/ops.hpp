@@ -159,6 +159,8 @@ __global__ void k_velocity(StepArgs a, MapDims d, const double* rho, const doubl
         const long long ym = cell_of(d, wrap_any(x - L::ex[i], d.nx), wrap_any(m - L::em[i], d.nm),
                                      wrap_any(z - L::ez[i], d.nz));
         double pp = psi_of(rho[yp], a.rho0), pm = psi_of(rho[ym], a.rho0);
+        if (a.open_z && (z + L::ez[i] < 0 || z + L::ez[i] >= d.nz)) pp = psi_of(a.rho_res, a.rho0);  // the reservoir
+        if (a.open_z && (z - L::ez[i] < 0 || z - L::ez[i] >= d.nz)) pm = psi_of(a.rho_res, a.rho0);
         if (bar & (1u << i)) pp = pb;
         if (bar & (1u << (i + 1))) pm = pb;
         const double dd = L::w[i] * (pp - pm);

@@ -374,6 +374,8 @@ inline StepArgs step_args(flb_ctx* c) {
   a.buf_bytes = c->fcomp;
   a.psi = c->psi;
   a.rho = c->rho;
+  a.open_z = c->p.open_z;
+  a.rho_res = c->p.rho_res;
   return a;
 }
 
@@ -389,6 +391,7 @@ inline TLArgs tl_args(flb_ctx* c) {
   t.G_gg = c->p.G_gg;
   t.tau_g = c->p.tau_g;
   t.psi_bar_g = c->p.rho0 * (1.0 - exp(-c->p.rho_g_liquid / c->p.rho0));
+  t.rho_g_res = c->p.rho_g_liquid;
   return t;
 }
 
@@ -724,10 +727,11 @@ inline int validate(const flb_params* p) {
     return fail(FLB_EINVAL, "non-finite body-force parameter");
   if (p->lattice == FLB_D2Q9 && p->gz != 0.0) return fail(FLB_EINVAL, "D2Q9 requires gz == 0");
   if (p->model != 0 && p->model != 1) return fail(FLB_EINVAL, "model must be 0 or 1");
+  if (p->open_z != 0 && p->open_z != 1) return fail(FLB_EINVAL, "open_z must be 0 or 1");
+  if (p->open_z && (!(p->rho_res > 0.0) || !isfinite(p->rho_res))) return fail(FLB_EINVAL, "rho_res must be > 0");
   if (p->model == 1) {
     if (p->storage == FLB_F16S) return fail(FLB_EINVAL, "model 1 needs FLB_F64 or FLB_F32 storage");
-    if (p->growth_on || p->gx != 0.0 || p->gy != 0.0 || p->gz != 0.0)
-      return fail(FLB_EINVAL, "model 1 has no gas release or body force");
+    if (p->gx != 0.0 || p->gy != 0.0 || p->gz != 0.0) return fail(FLB_EINVAL, "model 1 has no body force");
     if (!(p->tau_g > 0.5) || !isfinite(p->tau_g)) return fail(FLB_EINVAL, "tau_g must be > 0.5");
     if (!isfinite(p->G_mg) || !isfinite(p->G_gg)) return fail(FLB_EINVAL, "non-finite coupling");
     if (!(p->rho_g_bubble > 0.0) || !(p->rho_g_liquid > 0.0) || !isfinite(p->rho_g_bubble) ||

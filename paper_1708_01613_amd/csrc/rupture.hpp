@@ -26,6 +26,7 @@ struct TLArgs {
   void* psi_g;
   double G_mg, G_gg, tau_g;  // couplings melt-gas and gas-gas; the gas relaxation time
   double psi_bar_g;          // psi of the gas density in the bulk melt
+  double rho_g_res;          // gas density of the bulk melt (and of the reservoir of an open container)
 };
 
 // bulk pressure of the two lattices together: (rho_m + rho_g)/3 + (G psi_m^2
@@ -75,7 +76,10 @@ __device__ __forceinline__ void rupture_cells(const StepArgs& a, unsigned bid, u
           if (!(mk & (1u << i))) continue;
           const unsigned yp = q.nb(d, L::ex[i], L::em[i], L::ez[i]);
           const unsigned ym = q.nb(d, -L::ex[i], -L::em[i], -L::ez[i]);
-          const T rp = rho[yp], rm = rho[ym];
+          // beyond an open plane the reservoir's densities
+          const bool op = a.open_z && (q.z + L::ez[i] < 0 || q.z + L::ez[i] >= a.nz);
+          const bool om = a.open_z && (q.z - L::ez[i] < 0 || q.z - L::ez[i] >= a.nz);
+          const T rp = op ? (T)a.rho_res : rho[yp], rm = om ? (T)a.rho_res : rho[ym];
           bool hit = false;
           if constexpr (TWO) {
             const T* rg = (const T*)tl->rho_g;
@@ -84,10 +88,11 @@ __device__ __forceinline__ void rupture_cells(const StepArgs& a, unsigned bid, u
               oc = a.own[c];
               have_pc = true;
             }
-            hit = p_tl_of((double)rp, (double)rg[yp], G64, tl->G_mg, tl->G_gg, r064) - 2.0 * pc +
-                      p_tl_of((double)rm, (double)rg[ym], G64, tl->G_mg, tl->G_gg, r064) >=
+            const double gp = op ? tl->rho_g_res : (double)rg[yp], gm = om ? tl->rho_g_res : (double)rg[ym];
+            hit = p_tl_of((double)rp, gp, G64, tl->G_mg, tl->G_gg, r064) - 2.0 * pc +
+                      p_tl_of((double)rm, gm, G64, tl->G_mg, tl->G_gg, r064) >=
                   0.0;
-          } else if (sizeof(T) != 4 || !a.rupture_filter ||
+          } else if (sizeof(T) != 4 || !a.rupture_filter || op || om ||
                      d2_may_be_nonneg((float)rp, (float)rc, (float)rm, psi_of((float)rp, r0f), (float)psc,
                                       psi_of((float)rm, r0f), g6, r0f)) {
             if (!have_pc) {

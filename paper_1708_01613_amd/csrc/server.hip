@@ -274,7 +274,7 @@ int flb_server_submit(flb_server* s, const flb_params* p, const flb_nucleus* nuc
   if (steps < 0) return fail(FLB_EINVAL, "steps must be >= 0");
   int rc = validate(p);
   if (rc) return rc;
-  if (p->model != 0) return fail(FLB_EINVAL, "the server runs single-lattice (model 0) jobs");
+  if (p->model != 0 || p->open_z) return fail(FLB_EINVAL, "the server runs periodic single-lattice (model 0) jobs");
   const size_t fp = ctx_footprint(p);
   if (fp > (size_t)s->cfg.pool_bytes)
     return fail(FLB_EBUSY, "job needs %zu device bytes, more than the pool of %lld", fp,

@@ -53,6 +53,8 @@ struct StepArgs {
   double* partials;      // 4 doubles per workgroup
   void* psi;             // two-pass path: psi and rho of the current state,
   void* rho;             // compute type, cell-linear
+  int open_z;            // 1: the first and last z planes face a liquid reservoir at rest (two-pass path)
+  double rho_res;        // its density
 };
 
 __device__ __forceinline__ int wrap_dec(int a, int n) { return a == 0 ? n - 1 : a - 1; }

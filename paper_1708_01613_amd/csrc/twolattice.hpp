@@ -119,11 +119,24 @@ __global__ __launch_bounds__(TP_NT) void k_collide_tl(StepArgs a, TLArgs t) {
   const unsigned bar = (a.film_on && act) ? a.mask[c] & kLinkBits : 0u;  // exact active links
   const T bm = a.psi_bar_mode == 0 ? (T)a.psi_bar : pmc;
   const T bg = a.psi_bar_mode == 0 ? (T)t.psi_bar_g : pgc;
+  // an open container: the planes beyond z = 0 and z = nz - 1 hold the reservoir
+  const bool lo_open = a.open_z && z == 0, hi_open = a.open_z && z == nz - 1;
+  // (reservoir values rounded once from FP64)
+  const double rm_res = a.rho_res, rg_res = t.rho_g_res;
+  const T pm_res = a.open_z ? (T)(a.rho0 * (1.0 - exp(-a.rho_res / a.rho0))) : T(0), pg_res = (T)t.psi_bar_g;
   T am[3] = {T(0), T(0), T(0)}, ag[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int i = 1; i < Q; i += 2) {
     const unsigned yp = nb(L::ex[i], L::em[i], L::ez[i]), ym = nb(-L::ex[i], -L::em[i], -L::ez[i]);
     T mp = psm[yp], mq = psm[ym], gp = psg[yp], gq = psg[ym];
+    if ((L::ez[i] > 0 && hi_open) || (L::ez[i] < 0 && lo_open)) {
+      mp = pm_res;
+      gp = pg_res;
+    }
+    if ((L::ez[i] > 0 && lo_open) || (L::ez[i] < 0 && hi_open)) {
+      mq = pm_res;
+      gq = pg_res;
+    }
     if (bar) {
       if (bar & (1u << i)) {
         mp = bm;
@@ -159,7 +172,13 @@ __global__ __launch_bounds__(TP_NT) void k_collide_tl(StepArgs a, TLArgs t) {
   // 4, 5. BGK of each lattice, stores
   const unsigned long long vo = act ? im.lane_off(x, m, z, 1) : kDrop;
   const unsigned long long vo0 = act ? im.lane_off(x, m, z, 0) : kDrop;
-  auto collide = [&](const PopIO<L, S, BUF>& io, const T (&p)[Q], T rho, const T (&u)[3], T tau) {
+  // gas release at a domain gas point (Sec. 2.1.3), into the gas lattice
+  const long long nsrc = a.srcw ? a.ctl->n_src : 0;
+  const bool src = nsrc > 0 && ((a.srcw[(xc >> 6) + a.geo.nxb * row] >> (xc & 63)) & 1ull);
+  const T ds = src ? (T)(3.0 * (a.src_rate / (double)nsrc)) : T(0);
+  // (rres: the reservoir density of this lattice, for the populations that
+  // enter through an open plane; ds: the released density, gas lattice only)
+  auto collide = [&](const PopIO<L, S, BUF>& io, const T (&p)[Q], T rho, const T (&u)[3], T tau, double rres, T dsrc) {
     const T omega = T(1) / tau;
     const T base = T(1) - T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     T moving = T(0);
@@ -174,14 +193,19 @@ __global__ __launch_bounds__(TP_NT) void k_collide_tl(StepArgs a, TLArgs t) {
       const T odd = wr * (T(3) * eu);
       const T fp = even + odd, fq = even - odd;
       moving += fp + fq;
-      io.store_at(i, vo, p[i] - (p[i] - fp) * omega);
-      io.store_at(i + 1, vo, p[i + 1] - (p[i + 1] - fq) * omega);
+      T vp = p[i] - (p[i] - fp) * omega + (T)L::w[i] * dsrc;
+      T vq = p[i + 1] - (p[i + 1] - fq) * omega + (T)L::w[i] * dsrc;
+      // through an open plane: out of the container; the slot is refilled from the reservoir
+      if ((L::ez[i] > 0 && hi_open) || (L::ez[i] < 0 && lo_open)) vp = (T)(L::w[i] * rres);
+      if ((L::ez[i] > 0 && lo_open) || (L::ez[i] < 0 && hi_open)) vq = (T)(L::w[i] * rres);
+      io.store_at(i, vo, vp);
+      io.store_at(i + 1, vo, vq);
     }
     const T feq0 = rho - moving;
-    io.store_at(0, vo0, p[0] - (p[0] - feq0) * omega);
+    io.store_at(0, vo0, p[0] - (p[0] - feq0) * omega + (T)L::w[0] * dsrc);
   };
-  collide(im, f, rm, um, tm);
-  collide(ig, g, rgs, ug, tg);
+  collide(im, f, rm, um, tm, rm_res, T(0));
+  collide(ig, g, rgs, ug, tg, rg_res, ds);
   const double keep = act ? 1.0 : 0.0;
   step_partials<TP_NT>(a, blockIdx.x, red, keep * ((double)rm + (double)rgs), keep * ((double)jm[0] + (double)jg[0]),
                        keep * ((double)jm[L::HAS_M ? 1 : 2] + (double)jg[L::HAS_M ? 1 : 2]),
@@ -218,6 +242,14 @@ __global__ void k_tl_query(StepArgs a, TLArgs t, MapDims d, const double* mq, co
                                      wrap_any(z - L::ez[i], d.nz));
         double mp = psi_of(mq[yp], a.rho0), mm = psi_of(mq[ym], a.rho0);
         double gp = psi_of(gq[yp], a.rho0), gm = psi_of(gq[ym], a.rho0);
+        if (a.open_z && (z + L::ez[i] < 0 || z + L::ez[i] >= d.nz)) {  // the reservoir
+          mp = psi_of(a.rho_res, a.rho0);
+          gp = t.psi_bar_g;
+        }
+        if (a.open_z && (z - L::ez[i] < 0 || z - L::ez[i] >= d.nz)) {
+          mm = psi_of(a.rho_res, a.rho0);
+          gm = t.psi_bar_g;
+        }
         if (bar & (1u << i)) {
           mp = bm;
           gp = bg;

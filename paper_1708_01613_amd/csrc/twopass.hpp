@@ -120,11 +120,17 @@ __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
   const T psic = psi[c];
   const unsigned bar = (a.film_on && act) ? a.mask[c] & kLinkBits : 0u;  // exact active links
   const T pbar = a.psi_bar_mode == 0 ? (T)a.psi_bar : psic;
+  // an open container: the planes beyond z = 0 and z = nz - 1 hold the reservoir
+  const bool lo_open = a.open_z && z == 0, hi_open = a.open_z && z == nz - 1;
+  // (reservoir values rounded once from FP64)
+  const T pres = a.open_z ? (T)(a.rho0 * (1.0 - exp(-a.rho_res / a.rho0))) : T(0);
   T fx = T(0), fm = T(0), fz = T(0);
 #pragma unroll
   for (int i = 1; i < Q; i += 2) {
     T pp = psi[nb(L::ex[i], L::em[i], L::ez[i])];
     T pm = psi[nb(-L::ex[i], -L::em[i], -L::ez[i])];
+    if ((L::ez[i] > 0 && hi_open) || (L::ez[i] < 0 && lo_open)) pp = pres;
+    if ((L::ez[i] > 0 && lo_open) || (L::ez[i] < 0 && hi_open)) pm = pres;
     if (bar) {
       if (bar & (1u << i)) pp = pbar;
       if (bar & (1u << (i + 1))) pm = pbar;
@@ -181,8 +187,15 @@ __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
     }
     // the source terms are added on their own (zero when off: the fused
     // kernel's values exactly)
-    io.store_at(i, vo, add_rn(tau_one ? fp : f[i] - (f[i] - fp) * omega, se + so));
-    io.store_at(i + 1, vo, add_rn(tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega, se - so));
+    T vp = add_rn(tau_one ? fp : f[i] - (f[i] - fp) * omega, se + so);
+    T vq = add_rn(tau_one ? fq : f[i + 1] - (f[i + 1] - fq) * omega, se - so);
+    // a population that leaves through an open plane is gone; the slot it
+    // would take is the one the opposite plane pulls from, which receives the
+    // reservoir's population at rest instead
+    if ((L::ez[i] > 0 && hi_open) || (L::ez[i] < 0 && lo_open)) vp = (T)(L::w[i] * a.rho_res);
+    if ((L::ez[i] > 0 && lo_open) || (L::ez[i] < 0 && hi_open)) vq = (T)(L::w[i] * a.rho_res);
+    io.store_at(i, vo, vp);
+    io.store_at(i + 1, vo, vq);
   }
   const T feq0 = rho - feq_moving;
   T s0 = (T)L::w[0] * ds;

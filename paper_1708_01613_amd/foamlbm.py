@@ -48,6 +48,7 @@ class flb_params(C.Structure):
         ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double), ("g_rho_ref", C.c_double),
         ("model", C.c_int32), ("G_mg", C.c_double), ("G_gg", C.c_double), ("tau_g", C.c_double),
         ("rho_g_bubble", C.c_double), ("rho_g_liquid", C.c_double),
+        ("open_z", C.c_int32), ("rho_res", C.c_double),
     ]
 
 

@@ -74,7 +74,8 @@ def test_two_lattice_parity(flb, kind, storage, case):
     m, mom = o.stats()
     assert abs(st["mass"] - m) <= tol * m
     assert np.abs(st["mom"] - mom).max() <= tol * m
-    assert np.abs(g.pressure() - o.pressure()).max() <= tol * np.abs(o.pressure()).max()
+    # the pressure is a difference of terms of the size of the density
+    assert np.abs(g.pressure() - o.pressure()).max() <= tol * o.density().max()
     gm, om = g.maps(), o.maps()
     for key in ("label", "owner", "owner2", "dist"):
         assert np.array_equal(gm[key], om[key]), key
@@ -117,7 +118,7 @@ def test_two_lattice_populations_round_trip(flb, kind):
 
 def test_two_lattice_rejections(flb):
     base = dict(lattice=0, nx=16, ny=16, model=1)
-    for bad in (dict(storage="f16s"), dict(growth_on=1), dict(gx=1e-5), dict(tau_g=0.5), dict(rho_g_liquid=0.0)):
+    for bad in (dict(storage="f16s"), dict(gx=1e-5), dict(tau_g=0.5), dict(rho_g_liquid=0.0)):
         with pytest.raises(RuntimeError):
             flb.Sim(**dict(base, **bad))
     s = flb.Sim(lattice=0, nx=16, ny=16)
