@@ -104,3 +104,31 @@ def test_open_container_rejected_in_batches(flb):
     p, _, _ = _case(0, "f32", 0)
     with pytest.raises(RuntimeError):
         flb.Batch([p, p])
+
+
+def test_growth_in_container_ruptures_at_the_oracles_step(flb):
+    # the validation case of Sec. 5 in lattice units: two bubbles growing in
+    # a container open for the liquid reach the rupture criterion; FP64 on
+    # the GPU takes the first event at the oracle's step, with the same pair
+    nx, ny, R, gap = 128, 96, 10.0, 16.0
+    c = (nx - 1) / 2
+    p = dict(lattice=0, storage="f64", nx=nx, ny=ny, nz=1, tau=1.0, G=-5.0, rho_liquid=2.0, rho_gas=0.15,
+             noise_amp=0.0, model=1, G_mg=0.3, tau_g=1.0, rho_g_bubble=0.4, rho_g_liquid=0.05, growth_on=1,
+             gas_A=1.0, gas_dndt=0.1, open_z=1, rho_res=2.0, film_on=1, rupture_warmup=20, k_own=5, zone_width=6)
+    nuc = [[c - R - gap / 2 - 0.5, ny / 2, 0, R], [c + R + gap / 2 + 0.5, ny / 2, 0, R]]
+    print(f"\n[case] {p}", flush=True)
+    g = flb.Sim(**p)
+    g.set_nuclei(nuc)
+    o = oracle_for(p, nuc)
+    first = None
+    for _ in range(12):
+        g.step(50)
+        o.step(50)
+        oe = o.events()
+        if len(oe):
+            first = oe
+            break
+    assert first is not None and first[0][0] > 20
+    ge = g.rupture_events()
+    assert {tuple(r) for r in ge.tolist()} == {tuple(r) for r in first.tolist()}
+    assert max_rel(g.gas_density(), o.density_gas()) <= 1e-11
