@@ -143,7 +143,8 @@ int flb_create(const flb_params* p, const flb_allocator* alloc, void* hip_stream
   for (int b = 0; b < 2; b++) ok = ok && (c->f[b] = c->dalloc(c->fbytes));
   ok = ok && (c->ctl = (Ctl*)c->dalloc(sizeof(Ctl)));
   ok = ok && (c->qctl = (Ctl*)c->dalloc(sizeof(Ctl)));
-  ok = ok && (c->partials = (double*)c->dalloc(sizeof(double) * 4 * (size_t)c->max_blk));
+  // (and room after them for the folded partials of the two-pass decompositions)
+  ok = ok && (c->partials = (double*)c->dalloc(sizeof(double) * 4 * (size_t)(c->max_blk + c->max_blk / FOLD + 1)));
   {
     const size_t tsz = p->storage == FLB_F64 ? 8 : 4;
     ok = ok && (c->psi = c->dalloc(tsz * (size_t)c->N));

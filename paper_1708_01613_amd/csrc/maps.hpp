@@ -179,7 +179,7 @@ __device__ __forceinline__ bool map_due(const MapArgs& m) {
 }
 
 // decompositions of a map launch (workgroups per lattice)
-enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_BFST, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_BFSB, SH_FEW, SH_COUNT };
+enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_MASKT, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_BFSB, SH_FEW, SH_COUNT };
 
 #define MAP_KERNEL_PARAMS const MapArgs *__restrict__ tab, const int *__restrict__ first, int nmem
 #define MAP_MEMBER                                                           \
@@ -549,16 +549,24 @@ __device__ __forceinline__ int wrap_mod(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
+constexpr int BFS_NT = 256;
+
+// Tiles of the masks kernel (the same halo layout)
+#ifndef FLB_MK_TM
+#define FLB_MK_TM 4
+#endif
+#ifndef FLB_MK_TZ
+#define FLB_MK_TZ 4
+#endif
 template <class L>
-struct BfsTile {
-  static constexpr int TM = L::HAS_M ? 4 : 1;
-  static constexpr int TZ = L::HAS_M ? 4 : 16;
-  static constexpr int HM = L::HAS_M ? 1 : 0;  // halo along m (none on 2-D lattices)
+struct MaskTile {
+  static constexpr int TM = L::HAS_M ? FLB_MK_TM : 1;
+  static constexpr int TZ = L::HAS_M ? FLB_MK_TZ : 16;
+  static constexpr int HM = L::HAS_M ? 1 : 0;
   static constexpr int LX = 64 + 2, LM = TM + 2 * HM, LZ = TZ + 2;
   static constexpr int CELLS = 64 * TM * TZ;
   static constexpr int HALO = LX * LM * LZ;
 };
-constexpr int BFS_NT = 256;
 
 // The halo of a tile, row by row: halo row hr (LM x LZ of them) holds the
 // cells x0 - 1 .. x0 + 64 of lattice row (m0 - HM + hr % LM, z0 - 1 + hr / LM),
@@ -831,8 +839,10 @@ static __global__ __launch_bounds__(MAP_NT) void k_alias_compress(MAP_KERNEL_PAR
   FOR_SHARE(b, (long long)nb + 1) m.alias[b] = uf_find_live(m.alias, (int)b);
 }
 
-// Barrier masks over the BFS tiles: the workgroup stages, for its tile and a
-// one-cell halo, every cell's distance and, for owned cells, its owner pair.
+// Barrier masks over tiles of 64 x 4 x 4 cells (64 x 16 on D2Q9): the
+// workgroup stages, for its tile and a one-cell halo, every cell's distance
+// and owner pair, loaded together (larger tiles measured slower: their LDS
+// halves the workgroups a CU holds, and this kernel is bound by latency).
 // A link is a barrier iff both ends are owned, the film is thin enough
 // (dist + dist + 1 <= zone_width) and the alias-root pairs of the two owner
 // pairs differ; equal owner pairs have equal root pairs, so the aliases are
@@ -846,9 +856,10 @@ template <class L>
 __global__ __launch_bounds__(BFS_NT) void k_masks(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m)) return;
-  using T = BfsTile<L>;
+  using T = MaskTile<L>;
   using H = HaloRows<T>;
   constexpr int PER = T::CELLS / BFS_NT;
+  constexpr int CH = 5;  // halo rows per wavefront with loads in flight together
   __shared__ uint8_t ld[T::HALO];
   __shared__ int2 lo[T::HALO];
   const MapDims d = m.d;
@@ -859,70 +870,59 @@ __global__ __launch_bounds__(BFS_NT) void k_masks(MAP_KERNEL_PARAMS) {
   const int x0 = (b % ntx) * 64, m0 = ((b / ntx) % ntm) * T::TM, z0 = (b / (ntx * ntm)) * T::TZ;
   const int lane = threadIdx.x & 63;
   const int x = x0 + lane;
-  unsigned cidx[PER];
-  bool in[PER], rowin[PER];
-#pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int r = (int)(threadIdx.x >> 6) + k * (BFS_NT / 64);
-    const int mm_ = m0 + r % T::TM, z = z0 + r / T::TM;
-    rowin[k] = mm_ < d.nm && z < d.nz;
-    in[k] = rowin[k] && x < d.nx;
-    cidx[k] = in[k] ? (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z) : 0u;
-  }
-  // distances of the tile and its halo; a tile whose halo holds no owned
-  // cell has no barrier links and stages nothing more
   const H hr(d, x0);
-  unsigned ga[H::RPW], ge[H::RPW];
-  uint8_t da[H::RPW], de[H::RPW];
+  // 1. distances and owner pairs of the tile and its halo, loaded together
+  // (an unreached cell's owners are stale and never read)
   bool any = false;
+  for (int j0 = 0; j0 < H::RPW; j0 += CH) {
+    uint8_t da[CH], de[CH];
+    int2 oa[CH], oe[CH];
 #pragma unroll
-  for (int j = 0; j < H::RPW; j++) {
-    da[j] = de[j] = 255;
-    ga[j] = ge[j] = 0;
-    if (hr.row(j) < H::NR) {
-      const unsigned base = hr.base(d, m0, z0, hr.row(j));
-      ga[j] = base + (unsigned)hr.xa;
-      ge[j] = base + (unsigned)hr.xe;
-      da[j] = dist[ga[j]];
-      if (hr.lane < 2) de[j] = dist[ge[j]];
-    }
-    any |= da[j] != 255 || de[j] != 255;
-  }
-  const bool owned = __syncthreads_or(any);  // block-uniform
-  if (owned) {
-    int2 oa[H::RPW], oe[H::RPW];
-#pragma unroll
-    for (int j = 0; j < H::RPW; j++) {  // the owners of owned cells
-      oa[j] = oe[j] = make_int2(0, 0);
-      if (da[j] != 255) oa[j] = ld_pair(m.own, ga[j]);
-      if (de[j] != 255) oe[j] = ld_pair(m.own, ge[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < H::RPW; j++) {
-      if (hr.row(j) >= H::NR) continue;
-      const int at = hr.row(j) * T::LX;
-      ld[at + 1 + hr.lane] = da[j];
-      lo[at + 1 + hr.lane] = oa[j];
-      if (hr.lane < 2) {
-        const int e = at + (hr.lane == 0 ? 0 : T::LX - 1);
-        ld[e] = de[j];
-        lo[e] = oe[j];
+    for (int u = 0; u < CH; u++) {
+      const int j = j0 + u;
+      da[u] = de[u] = 255;
+      oa[u] = oe[u] = make_int2(0, 0);
+      if (j < H::RPW && hr.row(j) < H::NR) {
+        const unsigned base = hr.base(d, m0, z0, hr.row(j));
+        da[u] = dist[base + (unsigned)hr.xa];
+        oa[u] = ld_pair(m.own, base + (unsigned)hr.xa);
+        if (hr.lane < 2) {
+          de[u] = dist[base + (unsigned)hr.xe];
+          oe[u] = ld_pair(m.own, base + (unsigned)hr.xe);
+        }
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < CH; u++) {
+      const int j = j0 + u;
+      if (j >= H::RPW || hr.row(j) >= H::NR) continue;  // wave-uniform
+      const int at = hr.row(j) * T::LX;
+      ld[at + 1 + hr.lane] = da[u];
+      lo[at + 1 + hr.lane] = oa[u];
+      if (hr.lane < 2) {
+        ld[at + (hr.lane == 0 ? 0 : T::LX - 1)] = de[u];
+        lo[at + (hr.lane == 0 ? 0 : T::LX - 1)] = oe[u];
+      }
+      any |= da[u] != 255 || de[u] != 255;
+    }
   }
+  const bool owned = __syncthreads_or(any);  // block-uniform: the staging is complete
+  // 2. the links of the tile's cells
   const int nxs = (d.nx + 63) >> 6;
   const FLB_AS_GLOBAL int* alias = as_global((const int*)m.alias);
   auto root_pair = [&](int2 o) {
     const int ra = alias[o.x], rb = alias[o.y];
     return make_int2(min(ra, rb), max(ra, rb));
   };
-#pragma unroll
   for (int k = 0; k < PER; k++) {
     const int r = (int)(threadIdx.x >> 6) + k * (BFS_NT / 64);
     const int lm = r % T::TM, lz = r / T::TM;
+    const int mm_ = m0 + lm, z = z0 + lz;
+    const bool rowin = mm_ < d.nm && z < d.nz;  // wave-uniform
+    const bool in = rowin && x < d.nx;
+    const unsigned cidx = in ? (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z) : 0u;
     unsigned mk = 0;
-    if (owned && in[k]) {
+    if (owned && in) {
       const int lc = (lane + 1) + T::LX * ((lm + T::HM) + T::LM * (lz + 1));
       const int dc = ld[lc];
       if (dc != 255) {
@@ -948,13 +948,13 @@ __global__ __launch_bounds__(BFS_NT) void k_masks(MAP_KERNEL_PARAMS) {
         }
       }
     }
-    if (in[k]) {
-      as_global(m.flag)[cidx[k]] = mk ? 1 : 0;
-      as_global(m.mask)[cidx[k]] = mk;
+    if (in) {
+      as_global(m.flag)[cidx] = mk ? 1 : 0;
+      as_global(m.mask)[cidx] = mk;
     }
     const unsigned long long bal = __ballot(mk != 0);
-    if (rowin[k] && lane == 0) {
-      const unsigned row = (unsigned)(m0 + lm) + (unsigned)d.nm * (unsigned)(z0 + lz);
+    if (rowin && lane == 0) {
+      const unsigned row = (unsigned)mm_ + (unsigned)d.nm * (unsigned)z;
       as_global(m.fwords)[(unsigned)(x0 >> 6) + (unsigned)nxs * row] = bal;
     }
   }
@@ -1097,7 +1097,7 @@ __host__ inline int map_share(int shape, const MapDims& d) {
     case SH_CELLS: g = std::min<long long>((N + 1 + MAP_NT - 1) / MAP_NT, 4096); break;
     case SH_SEG: g = std::min<long long>((nseg + MAP_WAVES - 1) / MAP_WAVES, 16384); break;
     case SH_CCT: g = cc_tiles(d, CCTile<L>::TM, CCTile<L>::TZ); break;
-    case SH_BFST: g = cc_tiles(d, BfsTile<L>::TM, BfsTile<L>::TZ); break;
+    case SH_MASKT: g = cc_tiles(d, MaskTile<L>::TM, MaskTile<L>::TZ); break;
     case SH_RANK: g = (N + RANK_BLOCK - 1) / RANK_BLOCK; break;
     case SH_ONE: g = 1; break;
     // passes over per-bubble tables (as long as the bubble count, which only

@@ -137,7 +137,7 @@ inline size_t ctx_footprint(const flb_params* p) {
   // partials: every tile variant at one plane per segment has at most one
   // workgroup per 64-cell row segment
   const size_t max_blk = nxb * (size_t)nm * nz;
-  size_t t = 2 * r(fbytes) + 2 * r(sizeof(Ctl)) + r(32 * max_blk) + 2 * r(tsz * N) + r(32 * N) + r(32 * 4096) +
+  size_t t = 2 * r(fbytes) + 2 * r(sizeof(Ctl)) + r(32 * (max_blk + max_blk / FOLD + 1)) + 2 * r(tsz * N) + r(32 * N) + r(32 * 4096) +
              2 * r(4 * N) + r(4 * (N / 1024 + 2)) + r(4 * N) + r(8 * (N + 1));
   const size_t nwords = nxb * nm * nz;
   if (p->film_on)
@@ -488,7 +488,7 @@ inline MapArgs map_args(flb_ctx* c, bool query, int src) {
 // owners, distances and aliases in place.
 template <class L>
 int map_masks(const MapSet& s, hipStream_t st) {
-  MAPL((k_masks<L>), SH_BFST, BFS_NT);
+  MAPL((k_masks<L>), SH_MASKT, BFS_NT);
   MAPL(k_flag_count, SH_FW, FW_BLOCK);
   MAPL(k_scan_counts, SH_ONE, 1024, 1);
   MAPL(k_flag_write, SH_FW, FW_BLOCK);
@@ -649,7 +649,16 @@ int do_steps(flb_ctx* c, int64_t nsteps, bool refresh, hipEvent_t* ev = nullptr)
       hipLaunchKernelGGL((k_mask_prune<L>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, prune_args(c));
     }
     if (e) HIPCHK(hipEventRecord(e[3], c->st));
-    hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(FIN_NT), 0, c->st, a, nblk);
+    if (c->two_pass() && nblk > 8 * FIN_NT && nblk + (nblk + FOLD - 1) / FOLD <= c->max_blk + c->max_blk / FOLD + 1) {
+      // fold the many partials of the two-pass decomposition first
+      const int nf = (nblk + FOLD - 1) / FOLD;
+      hipLaunchKernelGGL(k_fold_partials, dim3(nf), dim3(64), 0, c->st, a.partials, nblk);
+      StepArgs af = a;
+      af.partials = a.partials + 4ll * nblk;
+      hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(FIN_NT), 0, c->st, af, nf);
+    } else {
+      hipLaunchKernelGGL(k_step_finish, dim3(1), dim3(FIN_NT), 0, c->st, a, nblk);
+    }
     if (e) HIPCHK(hipEventRecord(e[4], c->st));
     c->launched++;
   }

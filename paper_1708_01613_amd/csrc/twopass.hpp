@@ -208,4 +208,27 @@ __global__ __launch_bounds__(TP_NT) void k_collide(StepArgs a) {
                        keep * (double)(L::HAS_M ? jz : T(0)));
 }
 
+// The two-pass decompositions leave one partial per 256 cells (65536 at
+// 256^3), more than the one-workgroup finisher reads quickly: groups of
+// FOLD consecutive partials are summed, in order, into the slots after the
+// last one, and the finisher reads those (a fixed order, so the totals stay
+// deterministic).
+constexpr int FOLD = 64;
+static __global__ __launch_bounds__(64) void k_fold_partials(double* partials, int nblk) {
+  const int g = blockIdx.x, q = threadIdx.x & 3, r = threadIdx.x >> 2;  // 16 rows x 4 quantities
+  double t = 0.0;
+  for (int k = r; k < FOLD; k += 16) {
+    const int blk = g * FOLD + k;
+    if (blk < nblk) t += partials[4ll * blk + q];
+  }
+  __shared__ double s[16][4];
+  s[r][q] = t;
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double u = 0.0;
+    for (int k = 0; k < 16; k++) u += s[k][threadIdx.x];
+    partials[4ll * (nblk + g) + threadIdx.x] = u;
+  }
+}
+
 }  // namespace flb
