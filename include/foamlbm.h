@@ -407,6 +407,19 @@ int flb_batch_step(flb_batch* batch, int64_t nsteps);
 int flb_batch_set_tuning(flb_batch* batch, int32_t tile, int64_t target, int32_t xcd, int32_t graph_steps);
 int flb_batch_get_tuning(flb_batch* batch, int32_t* tile, int64_t* target, int32_t* xcd, int32_t* graph_steps,
                          int32_t* n_tiles);
+/* Persistent runs (D2Q9 batches only; EINVAL for D3Q19).  With on = 1 each
+ * stretch of steps between film-map refreshes, of at most max_steps steps
+ * (0 keeps; default 1024), is one cooperative launch whose workgroups, as
+ * many as are resident at once, take the step tiles of all members in turn,
+ * then the rupture test, the mask pruning and the finisher of every member,
+ * with a grid-wide barrier between those phases of each step; the refreshes
+ * stay launches of their own before the stretch.  The batch then uses the
+ * 256 x 1 tile (flb_batch_set_tuning rejects another).  Populations, maps
+ * and events equal those of the per-step launches bit for bit; the FP64
+ * mass and momentum totals are summed in another order (equal to rounding).
+ * on = 0 returns to per-step launches and graph replay.  Fails with EINVAL
+ * when the device has no cooperative launches (at the next step). */
+int flb_batch_set_persistent(flb_batch* batch, int32_t on, int32_t max_steps);
 /* Autotuner: times `reps` launches of the batched step kernel for every tile
  * variant, workgroup target and XCD setting without changing any member
  * (each trial writes a scratch buffer under a copy of the run control),

@@ -91,11 +91,27 @@ int flb_batch_set_tuning(flb_batch* b, int32_t tile, int64_t target, int32_t xcd
   if (target < 0) return fail(FLB_EINVAL, "target must be >= 0");
   if (xcd < -1 || xcd > 64) return fail(FLB_EINVAL, "xcd must be in -1..64");
   if (graph_steps < -1 || graph_steps > 4096) return fail(FLB_EINVAL, "graph_steps must be in -1..4096");
+  if (b->persist && tile >= 0 && tile != flb_batch::kPersistTile)
+    return fail(FLB_EINVAL, "persistent runs take tile %d", flb_batch::kPersistTile);
   HIPCHK(hipStreamSynchronize(b->st));
   if (tile >= 0) b->tile = tile;
   if (target > 0) b->target = target;
   if (xcd >= 0) b->xcd = xcd;
   if (graph_steps >= 0) b->graph_steps = graph_steps;
+  b->dirty = true;
+  b->drop_graph();
+  return FLB_OK;
+}
+
+int flb_batch_set_persistent(flb_batch* b, int32_t on, int32_t max_steps) {
+  if (!b) return fail(FLB_EINVAL, "batch is NULL");
+  if (on != 0 && on != 1) return fail(FLB_EINVAL, "on must be 0 or 1");
+  if (max_steps < 0 || max_steps > 1000000) return fail(FLB_EINVAL, "max_steps must be in 0..1000000");
+  if (on && b->D != 2) return fail(FLB_EINVAL, "persistent runs are for D2Q9 batches");
+  HIPCHK(hipStreamSynchronize(b->st));
+  b->persist = on != 0;
+  if (max_steps > 0) b->persist_max = max_steps;
+  if (b->persist) b->tile = flb_batch::kPersistTile;
   b->dirty = true;
   b->drop_graph();
   return FLB_OK;
@@ -138,7 +154,9 @@ int flb_batch_autotune(flb_batch* b, int32_t reps, double* best_ms) {
   float best = 1e30f;
   int bt = b->tile, bx = b->xcd;
   long long bg = b->target;
-  for (int t = 0; t < b->n_tiles() && !rc; t++)
+  // persistent runs keep their tile and tune the rest
+  for (int t = 0; t < b->n_tiles() && !rc; t++) {
+    if (b->persist && t != flb_batch::kPersistTile) continue;
     for (long long tg : targets)
       for (int xc : xcds) {
         if (rc) break;
@@ -154,6 +172,7 @@ int flb_batch_autotune(flb_batch* b, int32_t reps, double* best_ms) {
           bx = xc;
         }
       }
+  }
   (void)hipStreamSynchronize(b->st);
   b->dfree(base);
   b->tile = bt;

@@ -8,8 +8,11 @@
 // and a batched mask-pruning launch; film-map refreshes stay per member.  So
 // the launch count per step does not grow with the number of lattices, and the
 // GPU is filled by all members at once instead of one small lattice at a time.
-// Runs of steps are captured in a HIP graph and replayed.
+// Runs of steps are captured in a HIP graph and replayed.  D2Q9 batches may
+// instead run each stretch of steps between refreshes as one persistent
+// cooperative launch (persist.hpp).
 #pragma once
+#include "persist.hpp"
 #include "runtime.hpp"
 
 namespace flb_rt {
@@ -86,6 +89,11 @@ struct flb_batch {
   flb_rt::Fork fork;   // side stream of the refresh
   bool dirty = true;
   bool ext = false;  // some member has a source term (gas release, body force)
+  // persistent launches (D2Q9): the batch tile of 256 x 1 cells, runs of at
+  // most persist_max steps per launch, workgroups sized to occupancy
+  bool persist = false;
+  int persist_max = 1024;
+  int pgrid = 0;
   // graphs
   int graph_steps = 16;
   hipGraphExec_t gexec = nullptr;
@@ -114,6 +122,7 @@ struct flb_batch {
     gkey.clear();
   }
   int n_tiles() const { return D == 2 ? flb_rt::kNBatch2 : flb_rt::kNBatch3; }
+  static constexpr int kPersistTile = 2;  // kBatch2's 256 x 1 tile
   flb_rt::BatchStepFn step_fn() const { return (D == 2 ? flb_rt::kBatch2 : flb_rt::kBatch3)[tile][storage]; }
 };
 
@@ -238,12 +247,83 @@ inline long long graph_period(const flb_batch* b) {
   return per;
 }
 
+// ---- persistent runs (D2Q9) ----
+template <class S, bool BUF, bool EXT>
+inline const void* persist_fn() {
+  return (const void*)&k_batch_persist<S, BUF, EXT>;
+}
+template <class S>
+inline const void* persist_kernel(const flb_batch* b) {
+  return b->buf ? (b->ext ? persist_fn<S, true, true>() : persist_fn<S, true, false>())
+                : (b->ext ? persist_fn<S, false, true>() : persist_fn<S, false, false>());
+}
+
+// workgroups of the persistent launch: as many as are resident at once (a
+// cooperative launch needs all of them resident), and no more than the
+// largest phase has work for
+template <class S>
+int persist_grid(flb_batch* b) {
+  int dev = 0, cus = 0, coop = 0, per = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (!coop) return fail(FLB_EINVAL, "the device has no cooperative launches");
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persist_kernel<S>(b), PERSIST_TX, 0));
+  if (per < 1) return fail(FLB_EHIP, "the persistent kernel fits no workgroup on a compute unit");
+  const int work = std::max(std::max(b->nblk, b->fblk), (int)b->m.size());
+  b->pgrid = std::max(1, std::min(per * cus, work));
+  return FLB_OK;
+}
+
+// steps until some film member is due for a refresh (each is due before the
+// step whose index is a multiple of its k_own), at most `left`
+inline int64_t steps_to_refresh(const flb_batch* b, int64_t left) {
+  int64_t r = left;
+  for (int k : b->film) {
+    const flb_ctx* c = b->m[k];
+    r = std::min<int64_t>(r, c->p.k_own - c->launched % c->p.k_own);
+  }
+  return r;
+}
+
+template <class S>
+int persist_steps(flb_batch* b, int64_t nsteps) {
+  if (b->tile != flb_batch::kPersistTile) return fail(FLB_EINVAL, "persistent runs take the 256 x 1 batch tile");
+  int rc = persist_grid<S>(b);
+  if (rc) return rc;
+  const void* fn = persist_kernel<S>(b);
+  const StepArgs* tab = b->tab;
+  const int* first = b->first;
+  int nmem = (int)b->m.size();
+  const StepArgs* ftab = b->ftab;
+  const PruneArgs* ptab = b->ptab;
+  const int* ffirst = b->ffirst;
+  int nf = (int)b->film.size();
+  for (int64_t done = 0; done < nsteps;) {
+    bool due = false;
+    for (int k : b->film) due = due || b->m[k]->launched % b->m[k]->p.k_own == 0;
+    if (due) {
+      rc = b->fork.init();
+      if (!rc) rc = map_pipeline<D2Q9K, S>(b->fms, b->st, GAS_AUTO, true, &b->fork);
+      if (rc) return rc;
+    }
+    int run = (int)steps_to_refresh(b, std::min<int64_t>(nsteps - done, b->persist_max));
+    void* args[] = {&tab, &first, &nmem, &ftab, &ptab, &ffirst, &nf, &run};
+    HIPCHK(hipLaunchCooperativeKernel(fn, dim3(b->pgrid), dim3(PERSIST_TX), args, 0, b->st));
+    for (flb_ctx* c : b->m) c->launched += run;
+    done += run;
+  }
+  return FLB_OK;
+}
+
 template <class L, class S>
 int batch_steps(flb_batch* b, int64_t nsteps) {
   if (b->dirty) {
     int rc = rebuild(b);
     if (rc) return rc;
   }
+  if constexpr (std::is_same_v<L, D2Q9K>)
+    if (b->persist) return persist_steps<S>(b, nsteps);
   int64_t done = 0;
   // graphs need a capturable (non-null) stream
   const long long per = (b->graph_steps > 0 && b->st) ? graph_period(b) : 0;

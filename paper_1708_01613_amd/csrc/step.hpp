@@ -326,22 +326,23 @@ __device__ __forceinline__ void step_partials(const StepArgs& a, int slot, doubl
 // order (deterministic), the non-finite check, the stop flag, and the step
 // counter that selects the A/B buffer.
 constexpr int FIN_NT = 1024;
-__device__ __forceinline__ void step_finish(const StepArgs& a, int nblk, double (&red)[FIN_NT / 64][4]) {
+template <int NT = FIN_NT>
+__device__ __forceinline__ void step_finish(const StepArgs& a, int nblk, double (&red)[NT / 64][4]) {
   Ctl* ctl = a.ctl;
   if (ctl->stopped) return;
   double t[4] = {0.0, 0.0, 0.0, 0.0};
-  // thread t adds workgroups t, t + FIN_NT, ... in that order; four rows are
+  // thread t adds workgroups t, t + NT, ... in that order; four rows are
   // loaded ahead of their additions to keep loads in flight
   const double4* part = (const double4*)a.partials;
   int blk = threadIdx.x;
-  for (; blk + 3 * FIN_NT < nblk; blk += 4 * FIN_NT) {
-    const double4 v0 = part[blk], v1 = part[blk + FIN_NT], v2 = part[blk + 2 * FIN_NT], v3 = part[blk + 3 * FIN_NT];
+  for (; blk + 3 * NT < nblk; blk += 4 * NT) {
+    const double4 v0 = part[blk], v1 = part[blk + NT], v2 = part[blk + 2 * NT], v3 = part[blk + 3 * NT];
     t[0] += v0.x; t[1] += v0.y; t[2] += v0.z; t[3] += v0.w;
     t[0] += v1.x; t[1] += v1.y; t[2] += v1.z; t[3] += v1.w;
     t[0] += v2.x; t[1] += v2.y; t[2] += v2.z; t[3] += v2.w;
     t[0] += v3.x; t[1] += v3.y; t[2] += v3.z; t[3] += v3.w;
   }
-  for (; blk < nblk; blk += FIN_NT) {
+  for (; blk < nblk; blk += NT) {
     const double4 v = part[blk];
     t[0] += v.x; t[1] += v.y; t[2] += v.z; t[3] += v.w;
   }
@@ -356,7 +357,7 @@ __device__ __forceinline__ void step_finish(const StepArgs& a, int nblk, double 
   __syncthreads();
   if (threadIdx.x == 0) {
     double tot[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int wv = 0; wv < FIN_NT / 64; wv++)
+    for (int wv = 0; wv < NT / 64; wv++)
       for (int q = 0; q < 4; q++) tot[q] += red[wv][q];
     ctl->mass = tot[0];
     ctl->mom[0] = tot[1];
@@ -378,7 +379,7 @@ __device__ __forceinline__ void step_finish(const StepArgs& a, int nblk, double 
 
 static __global__ __launch_bounds__(FIN_NT) void k_step_finish(StepArgs a, int nblk) {
   __shared__ double red[FIN_NT / 64][4];
-  step_finish(a, nblk, red);
+  step_finish<FIN_NT>(a, nblk, red);
 }
 
 // ---- batched launches: many lattices of one lattice type and storage ----
@@ -400,7 +401,7 @@ static __global__ __launch_bounds__(FIN_NT) void k_step_finish_batch(const StepA
   __shared__ double red[FIN_NT / 64][4];
   const int k = blockIdx.x;
   const StepArgs& a = tab[k];  // read in place: a local copy would live in scratch
-  step_finish(a, first[k + 1] - first[k], red);
+  step_finish<FIN_NT>(a, first[k + 1] - first[k], red);
 }
 
 // Plane loop: iteration k loads plane z0-1+k (k <= L+1) into one register

@@ -150,6 +150,7 @@ _SIGS = {
     "flb_batch_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "flb_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
+    "flb_batch_set_persistent": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "flb_batch_time_steps": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_double)]),
     "flb_batch_destroy": (None, [C.c_void_p]),
     "flb_server_default_config": (None, [C.POINTER(flb_server_config)]),
@@ -495,6 +496,9 @@ class Batch:
 
     def set_tuning(self, tile=-1, target=0, xcd=-1, graph_steps=-1):
         check(flb_batch_set_tuning(self.h, tile, target, xcd, graph_steps), "flb_batch_set_tuning")
+
+    def set_persistent(self, on=True, max_steps=0):
+        check(flb_batch_set_persistent(self.h, 1 if on else 0, int(max_steps)), "flb_batch_set_persistent")
 
     def tuning(self):
         t, x, g, nt = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()

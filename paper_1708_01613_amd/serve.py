@@ -30,8 +30,10 @@ def ensemble(members, steps, mode="batched", autotune=True, log=None):
     import torch
 
     total = sum(_cells(p) for p, _ in members) * steps
-    if mode == "batched":
+    if mode in ("batched", "persistent"):
         b = foamlbm.Batch([p for p, _ in members])
+        if mode == "persistent":
+            b.set_persistent(True)
         for k, (_, nuc) in enumerate(members):
             b.members[k].set_nuclei(nuc)
         b.synchronize()
