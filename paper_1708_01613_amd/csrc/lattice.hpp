@@ -86,6 +86,18 @@ struct SF16S {
   __host__ __device__ static constexpr unsigned pofs(int i) { return i == 0 ? 0u : 256u + 128u * (i - 1); }
 };
 
+// FP16-shifted element <-> compute value (wh = w_i href).  The sum and the
+// difference round on their own (never fused with the product that formed
+// wh), so every kernel decodes and encodes a population to the same bits.
+__device__ __forceinline__ float h16_dec(unsigned short bits, float wh) {
+#pragma clang fp contract(off)
+  return (float)__builtin_bit_cast(_Float16, bits) + wh;
+}
+__device__ __forceinline__ unsigned short h16_enc(float v, float wh) {
+#pragma clang fp contract(off)
+  return __builtin_bit_cast(unsigned short, (_Float16)(v - wh));
+}
+
 template <class S>
 __host__ __device__ constexpr unsigned block_bytes(int Q) {
   return S::pofs(Q - 1) + kBlk * S::esz(Q - 1);
@@ -101,14 +113,14 @@ template <class L, class S>
 __device__ inline typename S::ct pop_ld(const void* base, const Geo& g, int i, int x, int m, int z) {
   const char* p = (const char*)base + block_of(g, x, m, z) + S::pofs(i) + (unsigned)(x & 63) * S::esz(i);
   if constexpr (sizeof(typename S::ct) == 8) return *(const double*)p;
-  else if (S::HALF && i > 0) return (float)*(const _Float16*)p + (float)L::w[i] * g.href;
+  else if (S::HALF && i > 0) return h16_dec(*(const unsigned short*)p, (float)L::w[i] * g.href);
   else return *(const float*)p;
 }
 template <class L, class S>
 __device__ inline void pop_st(void* base, const Geo& g, int i, int x, int m, int z, typename S::ct v) {
   char* p = (char*)base + block_of(g, x, m, z) + S::pofs(i) + (unsigned)(x & 63) * S::esz(i);
   if constexpr (sizeof(typename S::ct) == 8) *(double*)p = v;
-  else if (S::HALF && i > 0) *(_Float16*)p = (_Float16)(v - (float)L::w[i] * g.href);
+  else if (S::HALF && i > 0) *(unsigned short*)p = h16_enc(v, (float)L::w[i] * g.href);
   else *(float*)p = v;
 }
 

@@ -253,10 +253,7 @@ struct PopIO {
       }
       return *(const double*)(gs + off + po);
     } else if (S::HALF && i > 0) {
-      _Float16 h;
-      if (BUF) h = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, vo, po, kLdCpol));
-      else h = *(const _Float16*)(gs + off + po);
-      return (float)h + (float)L::w[i] * g.href;
+      return decode(i, load_raw(i, off));
     } else {
       if (BUF) return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, po, kLdCpol));
       return *(const float*)(gs + off + po);
@@ -275,9 +272,9 @@ struct PopIO {
         *(double*)(gd + off + po) = v;
       }
     } else if (S::HALF && i > 0) {
-      const _Float16 h = (_Float16)(v - (float)L::w[i] * g.href);
-      if (BUF) __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), rd, vo, po, kStCpol);
-      else *(_Float16*)(gd + off + po) = h;
+      const unsigned short h = h16_enc(v, (float)L::w[i] * g.href);
+      if (BUF) __builtin_amdgcn_raw_buffer_store_b16(h, rd, vo, po, kStCpol);
+      else *(unsigned short*)(gd + off + po) = h;
     } else {
       if (BUF) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rd, vo, po, kStCpol);
       else *(float*)(gd + off + po) = v;
@@ -291,6 +288,41 @@ struct PopIO {
 #pragma unroll
     for (int i = 0; i < L::Q; i++)
       out[i] = load_at(i, lane_off(xs[1 + L::ex[i]], ms[1 + L::em[i]], zs[1 + L::ez[i]], i));
+  }
+
+  // ---- raw loads: FP16 elements stay undecoded (their 16 bits in the low
+  // half of the register) until decode() after the loads have landed.  A
+  // conversion right after the load would make the wavefront wait for every
+  // load of the plane before the collide that the loads should overlap.
+  __device__ __forceinline__ T load_raw(int i, unsigned long long off) const {
+    if constexpr (S::HALF) {
+      if (i > 0) {
+        const unsigned po = S::pofs(i);
+        unsigned short h;
+        if (BUF) h = __builtin_amdgcn_raw_buffer_load_b16(rs, (unsigned)off, po, kLdCpol);
+        else h = *(const unsigned short*)(gs + off + po);
+        return __builtin_bit_cast(float, (unsigned)h);
+      }
+    }
+    return load_at(i, off);
+  }
+  __device__ __forceinline__ T decode(int i, T raw) const {
+    if constexpr (S::HALF) {
+      if (i > 0) return h16_dec((unsigned short)__builtin_bit_cast(unsigned, raw), (float)L::w[i] * g.href);
+    }
+    return raw;
+  }
+  __device__ __forceinline__ void pull_raw(int x, int m, int z, T (&out)[L::Q]) const {
+    const int xs[3] = {wrap_inc(x, g.nx), x, wrap_dec(x, g.nx)};
+    const int ms[3] = {L::HAS_M ? wrap_inc(m, g.nm) : 0, m, L::HAS_M ? wrap_dec(m, g.nm) : 0};
+    const int zs[3] = {wrap_inc(z, g.nz), z, wrap_dec(z, g.nz)};
+#pragma unroll
+    for (int i = 0; i < L::Q; i++)
+      out[i] = load_raw(i, lane_off(xs[1 + L::ex[i]], ms[1 + L::em[i]], zs[1 + L::ez[i]], i));
+  }
+  __device__ __forceinline__ void decode_all(T (&r)[L::Q]) const {
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) r[i] = decode(i, r[i]);
   }
 };
 
@@ -459,8 +491,8 @@ struct StepBlock {
       // and branch cost more than the 3 bytes they save)
       const int zl = wrap_any(z0 - 1 + k, nz);
       if (film) fl_ld = a.mask[(unsigned)(xc + nx * (mc + nm * zl))];
-      io.pull(xc, mc, zl, ld);
-      if (HIN && has_halo) io.pull(gx, gm, zl, hv);
+      io.pull_raw(xc, mc, zl, ld);
+      if (HIN && has_halo) io.pull_raw(gx, gm, zl, hv);
     }
     // keep the collide between the loads and their first use
     __builtin_amdgcn_sched_barrier(0);
@@ -474,6 +506,8 @@ struct StepBlock {
       // the sum runs on every lane (so the wait for the loads is on every
       // path); only lanes inside the lattice publish it
       const int slot = k & 3;
+      io.decode_all(ld);
+      if (HIN && has_halo) io.decode_all(hv);
       T r = T(0);
 #pragma unroll
       for (int i = 0; i < Q; i++) r += ld[i];
