@@ -105,6 +105,38 @@ def test_foam3d_256_f64_ruptures_from_step_0(flb):
     _same_maps(flb, 1, g.maps(), o.maps())
 
 
+@pytest.mark.parametrize("storage,dims", [("f32", (320, 320, 280)), ("f64", (256, 256, 224))])
+def test_population_buffers_above_2_gib(flb, storage, dims):
+    # a population buffer of 2 GiB or more leaves the step kernel's 32-bit
+    # buffer offsets for 64-bit global addresses; the foam against the oracle
+    # over whole fields, with two refreshes, and in FP64 the rupture test
+    # from step 0
+    nx, ny, nz = dims
+    esz = 8 if storage == "f64" else 4
+    assert 19 * esz * nx * ny * nz >= 2 ** 31
+    f64 = storage == "f64"
+    params, _ = _foam3d(storage, nx=nx, ny=ny, nz=nz, k_own=2, rupture_warmup=0 if f64 else 10 ** 6)
+    rng = np.random.default_rng(21)
+    nuc = [[float(rng.uniform(0, nx)), float(rng.uniform(0, ny)), float(rng.uniform(0, nz)), float(rng.uniform(4, 8))]
+           for _ in range(600)]
+    _say(f"D3Q19 {nx}x{ny}x{nz} {storage} ({19 * esz * nx * ny * nz / 2 ** 30:.2f} GiB of populations), 3 steps")
+    g = flb.Sim(**params)
+    g.set_nuclei(nuc)
+    o = oracle_for(params, nuc)
+    g.step(3)
+    o.step(3)
+    tol = 1e-12 if f64 else 1e-5
+    assert max_rel(g.density(), o.density()) <= tol
+    assert vel_err(g.velocity(), o.velocity()) <= tol
+    _same_maps(flb, 1, g.maps(), o.maps())
+    if f64:
+        st = g.stats()
+        assert o.n_ruptures > 0 and st["n_ruptures"] == o.n_ruptures
+        ge = {tuple(r) for r in g.rupture_events().tolist()}
+        oe = {tuple(r) for r in o.events().tolist()}
+        assert ge == oe if not st["events_lost"] else ge <= oe
+
+
 def test_foam3d_256_f16s(flb):
     params, nuc = _foam3d("f16s")
     _say("D3Q19 256^3 f16s, 10 steps")
