@@ -318,7 +318,12 @@ int flb_get_rupture_events(flb_ctx* ctx, int64_t* out, int64_t cap, int64_t* n);
 /* Tuning of the fused step kernel: tile variant index (0..n_tiles-1, -1 keeps
  * the current one), planes per workgroup segment lz >= 1 (0 keeps), and
  * xcd > 1 to place spatially adjacent tiles on one XCD (0 or 1: off; -1
- * keeps).  Results do not depend on the tuning. */
+ * keeps).  Results do not depend on the tuning.  Variants, in index order:
+ * D2Q9 z-march tiles 64, 128 and 256 cells wide, flat tiles of 64 cells x 8
+ * and x 16 rows (their segment is their height; lz is kept but unused), the
+ * two-pass path; D3Q19 z-march tiles 64x4, 64x8, 32x8, 128x4, the two-pass
+ * path.  tile_x / tile_m report the tile's cells along x and m (0 for the
+ * two-pass path). */
 int flb_set_tuning(flb_ctx* ctx, int32_t tile, int32_t lz, int32_t xcd);
 int flb_get_tuning(flb_ctx* ctx, int32_t* tile, int32_t* lz, int32_t* xcd, int32_t* n_tiles,
                    int32_t* tile_x, int32_t* tile_m);
@@ -399,7 +404,7 @@ int flb_batch_size(flb_batch* batch, int32_t* count);
 int flb_batch_member(flb_batch* batch, int32_t k, flb_ctx** out);
 /* Advances every member by nsteps steps (asynchronous, like flb_step). */
 int flb_batch_step(flb_batch* batch, int64_t nsteps);
-/* Batch tuning: z-march tile variant shared by the members (-1 keeps; the
+/* Batch tuning: z-march or flat tile variant shared by the members (-1 keeps; the
  * two-pass variant has no batched form), the total workgroup target of a step
  * launch that sets each member's segment length in proportion to its cells
  * (0 keeps), the XCD remap (-1 keeps) and the steps per captured graph

@@ -21,31 +21,33 @@ namespace flb_rt {
 // members without them skip them inside that variant)
 using BatchStepFn = void (*)(const StepArgs*, const int*, int, int, bool, bool, hipStream_t);
 
-template <class L, class S, int TX, int TM, bool EXT>
+template <class L, class S, int TX, int TM, bool EXT, int FR>
 void launch_step_batch_g(const StepArgs* tab, const int* first, int nmem, int nblk, bool buf, hipStream_t s) {
   if (buf)
-    hipLaunchKernelGGL((k_step_batch<L, S, TX, TM, true, EXT>), dim3(nblk),
-                       dim3(StepBlock<L, S, TX, TM, true, EXT>::NT), 0, s, tab, first, nmem);
+    hipLaunchKernelGGL((k_step_batch<L, S, TX, TM, true, EXT, FR>), dim3(nblk),
+                       dim3(StepBlock<L, S, TX, TM, true, EXT, FR>::NT), 0, s, tab, first, nmem);
   else
-    hipLaunchKernelGGL((k_step_batch<L, S, TX, TM, false, EXT>), dim3(nblk),
-                       dim3(StepBlock<L, S, TX, TM, false, EXT>::NT), 0, s, tab, first, nmem);
+    hipLaunchKernelGGL((k_step_batch<L, S, TX, TM, false, EXT, FR>), dim3(nblk),
+                       dim3(StepBlock<L, S, TX, TM, false, EXT, FR>::NT), 0, s, tab, first, nmem);
 }
-template <class L, class S, int TX, int TM>
+template <class L, class S, int TX, int TM, int FR>
 void launch_step_batch(const StepArgs* tab, const int* first, int nmem, int nblk, bool buf, bool ext,
                        hipStream_t s) {
-  if (ext) launch_step_batch_g<L, S, TX, TM, true>(tab, first, nmem, nblk, buf, s);
-  else launch_step_batch_g<L, S, TX, TM, false>(tab, first, nmem, nblk, buf, s);
+  if (ext) launch_step_batch_g<L, S, TX, TM, true, FR>(tab, first, nmem, nblk, buf, s);
+  else launch_step_batch_g<L, S, TX, TM, false, FR>(tab, first, nmem, nblk, buf, s);
 }
 
-// batched launchers of the z-march tile variants, in the order of the
-// single-lattice tile tables (the two-pass variant has no batched form)
-template <class L, int TX, int TM>
+// batched launchers of the z-march and flat tile variants, in the order of
+// the single-lattice tile tables (the two-pass variant has no batched form)
+template <class L, int TX, int TM, int FR = 0>
 struct BatchTile {
-  static constexpr BatchStepFn fn[3] = {&launch_step_batch<L, SF64, TX, TM>, &launch_step_batch<L, SF32, TX, TM>,
-                                        &launch_step_batch<L, SF16S, TX, TM>};
+  static constexpr BatchStepFn fn[3] = {&launch_step_batch<L, SF64, TX, TM, FR>,
+                                        &launch_step_batch<L, SF32, TX, TM, FR>,
+                                        &launch_step_batch<L, SF16S, TX, TM, FR>};
 };
 inline const BatchStepFn* const kBatch2[] = {BatchTile<D2Q9K, 64, 1>::fn, BatchTile<D2Q9K, 128, 1>::fn,
-                                      BatchTile<D2Q9K, 256, 1>::fn};
+                                      BatchTile<D2Q9K, 256, 1>::fn, BatchTile<D2Q9K, 64, 1, 2>::fn,
+                                      BatchTile<D2Q9K, 64, 1, 4>::fn};
 inline const BatchStepFn* const kBatch3[] = {BatchTile<D3Q19K, 64, 4>::fn, BatchTile<D3Q19K, 64, 8>::fn,
                                       BatchTile<D3Q19K, 32, 8>::fn, BatchTile<D3Q19K, 128, 4>::fn};
 constexpr int kNBatch2 = sizeof(kBatch2) / sizeof(kBatch2[0]);

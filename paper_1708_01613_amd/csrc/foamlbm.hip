@@ -368,7 +368,7 @@ int flb_autotune(flb_ctx* c, int32_t reps, double* best_ms) {
   for (int t = 0; t < nt && e == hipSuccess; t++) {
     c->tile = t;
     std::vector<int> cand;
-    if (c->two_pass()) cand.push_back(c->md.nz);
+    if (c->two_pass() || c->tcfg().fh) cand.push_back(c->md.nz);  // the segment length is fixed
     else
       for (int l : lzs) cand.push_back(std::min(l, c->md.nz));
     cand.erase(std::unique(cand.begin(), cand.end()), cand.end());

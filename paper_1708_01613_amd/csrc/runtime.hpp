@@ -48,19 +48,19 @@ using StepFn = void (*)(const StepArgs&, int, hipStream_t);
 
 // buffers below 2 GiB use buffer-resource loads with 32-bit offsets; the
 // source terms (gas release, body force) have a variant of their own
-template <class L, class S, int TX, int TM, bool EXT>
+template <class L, class S, int TX, int TM, bool EXT, int FR>
 void launch_step_g(const StepArgs& a, int nblk, hipStream_t s) {
   if (a.buf_bytes < kBufPathLimit)
-    hipLaunchKernelGGL((k_step<L, S, TX, TM, true, EXT>), dim3(nblk), dim3(StepBlock<L, S, TX, TM, true, EXT>::NT),
-                       0, s, a);
+    hipLaunchKernelGGL((k_step<L, S, TX, TM, true, EXT, FR>), dim3(nblk),
+                       dim3(StepBlock<L, S, TX, TM, true, EXT, FR>::NT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_step<L, S, TX, TM, false, EXT>), dim3(nblk),
-                       dim3(StepBlock<L, S, TX, TM, false, EXT>::NT), 0, s, a);
+    hipLaunchKernelGGL((k_step<L, S, TX, TM, false, EXT, FR>), dim3(nblk),
+                       dim3(StepBlock<L, S, TX, TM, false, EXT, FR>::NT), 0, s, a);
 }
-template <class L, class S, int TX, int TM>
+template <class L, class S, int TX, int TM, int FR>
 void launch_step(const StepArgs& a, int nblk, hipStream_t s) {
-  if (a.srcw || a.force_on) launch_step_g<L, S, TX, TM, true>(a, nblk, s);
-  else launch_step_g<L, S, TX, TM, false>(a, nblk, s);
+  if (a.srcw || a.force_on) launch_step_g<L, S, TX, TM, true, FR>(a, nblk, s);
+  else launch_step_g<L, S, TX, TM, false, FR>(a, nblk, s);
 }
 
 // two-pass path: k_psi then k_collide
@@ -79,23 +79,27 @@ void launch_collide(const StepArgs& a, int nblk, hipStream_t s) {
     hipLaunchKernelGGL((k_collide<L, S, false>), dim3(nblk), dim3(TP_NT), 0, s, a);
 }
 
-// step variants: z-march tiles (tx, tm) or the two-pass path (tx = tm = 0)
+// step variants: z-march tiles (tx, tm), flat 2-D tiles (tx = 64, tm = 1,
+// fh rows: the segment length is fixed) or the two-pass path (tx = tm = 0)
 struct TileCfg {
   int tx, tm;
-  StepFn fn[3];    // z-march kernel, or k_psi, per storage F64, F32, F16S
+  StepFn fn[3];    // z-march or flat kernel, or k_psi, per storage F64, F32, F16S
   StepFn coll[3];  // k_collide of the two-pass path
+  int fh;          // rows of a flat tile (0: march or two-pass)
 };
 
-template <class L, int TX, int TM>
+template <class L, int TX, int TM, int FR = 0>
 constexpr TileCfg make_tile() {
   return TileCfg{TX, TM,
-                 {&launch_step<L, SF64, TX, TM>, &launch_step<L, SF32, TX, TM>, &launch_step<L, SF16S, TX, TM>},
-                 {nullptr, nullptr, nullptr}};
+                 {&launch_step<L, SF64, TX, TM, FR>, &launch_step<L, SF32, TX, TM, FR>,
+                  &launch_step<L, SF16S, TX, TM, FR>},
+                 {nullptr, nullptr, nullptr},
+                 StepBlock<L, SF32, TX, TM, true, false, FR>::FH * (FR > 0)};
 }
 template <class L>
 constexpr TileCfg make_two_pass() {
   return TileCfg{0, 0, {&launch_psi<L, SF64>, &launch_psi<L, SF32>, &launch_psi<L, SF16S>},
-                 {&launch_collide<L, SF64>, &launch_collide<L, SF32>, &launch_collide<L, SF16S>}};
+                 {&launch_collide<L, SF64>, &launch_collide<L, SF32>, &launch_collide<L, SF16S>}, 0};
 }
 
 // the two-lattice step: k_psi_tl then k_collide_tl, on the two-pass decomposition
@@ -110,8 +114,9 @@ void launch_tl(const StepArgs& a, const TLArgs& t, int nblk, hipStream_t s) {
   }
 }
 
-const TileCfg kTiles2[] = {make_tile<D2Q9K, 64, 1>(), make_tile<D2Q9K, 128, 1>(), make_tile<D2Q9K, 256, 1>(),
-                           make_two_pass<D2Q9K>()};
+const TileCfg kTiles2[] = {make_tile<D2Q9K, 64, 1>(),    make_tile<D2Q9K, 128, 1>(),
+                           make_tile<D2Q9K, 256, 1>(),   make_tile<D2Q9K, 64, 1, 2>(),
+                           make_tile<D2Q9K, 64, 1, 4>(), make_two_pass<D2Q9K>()};
 const TileCfg kTiles3[] = {make_tile<D3Q19K, 64, 4>(), make_tile<D3Q19K, 64, 8>(), make_tile<D3Q19K, 32, 8>(),
                            make_tile<D3Q19K, 128, 4>(), make_two_pass<D3Q19K>()};
 constexpr int kNTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
@@ -299,9 +304,11 @@ struct flb_ctx {
   bool two_pass() const { return tcfg().tx == 0; }
   int tiles_x() const { return two_pass() ? 1 : (md.nx + tcfg().tx - 1) / tcfg().tx; }
   int tiles_m() const { return two_pass() ? 1 : (md.nm + tcfg().tm - 1) / tcfg().tm; }
+  // the segment length of the launch: the tuning's, or a flat tile's rows
+  int seg_len() const { return tcfg().fh ? tcfg().fh : lz; }
   int nblocks() const {
     if (two_pass()) return geo.nxb * (int)((md.nm * (long long)md.nz + TP_ROWS - 1) / TP_ROWS);
-    return tiles_x() * tiles_m() * ((md.nz + lz - 1) / lz);
+    return tiles_x() * tiles_m() * ((md.nz + seg_len() - 1) / seg_len());
   }
 };
 
@@ -336,7 +343,7 @@ inline StepArgs step_args(flb_ctx* c) {
   a.nz = c->md.nz;
   a.tiles_x = c->tiles_x();
   a.tiles_m = c->tiles_m();
-  a.lz = c->lz;
+  a.lz = c->seg_len();
   const int nblk = c->nblocks();
   a.xcd_chunks = (c->xcd > 1 && nblk % c->xcd == 0) ? c->xcd : 1;
   a.tau = c->p.tau;

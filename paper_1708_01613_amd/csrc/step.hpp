@@ -443,7 +443,18 @@ static __global__ __launch_bounds__(FIN_NT) void k_step_finish_batch(const StepA
 // z0-1+j; a collide at iteration k reads slots k-3..k-1, and the slot written
 // at iteration k was last read before the barrier of iteration k-1.  The three
 // register sets rotate by unrolling the loop three times.
-template <class L, class S, int TX, int TM, bool BUF, bool EXT>
+//
+// FR > 0: the flat tile of 2-D lattices (no march), FR rows per wavefront.
+// A workgroup of FW wavefronts owns 64 cells x FH = FW * FR rows (the rows
+// z0 .. z0+FH-1, fewer in the last segment); wavefront w keeps rows w*FR ..
+// w*FR+FR-1 in registers.  Every wavefront issues the loads of all its rows
+// at once (wavefronts 0 and FW-1 also the rows z0-1 and z0+FH around the
+// tile, and lanes 0 .. 2FR+1 the end cells x0-1 and x0+TXe of those rows),
+// publishes psi of every loaded row into LDS row (z - z0 + 1), synchronises
+// once and collides its rows.  A short D2Q9 march spends most of its time
+// waiting on one plane of nine loads at a time; here a wavefront has all of
+// its rows' loads in flight together.
+template <class L, class S, int TX, int TM, bool BUF, bool EXT, int FR = 0>
 struct StepBlock {
   using T = typename S::ct;
   static constexpr int Q = L::Q;
@@ -457,9 +468,16 @@ struct StepBlock {
   // wave of their own
   static constexpr bool HIN = !L::HAS_M;
   static constexpr int NH = 2 * (TM + 2 * HM) + (HM ? 2 * TX : 0);
-  static constexpr int NT = HIN ? NI : NI + (NH + 63) / 64 * 64;
+  static constexpr bool FLAT = FR > 0;
+  static constexpr int FW = 4;            // wavefronts of a flat tile
+  static constexpr int FH = FR * FW;      // rows of a flat tile
+  static_assert(!FLAT || (!L::HAS_M && TX == 64 && TM == 1), "flat tiles are 64-cell D2Q9 row blocks");
+  static constexpr int NT = FLAT ? 64 * FW : (HIN ? NI : NI + (NH + 63) / 64 * 64);
+  // LDS rows of psi: a ring of 4 planes for the march, every row of a flat tile
+  static constexpr int NSLOT = FLAT ? FH + 2 : 4;
+  __device__ static constexpr int slot(int j) { return FLAT ? j : (j & 3); }
   struct Smem {
-    T psi[4][LH][LW];
+    T psi[NSLOT][LH][LW];
     double red[NT / 64][4];
     int last;
   };
@@ -523,6 +541,63 @@ struct StepBlock {
     __syncthreads();
   }
 
+  __device__ static __forceinline__ int wrap_row(int z, int n) {
+    const int r = z % n;
+    return r < 0 ? r + n : r;
+  }
+  __device__ __forceinline__ void flat_tile() {
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int lane = (int)threadIdx.x & 63;
+    const bool actx = lane < TXe;
+    T f[FR][Q];
+    unsigned fl[FR];
+#pragma unroll
+    for (int j = 0; j < FR; j++) {
+      const int zl = wrap_row(z0 + w * FR + j, nz);
+      fl[j] = film ? a.mask[(unsigned)(xc + nx * zl)] : 0u;
+      io.pull_raw(xc, 0, zl, f[j]);
+    }
+    // the rows around the tile (wave-uniform), then the end cells
+    const bool hrow = w == 0 || w == FW - 1;
+    const int hi = w == 0 ? 0 : FH + 1;
+    T fh[Q] = {};
+    if (hrow) io.pull_raw(xc, 0, wrap_row(z0 - 1 + hi, nz), fh);
+    const bool hend = lane < 2 * FR + (hrow ? 2 : 0);
+    const int er = lane < 2 * FR ? w * FR + (lane >> 1) + 1 : hi;
+    const int ex_ = (lane & 1) ? TXe : -1;
+    T fe[Q] = {};
+    if (hend) io.pull_raw(wrap_row(x0 + ex_, nx), 0, wrap_row(z0 - 1 + er, nz), fe);
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+#pragma unroll
+    for (int j = 0; j < FR; j++) {
+      io.decode_all(f[j]);
+      T r = T(0);
+#pragma unroll
+      for (int i = 0; i < Q; i++) r += f[j][i];
+      if (actx) sm.psi[w * FR + j + 1][0][lane + 1] = psi_of(r, rho0);
+    }
+    if (hrow) {
+      io.decode_all(fh);
+      T r = T(0);
+#pragma unroll
+      for (int i = 0; i < Q; i++) r += fh[i];
+      if (actx) sm.psi[hi][0][lane + 1] = psi_of(r, rho0);
+    }
+    if (hend) {
+      io.decode_all(fe);
+      T r = T(0);
+#pragma unroll
+      for (int i = 0; i < Q; i++) r += fe[i];
+      sm.psi[er][0][ex_ + 1] = psi_of(r, rho0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < FR; j++) {
+      const int r = w * FR + j;  // wave-uniform
+      if (r < L_) collide(r + 3, f[j], actx ? fl[j] : 0u);
+    }
+  }
+
   // halo waves: psi of the ring cells of every loaded plane
   __device__ __forceinline__ void halo_loop() {
     const int kend = L_ + 2;
@@ -546,7 +621,7 @@ struct StepBlock {
     // the same values bit for bit whatever other code the compiler sees
 #pragma clang fp contract(off)
     const int zc = z0 + k - 3;
-    const int sl[3] = {(k - 3) & 3, (k - 2) & 3, (k - 1) & 3};
+    const int sl[3] = {slot(k - 3), slot(k - 2), slot(k - 1)};
     // lanes outside the lattice compute on clamped data and store to an
     // offset past the end of the buffer, which the buffer unit discards
     const unsigned c = (unsigned)(xc + nx * (mc + nm * zc));
@@ -721,7 +796,16 @@ struct StepBlock {
     rho_all = a.gas_k > 0 && (step + 1) % a.gas_k == 0;
     psi_bar = (T)a.psi_bar;
 
-    if (interior) {
+    if constexpr (FLAT) {
+      lx = (int)threadIdx.x & 63;
+      lm = 0;
+      m = 0;
+      mc = 0;
+      x = x0 + lx;
+      xc = min(x, nx - 1);
+      act = lx < TXe;
+      flat_tile();
+    } else if (interior) {
       T r0[Q], r1[Q], r2[Q];
       unsigned g0 = 0, g1 = 0, g2 = 0;
       const int kend = L_ + 2;
@@ -743,19 +827,19 @@ struct StepBlock {
 // EXT: the variant with the source terms after the collision, the gas release
 // and the body force (their code costs registers, so lattices without them
 // run the variant without it)
-template <class L, class S, int TX, int TM, bool BUF, bool EXT>
-__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF, EXT>::NT)) void k_step(StepArgs a) {
-  using SB = StepBlock<L, S, TX, TM, BUF, EXT>;
+template <class L, class S, int TX, int TM, bool BUF, bool EXT, int FR = 0>
+__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF, EXT, FR>::NT)) void k_step(StepArgs a) {
+  using SB = StepBlock<L, S, TX, TM, BUF, EXT, FR>;
   __shared__ typename SB::Smem sm;
   if (a.ctl->stopped) return;
   SB blk(a, sm);
   blk.run(blockIdx.x, gridDim.x);
 }
 
-template <class L, class S, int TX, int TM, bool BUF, bool EXT>
-__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF, EXT>::NT)) void k_step_batch(
+template <class L, class S, int TX, int TM, bool BUF, bool EXT, int FR = 0>
+__global__ __launch_bounds__((StepBlock<L, S, TX, TM, BUF, EXT, FR>::NT)) void k_step_batch(
     const StepArgs* __restrict__ tab, const int* __restrict__ first, int nmem) {
-  using SB = StepBlock<L, S, TX, TM, BUF, EXT>;
+  using SB = StepBlock<L, S, TX, TM, BUF, EXT, FR>;
   __shared__ typename SB::Smem sm;
   const int k = batch_member(first, nmem, blockIdx.x);
   const StepArgs& a = tab[k];  // read in place: a local copy would live in scratch
