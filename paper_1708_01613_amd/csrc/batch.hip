@@ -33,7 +33,7 @@ int flb_batch_create(const flb_params* params, int32_t count, const flb_allocato
   b->st = (hipStream_t)hip_stream;
   b->D = params[0].lattice == FLB_D2Q9 ? 2 : 3;
   b->storage = params[0].storage;
-  b->tile = b->D == 2 ? 0 : 1;
+  b->tile = flb_batch::default_tile(b->D);
   b->target = b->D == 2 ? 4096 : 512;
   for (int k = 0; k < count; k++) {
     flb_ctx* c = nullptr;

@@ -125,6 +125,9 @@ struct flb_batch {
   }
   int n_tiles() const { return D == 2 ? flb_rt::kNBatch2 : flb_rt::kNBatch3; }
   static constexpr int kPersistTile = 2;  // kBatch2's 256 x 1 tile
+  // untuned batches: D2Q9 the flat 64 x 8 tile (the fastest on small
+  // lattices), D3Q19 the 64 x 8 march
+  static int default_tile(int D) { return D == 2 ? 3 : 1; }
   flb_rt::BatchStepFn step_fn() const { return (D == 2 ? flb_rt::kBatch2 : flb_rt::kBatch3)[tile][storage]; }
 };
 
@@ -431,7 +434,7 @@ inline flb_batch* batch_view(const std::vector<flb_ctx*>& ms, hipStream_t st, co
   b->st = st;
   b->D = ms[0]->D;
   b->storage = ms[0]->p.storage;
-  b->tile = b->D == 2 ? 0 : 1;
+  b->tile = flb_batch::default_tile(b->D);
   b->target = b->D == 2 ? 4096 : 512;
   return b;
 }
