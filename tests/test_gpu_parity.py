@@ -428,3 +428,40 @@ def test_film_on_lattices_smaller_than_a_tile(flb, kind, dims):
     lab, nb = g.labels()
     olab, onb = o.labels()
     assert nb == onb and np.array_equal(lab, olab)
+
+
+_DEGENERATE = {(0, (1, 40, 1)): [[0.0, 10.0, 0, 7.0], [0.0, 27.0, 0, 7.0]],
+               (0, (50, 1, 1)): [[12.0, 0.0, 0, 9.0], [35.0, 0.0, 0, 9.0]],
+               (1, (1, 30, 7)): [[0.0, 8.0, 3.0, 5.0], [0.0, 21.0, 3.0, 5.0]],
+               (1, (40, 1, 1)): [[10.0, 0.0, 0.0, 7.0], [28.0, 0.0, 0.0, 7.0]],
+               (1, (2, 2, 2)): [[0.5, 0.5, 0.5, 0.9]],
+               (0, (1, 1, 1)): []}
+
+
+@pytest.mark.parametrize("kind,dims", list(_DEGENERATE))
+def test_degenerate_extents(flb, kind, dims):
+    # extents of one or two cells, where a cell is its own periodic neighbour
+    # (or x + e and x - e are one cell), with the film on and ruptures: the
+    # oracle's fields, maps and events under every tile variant, whose
+    # populations agree bit for bit
+    nx, ny, nz = dims
+    nuc = _DEGENERATE[(kind, dims)]
+    p = _case(flb, lattice=kind, storage="f64", nx=nx, ny=ny, nz=nz, G=-5.5, rho_liquid=2.3, rho_gas=0.11, film_on=1,
+              k_own=2, zone_width=6, rupture_warmup=2, seed=6)
+    o = oracle_for(p, nuc)
+    o.step(8)
+    ref = None
+    for tile in range(flb.Sim(**p).tuning()["n_tiles"]):
+        print(f"[case] tile {tile}", flush=True)
+        g = flb.Sim(**p)
+        g.set_tuning(tile, 0, -1)
+        g.set_nuclei(nuc)
+        g.step(8)
+        f = g.populations()
+        if ref is None:
+            ref = f
+            assert max_rel(g.density(), o.density()) <= 1e-12
+            _compare_maps(flb, kind, g, o)
+            assert g.stats()["n_ruptures"] == o.n_ruptures
+            assert {tuple(r) for r in g.rupture_events().tolist()} == {tuple(r) for r in o.events().tolist()}
+        assert np.array_equal(f, ref), tile
