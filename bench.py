@@ -390,7 +390,9 @@ def main():
             "n_bubbles": nb2, "coalescences": merges, "n_ruptures": st2["n_ruptures"], "kernel_ms": round(ms2, 4),
             "kernel_GBs_algorithmic": round(BYTES_PER_UPDATE[("d2q9", "f32")] * n2 / (ms2 * 1e-3) / 1e9, 1),
             "kernel": (f"k_step<D2Q9K,SF32,{t2['tile_x']},{t2['tile_m']}>" if t2["tile_x"]
-                       else "k_psi+k_collide<D2Q9K,SF32>")}
+                       else "k_psi+k_collide<D2Q9K,SF32>"),
+            # variant index: 0-2 marches 64/128/256 wide, 3-4 flat tiles of 8/16 rows
+            "tile": t2["tile"]}
         log(f"d2q9 1024^2 foam: {variants['d2q9_1024_foam']['MLUPS']:.0f} MLUPS over {steps2} steps, "
             f"step kernel {ms2:.4f} ms")
         del s2

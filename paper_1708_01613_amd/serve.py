@@ -144,7 +144,7 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     e = sub.add_parser("ensemble")
     e.add_argument("--steps", type=int, default=1000)
-    e.add_argument("--mode", choices=("batched", "sequential"), default="batched")
+    e.add_argument("--mode", choices=("batched", "persistent", "sequential"), default="batched")
     s = sub.add_parser("served")
     s.add_argument("--jobs", type=int, default=48)
     s.add_argument("--steps", type=int, default=1000)
