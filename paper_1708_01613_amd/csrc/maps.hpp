@@ -179,7 +179,7 @@ __device__ __forceinline__ bool map_due(const MapArgs& m) {
 }
 
 // decompositions of a map launch (workgroups per lattice)
-enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_MASKT, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_BFSB, SH_FEW, SH_COUNT };
+enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_MASKT, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_BFSB, SH_FEW, SH_MASKZ, SH_COUNT };
 
 #define MAP_KERNEL_PARAMS const MapArgs *__restrict__ tab, const int *__restrict__ first, int nmem
 #define MAP_MEMBER                                                           \
@@ -960,6 +960,118 @@ __global__ __launch_bounds__(BFS_NT) void k_masks(MAP_KERNEL_PARAMS) {
   }
 }
 
+// ---- barrier masks, 3-D lattices: a z-march over planes ----
+// A workgroup owns 64 x MZ_TM cells of MZ_LZ consecutive planes.  Iteration k
+// issues the loads of plane z0-1+k (distances and owner pairs of the plane's
+// 66 x (MZ_TM + 2) staged cells, periodic), computes the masks of plane
+// z0+k-3 from the three planes staged before (LDS ring of 4 planes) while
+// those loads are in flight, then stages the new plane and synchronises once.
+// Each staged cell is loaded once per workgroup instead of once per 64 x 4 x 4
+// tile with a halo all round (1.5x the tile's cells instead of 2.3x), and the
+// loads of one plane overlap the links of the previous one.  Per cell the
+// links and masks are those of k_masks.
+constexpr int MZ_TM = 4, MZ_LZ = 16;
+template <class L>
+__global__ __launch_bounds__(BFS_NT) void k_masks_z(MAP_KERNEL_PARAMS) {
+  static_assert(L::HAS_M && BFS_NT == 64 * MZ_TM, "one cell of a plane per thread");
+  MAP_MEMBER
+  if (!map_due(m)) return;
+  constexpr int LX = 66, LM = MZ_TM + 2, PL = LX * LM;
+  static_assert(PL <= 2 * BFS_NT, "two staged cells per thread");
+  __shared__ uint8_t sd[4][PL];
+  __shared__ int2 so[4][PL];
+  const MapDims d = m.d;
+  const int zone_width = m.zone_width;
+  const FLB_AS_GLOBAL uint8_t* dist = as_global((const uint8_t*)m.dist);
+  const FLB_AS_GLOBAL int* alias = as_global((const int*)m.alias);
+  const int ntx = (d.nx + 63) / 64, ntm = (d.nm + MZ_TM - 1) / MZ_TM;
+  const int b = (int)bid;
+  const int x0 = (b % ntx) * 64, m0 = ((b / ntx) % ntm) * MZ_TM, z0 = (b / (ntx * ntm)) * MZ_LZ;
+  const int L_ = min(MZ_LZ, d.nz - z0);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nxs = (d.nx + 63) >> 6;
+  // the two staged cells of this thread: in-plane offsets (periodic)
+  unsigned soff[2];
+  bool sv[2];
+#pragma unroll
+  for (int u = 0; u < 2; u++) {
+    const int st = (int)threadIdx.x + u * BFS_NT;
+    sv[u] = st < PL;
+    const int r = st / LX, q = st % LX;
+    soff[u] = (unsigned)wrap_mod(x0 - 1 + q, d.nx) + (unsigned)d.nx * (unsigned)wrap_mod(m0 - 1 + r, d.nm);
+  }
+  const unsigned plane = (unsigned)d.nx * (unsigned)d.nm;
+  const int x = x0 + lane, mm_ = m0 + wv;
+  const bool colin = x < d.nx && mm_ < d.nm;
+  const int lc = (lane + 1) + LX * (wv + 1);
+  auto root_pair = [&](int2 o) {
+    const int ra = alias[o.x], rb = alias[o.y];
+    return make_int2(min(ra, rb), max(ra, rb));
+  };
+  for (int k = 0; k <= L_ + 2; k++) {  // uniform over the workgroup
+    uint8_t dv[2] = {255, 255};
+    int2 ov[2] = {make_int2(0, 0), make_int2(0, 0)};
+    if (k <= L_ + 1) {
+      const unsigned zb = plane * (unsigned)wrap_mod(z0 - 1 + k, d.nz);
+#pragma unroll
+      for (int u = 0; u < 2; u++)
+        if (sv[u]) {
+          dv[u] = dist[zb + soff[u]];
+          ov[u] = ld_pair(m.own, zb + soff[u]);
+        }
+    }
+    if (k >= 3) {
+      // the links of plane zc from the planes staged at iterations k-3 .. k-1
+      const int zc = z0 + k - 3;
+      const int sl[3] = {(k - 3) & 3, (k - 2) & 3, (k - 1) & 3};
+      const bool in = colin;
+      const unsigned cidx = in ? (unsigned)x + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)zc) : 0u;
+      unsigned mk = 0;
+      if (in) {
+        const int dc = sd[sl[1]][lc];
+        if (dc != 255) {
+          const int2 oc = so[sl[1]][lc];
+          unsigned cand = 0;  // thin links to cells with another owner pair
+#pragma unroll
+          for (int i = 1; i < L::Q; i++) {
+            const int li = lc + L::ex[i] + LX * L::em[i];
+            const int si = sl[1 + L::ez[i]];
+            if (dc + (int)sd[si][li] + 1 <= zone_width) {
+              const int2 on = so[si][li];
+              if (on.x != oc.x || on.y != oc.y) cand |= 1u << i;
+            }
+          }
+          if (cand) {
+            const int2 rc = root_pair(oc);
+#pragma unroll
+            for (int i = 1; i < L::Q; i++) {
+              if (!(cand & (1u << i))) continue;
+              const int2 rn = root_pair(so[sl[1 + L::ez[i]]][lc + L::ex[i] + LX * L::em[i]]);
+              if (rn.x != rc.x || rn.y != rc.y) mk |= 1u << i;
+            }
+          }
+        }
+        as_global(m.flag)[cidx] = mk ? 1 : 0;
+        as_global(m.mask)[cidx] = mk;
+      }
+      const unsigned long long bal = __ballot(mk != 0);
+      if (mm_ < d.nm && lane == 0) {
+        const unsigned row = (unsigned)mm_ + (unsigned)d.nm * (unsigned)zc;
+        as_global(m.fwords)[(unsigned)(x0 >> 6) + (unsigned)nxs * row] = bal;
+      }
+    }
+    if (k <= L_ + 1) {
+#pragma unroll
+      for (int u = 0; u < 2; u++)
+        if (sv[u]) {
+          sd[k & 3][(int)threadIdx.x + u * BFS_NT] = dv[u];
+          so[k & 3][(int)threadIdx.x + u * BFS_NT] = ov[u];
+        }
+    }
+    __syncthreads();
+  }
+}
+
 // ---- the flagged-cell list from the flag words, in cell order ----
 static __global__ __launch_bounds__(FW_BLOCK) void k_flag_count(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
@@ -1098,6 +1210,7 @@ __host__ inline int map_share(int shape, const MapDims& d) {
     case SH_SEG: g = std::min<long long>((nseg + MAP_WAVES - 1) / MAP_WAVES, 16384); break;
     case SH_CCT: g = cc_tiles(d, CCTile<L>::TM, CCTile<L>::TZ); break;
     case SH_MASKT: g = cc_tiles(d, MaskTile<L>::TM, MaskTile<L>::TZ); break;
+    case SH_MASKZ: g = cc_tiles(d, MZ_TM, MZ_LZ); break;
     case SH_RANK: g = (N + RANK_BLOCK - 1) / RANK_BLOCK; break;
     case SH_ONE: g = 1; break;
     // passes over per-bubble tables (as long as the bubble count, which only

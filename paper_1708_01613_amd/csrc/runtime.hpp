@@ -495,7 +495,8 @@ inline MapArgs map_args(flb_ctx* c, bool query, int src) {
 // owners, distances and aliases in place.
 template <class L>
 int map_masks(const MapSet& s, hipStream_t st) {
-  MAPL((k_masks<L>), SH_MASKT, BFS_NT);
+  if constexpr (L::HAS_M) MAPL((k_masks_z<L>), SH_MASKZ, BFS_NT);
+  else MAPL((k_masks<L>), SH_MASKT, BFS_NT);
   MAPL(k_flag_count, SH_FW, FW_BLOCK);
   MAPL(k_scan_counts, SH_ONE, 1024, 1);
   MAPL(k_flag_write, SH_FW, FW_BLOCK);
