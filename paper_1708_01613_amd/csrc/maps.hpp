@@ -1265,6 +1265,39 @@ __global__ __launch_bounds__(MAP_NT) void k_mask_prune(PruneArgs p) {
   mask_prune<L>(p, blockIdx.x, gridDim.x);
 }
 
+// The pruning launch that also closes the step (one lattice; the finisher
+// of step.hpp with MAP_NT threads).  A step without unions (alias_dirty 0,
+// the common case) prunes nothing, so workgroup 0 finishes the step at once.
+// After unions every workgroup prunes its share and the last to arrive (an
+// arrival counter in the run control, reset by that workgroup) finishes the
+// step; the device-scope fences and atomics are paid only on those steps.
+// Every workgroup reads alias_dirty before any finisher can clear it: in the
+// first case it is 0 throughout, in the second the finisher runs after all
+// workgroups have arrived.
+template <class L>
+__global__ __launch_bounds__(MAP_NT) void k_prune_finish(PruneArgs p, StepArgs a, int nblk) {
+  __shared__ double red[MAP_NT / 64][4];
+  __shared__ int last;
+  Ctl* ctl = a.ctl;
+  const bool dirty = ctl->alias_dirty && !ctl->stopped;  // workgroup-uniform
+  if (!dirty) {
+    if (blockIdx.x == 0) step_finish<MAP_NT>(a, nblk, red);
+    return;
+  }
+  mask_prune<L>(p, blockIdx.x, gridDim.x);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(&ctl->done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    step_finish<MAP_NT>(a, nblk, red);
+    if (threadIdx.x == 0) ctl->done = 0;
+  }
+}
+
 // batched: workgroups [first[k], first[k+1]) prune member k
 template <class L>
 __global__ __launch_bounds__(MAP_NT) void k_mask_prune_batch(const PruneArgs* __restrict__ tab,

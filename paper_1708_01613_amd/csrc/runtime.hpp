@@ -649,15 +649,24 @@ int do_steps(flb_ctx* c, int64_t nsteps, bool refresh, hipEvent_t* ev = nullptr)
     if (e) HIPCHK(hipEventRecord(e[2], c->st));
     // rupture test (applies its unions), pruning of united pairs' links,
     // then the finisher, which closes the step
-    if (c->p.film_on && c->launched >= c->p.rupture_warmup) {
+    const bool fold =
+        c->two_pass() && nblk > 8 * FIN_NT && nblk + (nblk + FOLD - 1) / FOLD <= c->max_blk + c->max_blk / FOLD + 1;
+    const bool test = c->p.film_on && c->launched >= c->p.rupture_warmup;
+    if (test) {
       if (tl)
         hipLaunchKernelGGL((k_rupture_tl<L, typename S::ct>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, a, t);
       else
         hipLaunchKernelGGL((k_rupture<L, typename S::ct>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, a);
-      hipLaunchKernelGGL((k_mask_prune<L>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, prune_args(c));
+      // without the fold, the pruning launch also closes the step
+      if (fold || e)
+        hipLaunchKernelGGL((k_mask_prune<L>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, prune_args(c));
+      else
+        hipLaunchKernelGGL((k_prune_finish<L>), dim3(list_grid(c->N)), dim3(MAP_NT), 0, c->st, prune_args(c), a, nblk);
     }
     if (e) HIPCHK(hipEventRecord(e[3], c->st));
-    if (c->two_pass() && nblk > 8 * FIN_NT && nblk + (nblk + FOLD - 1) / FOLD <= c->max_blk + c->max_blk / FOLD + 1) {
+    if (test && !fold && !e) {
+      // closed by the pruning launch
+    } else if (fold) {
       // fold the many partials of the two-pass decomposition first
       const int nf = (nblk + FOLD - 1) / FOLD;
       hipLaunchKernelGGL(k_fold_partials, dim3(nf), dim3(64), 0, c->st, a.partials, nblk);
