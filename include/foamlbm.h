@@ -386,9 +386,10 @@ void flb_destroy(flb_ctx* ctx);
  * format; every other parameter (extents, tau, G, film settings, seed, ...)
  * may differ per member (params[k]).  A batch step advances every member by
  * one time step exactly as flb_step would, with one batched step-kernel
- * launch over all members' workgroups, one batched finisher launch and, when
- * members have films, one batched rupture-test and one batched mask-pruning
- * launch (film maps are refreshed per member).  Runs of steps are captured in
+ * launch over all members' workgroups and one batched finisher launch (when
+ * members have films: one batched rupture-test launch and one batched launch
+ * that prunes the masks and runs the finishers; film maps are refreshed in
+ * batched launches over the members that are due).  Runs of steps are captured in
  * a HIP graph and replayed when the stream is not the null stream.  Results
  * of a member do not depend on the batch it is in.
  *

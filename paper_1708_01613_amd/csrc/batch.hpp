@@ -3,9 +3,11 @@
 // Members are ordinary contexts of one lattice type and one storage format;
 // their extents and parameters may differ.  One step of the batch is one
 // batched step-kernel launch over every member's workgroups (member k owns the
-// launch's workgroups [first[k], first[k+1])), one batched finisher launch
-// with a workgroup per member, and with films a batched rupture-test launch
-// and a batched mask-pruning launch; film-map refreshes stay per member.  So
+// launch's workgroups [first[k], first[k+1])) and one batched finisher
+// launch with a workgroup per member; with films, a batched rupture-test
+// launch, and a batched launch that prunes the film members' masks and runs
+// every member's finisher; film-map refreshes run batched over the members
+// that are due.  So
 // the launch count per step does not grow with the number of lattices, and the
 // GPU is filled by all members at once instead of one small lattice at a time.
 // Runs of steps are captured in a HIP graph and replayed.  D2Q9 batches may
@@ -86,6 +88,8 @@ struct flb_batch {
   StepArgs* ftab = nullptr;
   PruneArgs* ptab = nullptr;
   int* ffirst = nullptr;
+  int* fidx = nullptr;  // film members' indices, then the other members' (the closing launch)
+  std::vector<int> fidx_h;
   int fblk = 0;
   flb_rt::MapSet fms;  // film refresh of the film members, one launch per map kernel
   flb_rt::Fork fork;   // side stream of the refresh
@@ -181,8 +185,9 @@ inline int rebuild(flb_batch* b) {
       b->ftab = (StepArgs*)b->dalloc(sizeof(StepArgs) * nf);
       b->ptab = (PruneArgs*)b->dalloc(sizeof(PruneArgs) * nf);
       b->ffirst = (int*)b->dalloc(sizeof(int) * (nf + 1));
+      b->fidx = (int*)b->dalloc(sizeof(int) * n);
     }
-    if (!b->tab || !b->first || (nf && (!b->ftab || !b->ptab || !b->ffirst)))
+    if (!b->tab || !b->first || (nf && (!b->ftab || !b->ptab || !b->ffirst || !b->fidx)))
       return fail(FLB_ENOMEM, "batch table allocation failed");
   }
   HIPCHK(hipMemcpyAsync(b->tab, tab.data(), sizeof(StepArgs) * n, hipMemcpyHostToDevice, b->st));
@@ -191,6 +196,10 @@ inline int rebuild(flb_batch* b) {
     HIPCHK(hipMemcpyAsync(b->ftab, ftab.data(), sizeof(StepArgs) * nf, hipMemcpyHostToDevice, b->st));
     HIPCHK(hipMemcpyAsync(b->ptab, ptab.data(), sizeof(PruneArgs) * nf, hipMemcpyHostToDevice, b->st));
     HIPCHK(hipMemcpyAsync(b->ffirst, ffirst.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, b->st));
+    b->fidx_h = b->film;
+    for (int k = 0; k < n; k++)
+      if (!b->m[k]->p.film_on) b->fidx_h.push_back(k);
+    HIPCHK(hipMemcpyAsync(b->fidx, b->fidx_h.data(), sizeof(int) * n, hipMemcpyHostToDevice, b->st));
   }
   if (nf) {
     int rc = b->fork.init();  // outside any graph capture
@@ -226,9 +235,12 @@ int batch_one_step(flb_batch* b) {
   if (nf) {
     hipLaunchKernelGGL((k_rupture_batch<L, typename S::ct>), dim3(b->fblk), dim3(MAP_NT), 0, b->st, b->ftab,
                        b->ffirst, nf);
-    hipLaunchKernelGGL((k_mask_prune_batch<L>), dim3(b->fblk), dim3(MAP_NT), 0, b->st, b->ptab, b->ffirst, nf);
+    // the pruning launch also closes every member's step
+    hipLaunchKernelGGL((k_prune_finish_batch<L>), dim3(b->fblk + (n - nf)), dim3(MAP_NT), 0, b->st, b->ptab,
+                       b->ffirst, nf, b->tab, b->first, b->fidx);
+  } else {
+    hipLaunchKernelGGL(k_step_finish_batch, dim3(n), dim3(FIN_NT), 0, b->st, b->tab, b->first);
   }
-  hipLaunchKernelGGL(k_step_finish_batch, dim3(n), dim3(FIN_NT), 0, b->st, b->tab, b->first);
   HIPCHK(hipGetLastError());
   for (flb_ctx* c : b->m) c->launched++;
   return FLB_OK;

@@ -1298,13 +1298,49 @@ __global__ __launch_bounds__(MAP_NT) void k_prune_finish(PruneArgs p, StepArgs a
   }
 }
 
-// batched: workgroups [first[k], first[k+1]) prune member k
+// batched form of k_prune_finish: workgroups [ffirst[j], ffirst[j+1]) prune
+// film member j (member index idx[j]) and close its step as k_prune_finish
+// does; workgroup ffirst[nf] + i closes the step of member idx[nf + i], one
+// without a film.  tab / first: the batched step launch's members and
+// workgroup ranges (a member's partials count).
 template <class L>
-__global__ __launch_bounds__(MAP_NT) void k_mask_prune_batch(const PruneArgs* __restrict__ tab,
-                                                             const int* __restrict__ first, int nmem) {
-  const int k = batch_member(first, nmem, blockIdx.x);
-  const PruneArgs p = tab[k];
-  mask_prune<L>(p, blockIdx.x - first[k], first[k + 1] - first[k]);
+__global__ __launch_bounds__(MAP_NT) void k_prune_finish_batch(const PruneArgs* __restrict__ ptab,
+                                                               const int* __restrict__ ffirst, int nf,
+                                                               const StepArgs* __restrict__ tab,
+                                                               const int* __restrict__ first,
+                                                               const int* __restrict__ idx) {
+  __shared__ double red[MAP_NT / 64][4];
+  __shared__ int last;
+  const int fblk = nf ? ffirst[nf] : 0;
+  if ((int)blockIdx.x >= fblk) {
+    const int k = idx[nf + (int)blockIdx.x - fblk];
+    step_finish<MAP_NT>(tab[k], first[k + 1] - first[k], red);
+    return;
+  }
+  const int j = batch_member(ffirst, nf, blockIdx.x);
+  const int k = idx[j];
+  const StepArgs& a = tab[k];  // read in place: a local copy would live in scratch
+  const int nblk = first[k + 1] - first[k];
+  const unsigned bid = blockIdx.x - (unsigned)ffirst[j], nb = (unsigned)(ffirst[j + 1] - ffirst[j]);
+  Ctl* ctl = a.ctl;
+  const bool dirty = ctl->alias_dirty && !ctl->stopped;  // workgroup-uniform
+  if (!dirty) {
+    if (bid == 0) step_finish<MAP_NT>(a, nblk, red);
+    return;
+  }
+  const PruneArgs p = ptab[j];
+  mask_prune<L>(p, bid, nb);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(&ctl->done, 1u) == nb - 1;
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    step_finish<MAP_NT>(a, nblk, red);
+    if (threadIdx.x == 0) ctl->done = 0;
+  }
 }
 
 }  // namespace flb
