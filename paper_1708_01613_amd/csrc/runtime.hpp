@@ -324,10 +324,10 @@ inline int lz_for_target(const flb_ctx* c, long long target) {
 }
 
 inline void default_tuning(flb_ctx* c) {
-  // D2Q9: 64x1 tiles, ~2048 workgroups; D3Q19: 64x8 tiles, ~256 long
-  // marches (one per CU), which spends the least on halo planes.
-  // Workgroups are spread over the 8 XCDs.
-  c->tile = c->D == 2 ? 0 : 1;
+  // D2Q9: the flat 64 x 8-row tile; D3Q19: 64x8 tiles, ~256 long marches
+  // (one per CU), which spends the least on halo planes.  Workgroups are
+  // spread over the 8 XCDs.
+  c->tile = c->D == 2 ? 3 : 1;
   c->lz = lz_for_target(c, c->D == 2 ? 2048 : 256);
   c->xcd = 8;
 }
