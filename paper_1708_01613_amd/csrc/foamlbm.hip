@@ -994,6 +994,7 @@ int flb_load(flb_ctx* c, const char* path) {
     if (!rc) rc = file_to_dev(fp, a.first, a.second, c->st);
   fclose(fp);
   if (rc) return rc;
+  hd.ctl.done = 0;  // the arrival counter of a launch; zero between steps
   HIPCHK(hipMemcpyAsync(c->ctl, &hd.ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   c->launched = hd.ctl.steps;
