@@ -409,6 +409,16 @@ __global__ __launch_bounds__(MAP_NT) void k_cc_cross(MAP_KERNEL_PARAMS) {
         py[p] = __atomic_load_n(&gpar[y], __ATOMIC_RELAXED);
       }
     }
+    // a cell's neighbours across a face mostly hang under one remote parent:
+    // each distinct (pc, py) pair of a lane is united once, in its first
+    // direction
+#pragma unroll
+    for (int p = 1; p < NP; p++) {
+      bool seen = false;
+#pragma unroll
+      for (int q = 0; q < p; q++) seen |= py[q] == py[p];
+      if (seen) py[p] = -1;
+    }
     // one union per run of equal root pairs, the runs' unions concurrently
 #pragma unroll
     for (int p = 0; p < NP; p++) {
