@@ -86,12 +86,6 @@ struct SegCell {
   __device__ __forceinline__ unsigned nb(int ex, int em, int ez) const { return xw[1 + ex] + rb[1 + em][1 + ez]; }
 };
 
-__host__ inline int map_grid(const MapDims& d) {
-  const long long nseg = (long long)((d.nx + 63) / 64) * d.nm * d.nz;
-  const long long g = (nseg + MAP_WAVES - 1) / MAP_WAVES;
-  return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
-}
-
 // calls f(const SegCell&) for every cell; `HALO` fills the neighbour tables.
 // Workgroup bid of nb workgroups (the launch's, or a batch member's share).
 template <bool HALO, class F>
@@ -179,7 +173,7 @@ __device__ __forceinline__ bool map_due(const MapArgs& m) {
 }
 
 // decompositions of a map launch (workgroups per lattice)
-enum MapShape { SH_CELLS = 0, SH_SEG, SH_CCT, SH_MASKT, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_BFSB, SH_FEW, SH_MASKZ, SH_COUNT };
+enum MapShape { SH_CELLS = 0, SH_CCT, SH_MASKT, SH_RANK, SH_ONE, SH_LIST, SH_FW, SH_BFSB, SH_FEW, SH_MASKZ, SH_COUNT };
 
 #define MAP_KERNEL_PARAMS const MapArgs *__restrict__ tab, const int *__restrict__ first, int nmem
 #define MAP_MEMBER                                                           \
@@ -210,9 +204,9 @@ __device__ __forceinline__ bool run_head(int a, int b) {
 // for liquid, the tile-local root for gas (the local order is the global
 // order, so that root is the component's smallest cell index within the
 // tile).  Phase 2 (k_cc_cross): the links that leave a tile (including the
-// periodic wrap) unite the local roots in the global union-find; a wavefront
-// first merges duplicate root pairs, which are the common case, so few global
-// atomics remain.  Large tiles keep the share of cells on tile faces, and so
+// periodic wrap) unite the local roots in the global union-find; each tile
+// first gathers its distinct root pairs, which are few, so few global atomics
+// remain.  Large tiles keep the share of cells on tile faces, and so
 // the global unions, small.
 #ifndef FLB_CC_TM3
 #define FLB_CC_TM3 8
@@ -372,33 +366,54 @@ __global__ __launch_bounds__(CCTile<L>::NT) void k_cc_local(MAP_KERNEL_PARAMS) {
   }
 }
 
+// One workgroup per tile of k_cc_local.  It visits the tile's cells that can
+// have a link leaving the tile (every cell of a row on an m or z tile face or
+// at the lattice's last row or plane, the two end cells of the other rows,
+// listed first so that no wavefront walks rows it does not need),
+// gathers the distinct pairs of tile-local parents across those links in an
+// LDS set, and unites each pair once after the set is complete.  A face
+// crossed by one component gives one pair, however many of its cells and
+// directions cross it.
+constexpr int CCX_HT = 1024;  // LDS set of parent pairs (8 KiB)
 template <class L>
 __global__ __launch_bounds__(MAP_NT) void k_cc_cross(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m)) return;
   using TT = CCTile<L>;
+  constexpr int NP = (L::Q - 1) / 2;  // one direction of each opposite pair
+  constexpr int RW = TT::TM * TT::TZ, CH = 4;  // rows of a tile; rows whose loads are in flight together
+  constexpr unsigned long long EMPTY = ~0ull;
+  __shared__ unsigned long long ht[CCX_HT];
   const MapDims d = m.d;
   int* par = m.par;
   FLB_AS_GLOBAL int* gpar = as_global(m.par);
+  const int ntx = (d.nx + 63) / 64, ntm = (d.nm + TT::TM - 1) / TT::TM;
+  const int b = (int)bid;
+  const int x0 = (b % ntx) * 64, m0 = ((b / ntx) % ntm) * TT::TM, z0 = (b / (ntx * ntm)) * TT::TZ;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nxs = (d.nx + 63) >> 6;
-  const unsigned nseg = (unsigned)nxs * (unsigned)d.nm * (unsigned)d.nz;
-  // wave-uniform loop over segments: every lane takes part in the merging
-  for (unsigned s = bid * MAP_WAVES + wv; s < nseg; s += nbk * MAP_WAVES) {
-    const unsigned row = s / (unsigned)nxs;
-    const int x = (int)(s - row * (unsigned)nxs) * 64 + lane;
-    const int mm_ = (int)(row % (unsigned)d.nm), z = (int)(row / (unsigned)d.nm);
-    const bool in = x < d.nx;
-    const unsigned c = (unsigned)min(x, d.nx - 1) + (unsigned)d.nx * row;
-    const int pc = in ? gpar[c] : -1;
-    if (!__ballot(pc >= 0)) continue;  // no gas in this segment
-    // the neighbours across tile edges, all loaded before any union
-    constexpr int NP = (L::Q - 1) / 2;
-    int py[NP];
+  for (int i = threadIdx.x; i < CCX_HT; i += MAP_NT) ht[i] = EMPTY;
+  __syncthreads();
+  const int xlast = min(x0 + 63, d.nx - 1);
+  // the pair (lo, hi) into the set; a crowded set unites at once
+  auto insert = [&](int p, int q) {
+    const int lo = min(p, q), hi = max(p, q);
+    const unsigned long long key = ((unsigned long long)(unsigned)lo << 32) | (unsigned)hi;
+    unsigned h = (unsigned)lo * 0x9E3779B1u ^ (unsigned)hi * 0x85EBCA77u;
+    h = (h ^ (h >> 16)) & (CCX_HT - 1);
+    for (int t = 0; t < 16; t++) {
+      const unsigned long long old = atomicCAS(&ht[h], EMPTY, key);
+      if (old == EMPTY || old == key) return;
+      h = (h + 1) & (CCX_HT - 1);
+    }
+    uf_unite(par, lo, hi);
+  };
+  // the remote parents of cell (x, mm_, z) with parent pc, in the chosen
+  // directions whose neighbour lies in another tile (-1 elsewhere)
+  auto remote = [&](int x, int mm_, int z, int pc, int (&py)[NP]) {
 #pragma unroll
     for (int p = 0; p < NP; p++) {
-      const int i = 2 * p + 1;  // one direction of each opposite pair
+      const int i = 2 * p + 1;
       const int xu = x + L::ex[i], mu = mm_ + L::em[i], zu = z + L::ez[i];
       const bool local = xu >= 0 && xu < d.nx && (xu >> 6) == (x >> 6) && mu >= 0 && mu < d.nm &&
                          mu / TT::TM == mm_ / TT::TM && zu >= 0 && zu < d.nz && zu / TT::TZ == z / TT::TZ;
@@ -409,9 +424,7 @@ __global__ __launch_bounds__(MAP_NT) void k_cc_cross(MAP_KERNEL_PARAMS) {
         py[p] = __atomic_load_n(&gpar[y], __ATOMIC_RELAXED);
       }
     }
-    // a cell's neighbours across a face mostly hang under one remote parent:
-    // each distinct (pc, py) pair of a lane is united once, in its first
-    // direction
+    // a lane's repeated remote parents count once
 #pragma unroll
     for (int p = 1; p < NP; p++) {
       bool seen = false;
@@ -419,13 +432,68 @@ __global__ __launch_bounds__(MAP_NT) void k_cc_cross(MAP_KERNEL_PARAMS) {
       for (int q = 0; q < p; q++) seen |= py[q] == py[p];
       if (seen) py[p] = -1;
     }
-    // one union per run of equal root pairs, the runs' unions concurrently
-#pragma unroll
-    for (int p = 0; p < NP; p++) {
-      const int ra = py[p] >= 0 ? pc : -1, rb = py[p];
-      const bool head = run_head(ra, rb);
-      if (ra >= 0 && ra != rb && head) uf_unite(par, ra, rb);
+  };
+  // the tile's rows: those on an m or z face (or the lattice's last row or
+  // plane), whose cells all may have links leaving the tile, and the others,
+  // where only the two end cells may
+  __shared__ unsigned short frow[RW], erow[RW];
+  __shared__ int nfr, ner;
+  if (threadIdx.x == 0) nfr = ner = 0;
+  __syncthreads();
+  for (int r = threadIdx.x; r < RW; r += MAP_NT) {
+    const int lm = r % TT::TM, lz = r / TT::TM, mm_ = m0 + lm, z = z0 + lz;
+    if (mm_ < d.nm && z < d.nz) {
+      const bool face = (L::HAS_M && (lm == 0 || lm == TT::TM - 1 || mm_ == d.nm - 1)) || lz == 0 ||
+                        lz == TT::TZ - 1 || z == d.nz - 1;
+      if (face) frow[atomicAdd(&nfr, 1)] = (unsigned short)r;
+      else erow[atomicAdd(&ner, 1)] = (unsigned short)r;
     }
+  }
+  __syncthreads();
+  const int nf = nfr, ne = ner;
+  // face rows, whole, CH at a time per wavefront (wave-uniform loop)
+  const int x = x0 + lane;
+  for (int k0 = wv * CH; k0 < nf; k0 += MAP_WAVES * CH) {
+    int pc[CH], ms[CH], zs[CH];
+#pragma unroll
+    for (int u = 0; u < CH; u++) {
+      const int r = frow[min(k0 + u, nf - 1)];
+      ms[u] = m0 + r % TT::TM;
+      zs[u] = z0 + r / TT::TM;
+      const bool act = k0 + u < nf && x < d.nx;
+      pc[u] = act ? gpar[(unsigned)x + (unsigned)d.nx * ((unsigned)ms[u] + (unsigned)d.nm * (unsigned)zs[u])] : -1;
+    }
+    int py[CH][NP];
+#pragma unroll
+    for (int u = 0; u < CH; u++) remote(x, ms[u], zs[u], pc[u], py[u]);
+#pragma unroll
+    for (int u = 0; u < CH; u++) {
+      if (!__ballot(pc[u] >= 0)) continue;
+      // the runs of equal pairs along x go into the set once
+#pragma unroll
+      for (int p = 0; p < NP; p++) {
+        const int ra = py[u][p] >= 0 ? pc[u] : -1, rb = py[u][p];
+        const bool head = run_head(ra, rb);
+        if (ra >= 0 && ra != rb && head) insert(ra, rb);
+      }
+    }
+  }
+  // the end cells of the other rows, one per thread
+  for (int k = threadIdx.x; k < 2 * ne; k += MAP_NT) {
+    const int r = erow[k >> 1];
+    const int xe = (k & 1) ? xlast : x0, mm_ = m0 + r % TT::TM, z = z0 + r / TT::TM;
+    const bool act = !((k & 1) && xlast == x0);
+    const int pc = act ? gpar[(unsigned)xe + (unsigned)d.nx * ((unsigned)mm_ + (unsigned)d.nm * (unsigned)z)] : -1;
+    int py[NP];
+    remote(xe, mm_, z, pc, py);
+#pragma unroll
+    for (int p = 0; p < NP; p++)
+      if (py[p] >= 0 && py[p] != pc) insert(pc, py[p]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < CCX_HT; i += MAP_NT) {
+    const unsigned long long k = ht[i];
+    if (k != EMPTY) uf_unite(par, (int)(k >> 32), (int)(unsigned)(k & 0xffffffffull));
   }
 }
 
@@ -1217,7 +1285,6 @@ __host__ inline int map_share(int shape, const MapDims& d) {
     // map kernel first looks up its lattice's arguments (dependent loads), so
     // many short workgroups spend their time starting
     case SH_CELLS: g = std::min<long long>((N + 1 + MAP_NT - 1) / MAP_NT, 4096); break;
-    case SH_SEG: g = std::min<long long>((nseg + MAP_WAVES - 1) / MAP_WAVES, 16384); break;
     case SH_CCT: g = cc_tiles(d, CCTile<L>::TM, CCTile<L>::TZ); break;
     case SH_MASKT: g = cc_tiles(d, MaskTile<L>::TM, MaskTile<L>::TZ); break;
     case SH_MASKZ: g = cc_tiles(d, MZ_TM, MZ_LZ); break;

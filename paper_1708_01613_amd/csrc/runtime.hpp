@@ -516,7 +516,7 @@ int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh, const F
   if (src == GAS_POP) MAPL((k_cc_local<L, S, GAS_POP>), SH_CCT, CNT);
   else if (src == GAS_AUTO) MAPL((k_cc_local<L, S, GAS_AUTO>), SH_CCT, CNT);
   else MAPL((k_cc_local<L, S, GAS_FIELD>), SH_CCT, CNT);
-  MAPL((k_cc_cross<L>), SH_SEG, MAP_NT);
+  MAPL((k_cc_cross<L>), SH_CCT, MAP_NT);
   MAPL(k_cc_compress, SH_RANK, RANK_BLOCK);
   MAPL(k_scan_counts, SH_ONE, 1024, 0);
   MAPL(k_write_rank, SH_RANK, RANK_BLOCK);
