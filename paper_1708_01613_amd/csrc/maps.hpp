@@ -527,35 +527,65 @@ static __global__ __launch_bounds__(RANK_BLOCK) void k_cc_compress(MAP_KERNEL_PA
 
 // one workgroup per lattice: exclusive scan of the per-block counts; the
 // total goes to *n_out (which 0: roots per rank block, the label count) or
-// to ctl->n_flagged (which 1: flagged cells per flag-word block)
+// to ctl->n_flagged (which 1: flagged cells per flag-word block).  A pass
+// loads 16 Ki counts at once (each thread four 16-byte groups, coalesced)
+// and scans them as four chunks of 4096 in order, a thread holding four
+// consecutive counts of each chunk (the 256^3 lattice in one pass).
 static __global__ __launch_bounds__(1024) void k_scan_counts(MAP_KERNEL_PARAMS, int which) {
   MAP_MEMBER
   if (!map_due(m)) return;
+  constexpr int CHK = 4096, NCH = 4;
   __shared__ int s_carry;
   __shared__ int s_w[16];
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
   const long long nwords = (long long)((m.d.nx + 63) >> 6) * m.d.nm * m.d.nz;
   const int nblocks = which == 0 ? m.nrb : (int)((nwords + FW_BLOCK - 1) / FW_BLOCK);
-  for (int base = 0; base < nblocks; base += 1024) {
-    const int i = base + threadIdx.x;
-    const int v = i < nblocks ? m.counts[i] : 0;
-    int incl = v;  // inclusive scan within the wave
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int* counts = m.counts;  // 256-byte aligned
+  for (int base = 0; base < nblocks; base += CHK * NCH) {
+    int4 v[NCH];
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int t = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += t;
+    for (int k = 0; k < NCH; k++) {
+      const int i = base + k * CHK + (int)threadIdx.x * 4;
+      if (i + 3 < nblocks) {
+        v[k] = *(const int4*)(counts + i);
+      } else {
+        v[k].x = i < nblocks ? counts[i] : 0;
+        v[k].y = i + 1 < nblocks ? counts[i + 1] : 0;
+        v[k].z = i + 2 < nblocks ? counts[i + 2] : 0;
+        v[k].w = 0;
+      }
     }
-    if (lane == 63) s_w[w] = incl;
-    __syncthreads();
-    int wbase = 0;
-    for (int k = 0; k < w; k++) wbase += s_w[k];
-    const int carry = s_carry;
-    if (i < nblocks) m.counts[i] = carry + wbase + incl - v;
-    __syncthreads();
-    if (threadIdx.x == 1023) s_carry = carry + wbase + incl;
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NCH; k++) {
+      if (base + k * CHK >= nblocks) break;  // uniform over the workgroup
+      const int i = base + k * CHK + (int)threadIdx.x * 4;
+      const int sum = v[k].x + v[k].y + v[k].z + v[k].w;
+      int incl = sum;  // inclusive scan of the thread sums within the wave
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+      }
+      if (lane == 63) s_w[w] = incl;
+      __syncthreads();
+      int wbase = 0;
+      for (int q = 0; q < w; q++) wbase += s_w[q];
+      const int carry = s_carry;
+      const int e0 = carry + wbase + incl - sum;
+      const int4 o = make_int4(e0, e0 + v[k].x, e0 + v[k].x + v[k].y, e0 + v[k].x + v[k].y + v[k].z);
+      if (i + 3 < nblocks) {
+        *(int4*)(counts + i) = o;
+      } else {
+        if (i < nblocks) counts[i] = o.x;
+        if (i + 1 < nblocks) counts[i + 1] = o.y;
+        if (i + 2 < nblocks) counts[i + 2] = o.z;
+      }
+      __syncthreads();
+      if (threadIdx.x == 1023) s_carry = carry + wbase + incl;
+      __syncthreads();
+    }
   }
   if (threadIdx.x == 0) {
     if (which == 0) *m.n_out = s_carry;
