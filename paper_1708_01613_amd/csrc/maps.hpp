@@ -327,25 +327,44 @@ __global__ __launch_bounds__(CCTile<L>::NT) void k_cc_local(MAP_KERNEL_PARAMS) {
     lp[l] = g ? (l & ~63) + (63 - __clzll((long long)upto)) : -1;
   }
   __syncthreads();
-  // links leaving the row: one union per run of equal (run, run) pairs, the
-  // runs' unions concurrently
+  // links leaving the row: the parents across all of a cell's links are read
+  // together, a lane's repeated parents count once, and one union is made per
+  // run of equal (run, run) pairs, the runs' unions concurrently.  Rows of a
+  // wavefront without gas are skipped.  (A parent read before this row's
+  // unions may since have been hooked; a union finds the roots anyway.)
+  constexpr int NQ = (L::Q - 1) / 2;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
+    if (!__ballot((gas >> k) & 1u)) continue;
     const int l = threadIdx.x + k * NT;
     const int lx = l & 63, lm = (l >> 6) % TT::TM, lz = (l >> 6) / TT::TM;
     const bool g = (gas >> k) & 1u;
+    int bn[NQ];
 #pragma unroll
-    for (int i = 1; i < L::Q; i += 2) {  // one direction of each opposite pair
-      if (L::em[i] == 0 && L::ez[i] == 0) continue;  // along x: inside the runs
+    for (int p = 0; p < NQ; p++) {
+      const int i = 2 * p + 1;  // one direction of each opposite pair
       const int nx_ = lx + L::ex[i], nm_ = lm + L::em[i], nz_ = lz + L::ez[i];
-      int a = -1, bn = -1;
+      bn[p] = -1;
+      if (L::em[i] == 0 && L::ez[i] == 0) continue;  // along x: inside the runs
       if (g && nx_ >= 0 && nx_ < 64 && nm_ >= 0 && nm_ < TT::TM && nz_ >= 0 && nz_ < TT::TZ &&
-          x0 + nx_ < d.nx && m0 + nm_ < d.nm && z0 + nz_ < d.nz) {
-        bn = lp[nx_ + 64 * (nm_ + TT::TM * nz_)];
-        if (bn >= 0) a = lp[l];
-      }
-      const bool head = run_head(a, bn);
-      if (a >= 0 && head) lds_unite(lp, a, bn);
+          x0 + nx_ < d.nx && m0 + nm_ < d.nm && z0 + nz_ < d.nz)
+        bn[p] = lp[nx_ + 64 * (nm_ + TT::TM * nz_)];
+    }
+    const int a = g ? lp[l] : -1;
+#pragma unroll
+    for (int p = 1; p < NQ; p++) {
+      bool seen = false;
+#pragma unroll
+      for (int q = 0; q < p; q++) seen |= bn[q] == bn[p];
+      if (seen) bn[p] = -1;
+    }
+#pragma unroll
+    for (int p = 0; p < NQ; p++) {
+      const int i = 2 * p + 1;
+      if (L::em[i] == 0 && L::ez[i] == 0) continue;
+      const int aa = bn[p] >= 0 ? a : -1;
+      const bool head = run_head(aa, bn[p]);
+      if (aa >= 0 && head) lds_unite(lp, aa, bn[p]);
     }
   }
   __syncthreads();
