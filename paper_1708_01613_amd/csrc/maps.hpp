@@ -919,16 +919,10 @@ static __global__ __launch_bounds__(MAP_NT) void k_alias_reset(MAP_KERNEL_PARAMS
   }
 }
 
-// One pass over the cells that are gas in both maps: the first new label seen
-// over an old alias class becomes the class's representative (a CAS on its
-// rep entry), and every other new label seen over that class is united with
-// it.  All new labels over one old class so end in one set, as when each is
-// united with the class's smallest; the compressed aliases do not depend on
-// which label came first.  The pass runs over whole wavefronts (the loop
-// bound is uniform per wavefront) and merges the many lanes that carry the
-// same (old class, new label) pair before touching global memory; the rep
-// entry is read before any CAS, since the entries of large bubbles are hot.
-static __global__ __launch_bounds__(MAP_NT) void k_alias_carry(MAP_KERNEL_PARAMS) {
+// Both carry passes run over whole wavefronts (the loop bound is uniform per
+// wavefront) and merge the many lanes that carry the same (old class, new
+// label) pair before touching global memory.
+static __global__ __launch_bounds__(MAP_NT) void k_alias_carry1(MAP_KERNEL_PARAMS) {
   MAP_MEMBER
   if (!map_due(m) || !m.ctl->maps_seen) return;
   const int lane = threadIdx.x & 63;
@@ -942,14 +936,26 @@ static __global__ __launch_bounds__(MAP_NT) void k_alias_carry(MAP_KERNEL_PARAMS
     }
     const bool pend = b > 0 && a > 0;
     const int r = pend ? uf_root(m.alias_old, a) : 0;
-    if (run_head(r, b) && pend) {
-      int q = __atomic_load_n(&m.rep[r], __ATOMIC_RELAXED);
-      if (q == 0x7fffffff) {
-        const int old = atomicCAS(&m.rep[r], 0x7fffffff, b);
-        q = old == 0x7fffffff ? b : old;
-      }
-      if (q != b) uf_unite(m.alias, b, q);
+    // one atomic per run of equal (root, label), the runs' atomics at once
+    if (run_head(r, b) && pend && __atomic_load_n(&m.rep[r], __ATOMIC_RELAXED) > b) atomicMin(&m.rep[r], b);
+  }
+}
+
+static __global__ __launch_bounds__(MAP_NT) void k_alias_carry2(MAP_KERNEL_PARAMS) {
+  MAP_MEMBER
+  if (!map_due(m) || !m.ctl->maps_seen) return;
+  const int lane = threadIdx.x & 63;
+  const long long stride = (long long)nbk * MAP_NT;
+  for (long long base = bid * (long long)MAP_NT + (threadIdx.x & ~63); base < m.d.N; base += stride) {
+    const long long c = base + lane;
+    int b = 0, a = 0;
+    if (c < m.d.N) {
+      b = m.label[c];
+      a = m.label_old[c];
     }
+    const int r = (b > 0 && a > 0) ? m.rep[uf_root(m.alias_old, a)] : 0;
+    const bool pend = b > 0 && a > 0 && r != b;
+    if (run_head(b, r) && pend) uf_unite(m.alias, b, r);
   }
 }
 

@@ -531,7 +531,8 @@ int map_pipeline(const MapSet& s, hipStream_t st, int src, bool refresh, const F
       hipStream_t st_main = st;
       hipStream_t st = fork ? fk->side : st_main;  // the alias carry, beside the BFS
       MAPL(k_alias_reset, SH_FEW, MAP_NT);
-      MAPL(k_alias_carry, SH_CELLS, MAP_NT);
+      MAPL(k_alias_carry1, SH_CELLS, MAP_NT);
+      MAPL(k_alias_carry2, SH_CELLS, MAP_NT);
       MAPL(k_alias_compress, SH_FEW, MAP_NT);
       if (fork) HIPCHK(hipEventRecord(fk->b, st));
     }
